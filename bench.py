@@ -1,0 +1,250 @@
+"""Benchmark of the Rosenbluth chain-growth hot path on one MI355X.
+
+A step is one pass of the whole path over one ensemble: grow every chain
+(draw, test, count, pick, weight, observables) and reduce the ensemble
+(weighted averages, c_n estimate, R^2 histogram).  The headline workload is
+the simple cubic lattice at N = 64 monomers, 10^7 chains, int16 coordinates,
+FP64 log-weights and a 256-bin histogram; the hard-sphere N = 64, k = 8,
+10^6-chain workload is reported beside it under "secondary".
+
+Prints one JSON line.  value = monomer-steps/s = M (N - 1) K / T with the
+inputs (seed, configuration) resident before the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+REPO = os.path.dirname(os.path.abspath(__file__))
+if REPO not in sys.path:
+    sys.path.insert(0, REPO)
+
+# Published MI355X peaks and the VALU figure derived from the unit counts:
+# 256 CUs x 4 SIMD16 x 16 lanes x 2.4 GHz = 3.93e13 lane-operations/s (one
+# full-rate 32-bit integer or binary64 add/mul per lane per clock).
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0
+
+
+def lattice_alg_ops_per_chain(N: int) -> int:
+    """Algorithmic VALU lane-operations to grow one lattice chain of N monomers.
+
+    Per step i: the pair tests against the monomers that can neighbour the
+    tip (floor(i/2) of them on the bipartite cubic lattice), 4 operations
+    each (L1 distance, neighbour flag, direction code, mask insert); a
+    quarter of one Philox4x32-10 block (10 rounds x 6 operations / 4); and
+    10 operations to count, pick and apply the move and add log m_i.
+    """
+    return sum(4 * (i // 2) + 15 + 10 for i in range(1, N))
+
+
+def real_alg_ops_per_chain(N: int, k: int) -> float:
+    """Algorithmic VALU lane-operations to grow one hard-sphere chain.
+
+    Per step i: k candidates, each tested against beads 0..i-2 at 9
+    binary64 operations (3 sub, 3 mul, 2 add, 1 compare); k Marsaglia
+    directions at 4/pi Philox blocks each (60 operations per block) plus
+    ~20 operations for the disc test, square root and candidate; and
+    10 operations to count, pick and add log m_i.
+    """
+    tot = 0.0
+    for i in range(1, N):
+        tot += k * 9 * max(i - 1, 0) + k * (60 * 4 / math.pi + 20) + 10
+    return tot
+
+
+def _percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    pos = (len(xs) - 1) * q
+    lo = int(math.floor(pos))
+    hi = min(lo + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (pos - lo)
+
+
+def run_gpu(w, steps, warmup, torch, rs, profile_kernel=True):
+    dev = torch.device("cuda", 0)
+    M, N = w["n_chains"], w["N"]
+    cfg = rs.make_config(w["geometry"], N, w["k"], M, w["seed"], coord=w["coord"],
+                         bond_length=w.get("bond_length", 1.0),
+                         bead_diameter=w.get("bead_diameter", 1.0),
+                         hist_bins=w["hist_bins"], exact_w=w.get("exact_w", False))
+    ctype = {rs.RSAW_I16: torch.int16, rs.RSAW_I32: torch.int32, rs.RSAW_F64: torch.float64}[cfg.coord_type]
+    bufs = dict(log_w=torch.empty(M, dtype=torch.float64, device=dev),
+                r_end=torch.empty((3, M), dtype=ctype, device=dev),
+                r2=torch.empty(M, dtype=torch.float64, device=dev),
+                rg2=torch.empty(M, dtype=torch.float64, device=dev),
+                n_grown=torch.empty(M, dtype=torch.int16, device=dev))
+    o = rs.rsaw_chain_out()
+    o.log_w, o.r_end, o.r2, o.rg2, o.n_grown = (bufs[k].data_ptr() for k in
+                                                  ("log_w", "r_end", "r2", "rg2", "n_grown"))
+    if w["geometry"] == "lattice":
+        bufs["n2rg2"] = torch.empty(M, dtype=torch.int64, device=dev)
+        o.n2rg2 = bufs["n2rg2"].data_ptr()
+    summ = torch.empty(rs.SUMMARY_BYTES, dtype=torch.uint8, device=dev)
+    hw = torch.empty(max(w["hist_bins"], 1), dtype=torch.float64, device=dev)
+    hn = torch.empty(max(w["hist_bins"], 1), dtype=torch.uint64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    sh = stream.cuda_stream
+
+    def step():
+        rs.gen_chains_raw(cfg, o, summ.data_ptr(), hw.data_ptr() if w["hist_bins"] else 0,
+                          hn.data_ptr() if w["hist_bins"] else 0, sh)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        step()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = [a.elapsed_time(b) for a, b in ev]
+    summary = rs.parse_summary(summ)
+    if summary["status"] != 0:
+        raise RuntimeError(f"device status {summary['status']}")
+
+    grow_ms = None
+    if profile_kernel:
+        # The growth kernel alone (plus a one-thread init kernel), bracketed by
+        # events on the stream it is launched on.
+        ge = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        for a, b in ge:
+            a.record(stream)
+            rs.gen_chains_raw(cfg, o, 0, 0, 0, sh)
+            b.record(stream)
+        torch.cuda.synchronize()
+        grow_ms = sum(a.elapsed_time(b) for a, b in ge) / len(ge)
+    return dict(wall=wall, lat=lat, summary=summary, grow_ms=grow_ms)
+
+
+def cpu_baseline(w, sample_chains, threads):
+    """The oracle, untuned, on the host cores: a bounded sample of the same
+    workload (its first `sample_chains` chains), split over threads."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
+    import oracle
+
+    oracle.build()
+    n = sample_chains
+    parts = [(i * n // threads, (i + 1) * n // threads) for i in range(threads)]
+
+    def work(rng):
+        lo, hi = rng
+        if w["geometry"] == "lattice":
+            return oracle.gen_lattice(w["seed"], w["N"], hi - lo, chain_offset=lo)
+        return oracle.gen_real(w["seed"], w["N"], w["k"], hi - lo, b=w.get("bond_length", 1.0),
+                               sigma=w.get("bead_diameter", 1.0), chain_offset=lo)
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        res = list(ex.map(work, parts))
+    cat = {k: np.concatenate([r[k] for r in res]) for k in ("log_w", "r2", "rg2", "n_grown")}
+    oracle.reduce(w["N"], cat["log_w"], cat["r2"], cat["rg2"], cat["n_grown"], bins=w["hist_bins"])
+    dt = time.perf_counter() - t0
+    return dict(value=n * (w["N"] - 1) / dt, unit="monomer-steps/s", cores=threads,
+                kind="oracle",
+                sample=f"first {n} chains of the workload (seed {w['seed']}), growth + reduction, "
+                       f"{threads} threads, {dt:.2f} s wall")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="lattice_n64")
+    ap.add_argument("--secondary", default="real_n64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}); the chain ranges would shard by chain_offset "
+              f"with no data exchange beyond the ensemble partials.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1704_04381_amd as rs
+    from paper_1704_04381_amd.workloads import WORKLOADS
+
+    if not torch.cuda.is_available():
+        print("bench.py needs an MI355X GPU", file=sys.stderr)
+        sys.exit(2)
+    rs.load()
+    w = WORKLOADS[args.workload]
+    M, N = w["n_chains"], w["N"]
+    r = run_gpu(w, args.steps, args.warmup, torch, rs)
+    T = sum(r["lat"]) / 1e3
+    value = M * (N - 1) * args.steps / T
+    if w["geometry"] == "lattice":
+        alg_ops = lattice_alg_ops_per_chain(N) * M
+    else:
+        alg_ops = real_alg_ops_per_chain(N, w["k"]) * M
+    achieved = alg_ops / (r["grow_ms"] / 1e3) / 1e12
+    line = {
+        "metric": "monomer-steps/s at N=64 lattice + hard-sphere; p50/p99 ensemble latency",
+        "value": value,
+        "unit": "monomer-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": T * 1e3 / args.steps,
+        "p50_ms": _percentile(r["lat"], 0.5),
+        "p99_ms": _percentile(r["lat"], 0.99),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32+f64" if w["geometry"] == "lattice" else "f64",
+        "data": "synthetic (counter-based Philox draws inside the method)",
+        "config": {"workload": args.workload, "geometry": w["geometry"], "N": N, "k": w["k"],
+                   "n_chains": M, "seed": w["seed"], "coord": w["coord"],
+                   "hist_bins": w["hist_bins"]},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
+                     "unit": "Tops/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                     "kernel": "grow_lattice_reg" if w["geometry"] == "lattice" else "grow_real_tp",
+                     "kernel_ms": r["grow_ms"], "alg_ops_per_launch": alg_ops},
+        "physics": {k: r["summary"][k] for k in ("n_alive", "log_c_est", "r2_mean", "r2_err",
+                                                 "rg2_mean", "rg2_err", "ess")},
+    }
+    if args.secondary:
+        w2 = WORKLOADS[args.secondary]
+        steps2 = max(3, args.steps // 4)
+        r2 = run_gpu(w2, steps2, 1, torch, rs)
+        T2 = sum(r2["lat"]) / 1e3
+        ops2 = (lattice_alg_ops_per_chain(w2["N"]) if w2["geometry"] == "lattice"
+                else real_alg_ops_per_chain(w2["N"], w2["k"])) * w2["n_chains"]
+        ach2 = ops2 / (r2["grow_ms"] / 1e3) / 1e12
+        line["secondary"] = {
+            "workload": args.secondary, "value": w2["n_chains"] * (w2["N"] - 1) * steps2 / T2,
+            "unit": "monomer-steps/s", "steps": steps2, "ms_per_step": T2 * 1e3 / steps2,
+            "p50_ms": _percentile(r2["lat"], 0.5), "p99_ms": _percentile(r2["lat"], 0.99),
+            "roofline": {"bound": "alu", "achieved": ach2, "peak": VALU_PEAK_TOPS,
+                         "unit": "Tops/s", "frac": ach2 / VALU_PEAK_TOPS,
+                         "kernel_ms": r2["grow_ms"]},
+            "physics": {k: r2["summary"][k] for k in ("n_alive", "log_c_est", "r2_mean",
+                                                      "r2_err", "rg2_mean", "rg2_err")},
+        }
+    if not args.no_cpu_baseline:
+        threads = min(16, os.cpu_count() or 1)
+        sample = args.cpu_sample or (320_000 if w["geometry"] == "lattice" else 40_000)
+        line["cpu_baseline"] = cpu_baseline(w, sample, threads)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,186 @@
+/*
+ * rsaw.h — C ABI of librsaw.so: Rosenbluth chain growth on AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The library grows many independent chains at once, each one monomer per
+ * step (Guo & Baulin, Comput. Phys. Commun. 2017):
+ *   - on the simple cubic lattice (Sec. 3.3.2, Algorithm 1): the 6
+ *     neighbours of the tip are the candidates;
+ *   - in continuous space as hard spheres (Sec. 3.3.3, Algorithm 2): k random
+ *     directions at bond length b are the candidates, and a candidate closer
+ *     than sigma to an earlier, non-bonded bead is blocked.
+ * At step i the chain counts the free candidates m_i, picks one uniformly and
+ * multiplies its Rosenbluth weight W by m_i (Eq. 3).  A dead end (m_i = 0)
+ * leaves the chain at weight zero.  The ensemble is then reduced to weighted
+ * averages (Eq. 2) and to the mean weight, the estimate of the number of
+ * self-avoiding walks (Eq. 6).
+ *
+ * Random numbers come from Philox4x32-10 keyed by the seed, with counter
+ * (chain, step, slot, attempt); chain index g = chain_offset + c, so results
+ * do not depend on how a range of chains is split across calls or devices.
+ *
+ * Conventions for every entry point:
+ *   - Pointers named d_* / device arrays are device memory owned by the
+ *     caller; the library never frees them.  Host structs are read or written
+ *     before the call returns.
+ *   - All work is enqueued on `stream` (a hipStream_t; NULL = default stream)
+ *     in stream order; entry points return once the work is enqueued, except
+ *     where stated.
+ *   - Errors are returned as rsaw_status; no exception crosses the ABI.  A
+ *     human-readable message for the last failure on the calling thread is
+ *     available from rsaw_last_error().
+ *   - Thread safety: calls on different streams may run concurrently; the
+ *     library keeps one internal workspace per (device, stream), so calls
+ *     on the same stream are ordered by that stream.
+ */
+#ifndef RSAW_H
+#define RSAW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RSAW_OK = 0,
+    RSAW_E_INVALID = 1,     /* bad argument (see rsaw_last_error)                 */
+    RSAW_E_UNSUPPORTED = 2, /* valid request this build has no kernel for         */
+    RSAW_E_OVERFLOW = 3,    /* exact 64-bit weight requested for N > 28           */
+    RSAW_E_NOMEM = 4,       /* device allocation of the workspace failed          */
+    RSAW_E_DEVICE = 5,      /* a HIP runtime call failed                          */
+    RSAW_E_RNG = 6          /* a rejection loop reached its 65536-attempt cap     */
+} rsaw_status;
+
+/* geometry */
+#define RSAW_LATTICE_SC 0 /* simple cubic lattice, k = 6 (Sec. 3.3.2)          */
+#define RSAW_REAL_HS 1    /* hard spheres in continuous space (Sec. 3.3.3)    */
+
+/* element type of the r_end output planes */
+#define RSAW_I16 0 /* lattice only */
+#define RSAW_I32 1 /* lattice only */
+#define RSAW_F64 2 /* real space only */
+
+/* flags */
+#define RSAW_EXACT_W 1u /* lattice: also keep W exactly as uint64 (needs N <= 28) */
+
+typedef struct {
+    int32_t geometry;      /* RSAW_LATTICE_SC or RSAW_REAL_HS                        */
+    int32_t n_monomers;    /* N >= 1 monomers per chain (N - 1 growth steps)         */
+    int32_t k_trials;      /* candidates per step: 6 on the lattice, 1..64 real space */
+    int32_t coord_type;    /* RSAW_I16 / RSAW_I32 (lattice) or RSAW_F64 (real space)  */
+    uint64_t n_chains;     /* M >= 0 chains                                          */
+    uint64_t seed;         /* Philox key                                             */
+    uint64_t chain_offset; /* global index of the first chain (sharding / resume)    */
+    double bond_length;    /* b > 0 (real space; the lattice constant is 1)          */
+    double bead_diameter;  /* sigma >= 0 (real space; 0 = ideal chain)               */
+    int32_t hist_bins;     /* B >= 0 bins of the R^2 histogram over [0, (N-1)^2]     */
+    uint32_t flags;        /* RSAW_EXACT_W                                           */
+} rsaw_config;
+
+/*
+ * Per-chain outputs, structure of arrays, n_chains entries each, device
+ * memory.  Any pointer may be NULL ("do not write").  Chain c of the call is
+ * element c.  A dead chain has log_w = -INFINITY, w_exact = 0, n_grown =
+ * monomers placed, and the observables of its placed prefix.
+ */
+typedef struct {
+    double *log_w;     /* sum_i log m_i, in step order (Eq. 3)                        */
+    uint64_t *w_exact; /* lattice with RSAW_EXACT_W: prod_i m_i                       */
+    void *r_end;       /* 3 planes (x, y, z) of n_chains, coord_type; r_0 = origin    */
+    double *r2;        /* squared end-to-end distance                                */
+    double *rg2;       /* squared radius of gyration (1/g) sum |r_i - r_cm|^2         */
+    int64_t *n2rg2;    /* lattice: g^2 Rg^2 = g sum |r|^2 - |sum r|^2, exact          */
+    uint16_t *n_grown; /* monomers placed, g (N for a complete chain)                 */
+} rsaw_chain_out;
+
+/*
+ * Ensemble summary (Eq. 2 and Eq. 6), written to device memory by
+ * rsaw_gen_chains.  w = exp(log W - log_w_max) for live chains.
+ */
+typedef struct {
+    uint64_t n_chains;     /* M, dead chains included                                */
+    uint64_t n_alive;      /* chains that reached N monomers                         */
+    double log_w_max;      /* L = max log W over live chains (-inf if none)          */
+    double sum_w;          /* S0 = sum w                                             */
+    double sum_w2;         /* S2 = sum w^2                                           */
+    double sum_w_r2;       /* sum w R^2                                              */
+    double sum_w2_r2;      /* sum w^2 R^2                                            */
+    double sum_w2_r2sq;    /* sum w^2 R^4                                            */
+    double sum_w_rg2;      /* sum w Rg^2                                             */
+    double sum_w2_rg2;     /* sum w^2 Rg^2                                           */
+    double sum_w2_rg2sq;   /* sum w^2 Rg^4                                           */
+    double log_c_est;      /* L + log(S0 / M): log of the mean weight (Eq. 6)        */
+    double c_rel_err;      /* sqrt((M S2 / S0^2 - 1) / (M - 1))                      */
+    double r2_mean;        /* <R^2> = sum w R^2 / S0 (Eq. 2)                          */
+    double r2_err;         /* sqrt(sum w^2 (R^2 - <R^2>)^2) / S0                      */
+    double rg2_mean;       /* <Rg^2>                                                 */
+    double rg2_err;        /* its standard error                                     */
+    double ess;            /* S0^2 / S2                                              */
+    double steps;          /* growth steps executed, sum (n_grown - 1)               */
+    uint64_t sum_w_exact[2];       /* lattice + RSAW_EXACT_W: sum W, 128 bit (lo, hi) */
+    uint64_t sum_w_r2_exact[2];    /* sum W R^2                                       */
+    uint64_t sum_w_n2rg2_exact[2]; /* sum W g^2 Rg^2                                  */
+    int32_t exact_valid;           /* 1 when the three exact sums are filled          */
+    int32_t status;                /* device-side status (RSAW_OK or RSAW_E_RNG)      */
+} rsaw_summary;
+
+/*
+ * rsaw_gen_chains — grow cfg->n_chains chains and reduce them.
+ *
+ *   cfg        host pointer; validated before anything is enqueued.
+ *   out        host pointer to per-chain device arrays (may be NULL; NULL
+ *              members are not written).  The reduction reads log_w, r2,
+ *              rg2 and n_grown: when the caller does not supply them the
+ *              library uses its own device workspace.
+ *   d_summary  device pointer to one rsaw_summary, or NULL to skip the
+ *              reduction entirely (growth only).
+ *   d_hist_w   device array of cfg->hist_bins doubles (W-weighted histogram
+ *              of R^2, w as in the summary), or NULL.
+ *   d_hist_n   device array of cfg->hist_bins uint64 (live-chain counts), or
+ *              NULL.  Bin of a chain: floor((R^2 B) / ((N-1)^2 + 1)).
+ *   stream     hipStream_t or NULL.
+ *
+ * Asynchronous: returns after enqueueing.  The results are deterministic:
+ * the same config gives bit-identical outputs run to run.
+ * Errors: RSAW_E_INVALID for N < 1, N > 65535, unknown geometry or
+ * coord_type, lattice k != 6, real-space k outside 1..64, b <= 0,
+ * sigma < 0, hist_bins < 0, n_chains >= 2^32 (split larger ensembles
+ * over calls with chain_offset);
+ * RSAW_E_UNSUPPORTED for lattice N > 64 or real-space N > 256 (no kernel in
+ * this build); RSAW_E_OVERFLOW for RSAW_EXACT_W with N > 28;
+ * RSAW_E_NOMEM / RSAW_E_DEVICE for runtime failures.  A Marsaglia or Lemire
+ * rejection loop that reaches its cap (probability below 2^-100000) sets
+ * d_summary->status = RSAW_E_RNG.
+ */
+rsaw_status rsaw_gen_chains(const rsaw_config *cfg, const rsaw_chain_out *out,
+                            rsaw_summary *d_summary, double *d_hist_w,
+                            uint64_t *d_hist_n, void *stream);
+
+/*
+ * rsaw_gen_chains_sync — rsaw_gen_chains followed by a copy of the summary
+ * to host memory `h_summary` (required) and a synchronisation of `stream`.
+ */
+rsaw_status rsaw_gen_chains_sync(const rsaw_config *cfg, const rsaw_chain_out *out,
+                                 rsaw_summary *h_summary, double *d_hist_w,
+                                 uint64_t *d_hist_n, void *stream);
+
+/* Static description of a status code. */
+const char *rsaw_status_string(rsaw_status s);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *rsaw_last_error(void);
+
+/* Library version as an integer: major * 10000 + minor * 100 + patch. */
+int32_t rsaw_version(void);
+
+/* Release the internal device workspace of every device (safe to call
+ * repeatedly; later calls re-create it on demand). */
+void rsaw_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSAW_H */

@@ -1,0 +1,204 @@
+"""Python binding of librsaw: Rosenbluth chain growth on MI355X.
+
+Argument marshalling only.  Every step of the method runs in the HIP kernels
+of ``librsaw.so`` behind the C ABI in ``include/rsaw.h``; PyTorch provides
+device memory and the stream.  There is no CPU fallback: without the built
+library (``python -m paper_1704_04381_amd.build``) or without a GPU, the calls
+raise.
+
+    out, summary = gen_chains("lattice", N=64, k=6, n_chains=10**7, seed=1,
+                              coord="i16", hist_bins=256)
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "librsaw.so")
+
+RSAW_LATTICE_SC = 0
+RSAW_REAL_HS = 1
+RSAW_I16, RSAW_I32, RSAW_F64 = 0, 1, 2
+RSAW_EXACT_W = 1
+
+STATUS = {0: "RSAW_OK", 1: "RSAW_E_INVALID", 2: "RSAW_E_UNSUPPORTED", 3: "RSAW_E_OVERFLOW",
+          4: "RSAW_E_NOMEM", 5: "RSAW_E_DEVICE", 6: "RSAW_E_RNG"}
+
+
+class rsaw_config(C.Structure):
+    _fields_ = [("geometry", C.c_int32), ("n_monomers", C.c_int32), ("k_trials", C.c_int32),
+                ("coord_type", C.c_int32), ("n_chains", C.c_uint64), ("seed", C.c_uint64),
+                ("chain_offset", C.c_uint64), ("bond_length", C.c_double),
+                ("bead_diameter", C.c_double), ("hist_bins", C.c_int32), ("flags", C.c_uint32)]
+
+
+class rsaw_chain_out(C.Structure):
+    _fields_ = [("log_w", C.c_void_p), ("w_exact", C.c_void_p), ("r_end", C.c_void_p),
+                ("r2", C.c_void_p), ("rg2", C.c_void_p), ("n2rg2", C.c_void_p),
+                ("n_grown", C.c_void_p)]
+
+
+class rsaw_summary(C.Structure):
+    _fields_ = [("n_chains", C.c_uint64), ("n_alive", C.c_uint64), ("log_w_max", C.c_double),
+                ("sum_w", C.c_double), ("sum_w2", C.c_double), ("sum_w_r2", C.c_double),
+                ("sum_w2_r2", C.c_double), ("sum_w2_r2sq", C.c_double), ("sum_w_rg2", C.c_double),
+                ("sum_w2_rg2", C.c_double), ("sum_w2_rg2sq", C.c_double),
+                ("log_c_est", C.c_double), ("c_rel_err", C.c_double), ("r2_mean", C.c_double),
+                ("r2_err", C.c_double), ("rg2_mean", C.c_double), ("rg2_err", C.c_double),
+                ("ess", C.c_double), ("steps", C.c_double),
+                ("sum_w_exact", C.c_uint64 * 2), ("sum_w_r2_exact", C.c_uint64 * 2),
+                ("sum_w_n2rg2_exact", C.c_uint64 * 2), ("exact_valid", C.c_int32),
+                ("status", C.c_int32)]
+
+
+SUMMARY_BYTES = C.sizeof(rsaw_summary)
+
+# Every symbol include/rsaw.h declares.
+EXPORTS = ["rsaw_gen_chains", "rsaw_gen_chains_sync", "rsaw_status_string",
+           "rsaw_last_error", "rsaw_version", "rsaw_shutdown"]
+
+_lib = None
+_lock = threading.Lock()
+
+
+class RsawError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def load(path: str = LIB_PATH):
+    """Load librsaw.so and declare the C ABI; raises if it was not built."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            raise RsawError(5, f"{path} is missing: build it with "
+                               "`python -m paper_1704_04381_amd.build`")
+        lib = C.CDLL(path)
+        vp = C.c_void_p
+        lib.rsaw_gen_chains.argtypes = [C.POINTER(rsaw_config), C.POINTER(rsaw_chain_out),
+                                        vp, vp, vp, vp]
+        lib.rsaw_gen_chains.restype = C.c_int
+        lib.rsaw_gen_chains_sync.argtypes = [C.POINTER(rsaw_config), C.POINTER(rsaw_chain_out),
+                                             C.POINTER(rsaw_summary), vp, vp, vp]
+        lib.rsaw_gen_chains_sync.restype = C.c_int
+        lib.rsaw_status_string.argtypes = [C.c_int]
+        lib.rsaw_status_string.restype = C.c_char_p
+        lib.rsaw_last_error.argtypes = []
+        lib.rsaw_last_error.restype = C.c_char_p
+        lib.rsaw_version.argtypes = []
+        lib.rsaw_version.restype = C.c_int32
+        lib.rsaw_shutdown.argtypes = []
+        lib.rsaw_shutdown.restype = None
+        _lib = lib
+        return lib
+
+
+def _check(status):
+    if status != 0:
+        raise RsawError(status, load().rsaw_last_error().decode())
+
+
+def make_config(geometry, N, k, n_chains, seed, *, coord=None, chain_offset=0,
+                bond_length=1.0, bead_diameter=1.0, hist_bins=0, exact_w=False):
+    geo = {"lattice": RSAW_LATTICE_SC, "real": RSAW_REAL_HS}[geometry] \
+        if isinstance(geometry, str) else int(geometry)
+    if coord is None:
+        coord = "f64" if geo == RSAW_REAL_HS else "i32"
+    ct = {"i16": RSAW_I16, "i32": RSAW_I32, "f64": RSAW_F64}[coord]
+    return rsaw_config(geo, int(N), int(k), ct, int(n_chains), int(seed), int(chain_offset),
+                       float(bond_length), float(bead_diameter), int(hist_bins),
+                       RSAW_EXACT_W if exact_w else 0)
+
+
+def summary_to_dict(s: rsaw_summary) -> dict:
+    d = {}
+    for name, _ in rsaw_summary._fields_:
+        v = getattr(s, name)
+        if name.endswith("_exact"):
+            v = int(v[0]) | (int(v[1]) << 64)
+        d[name] = v
+    return d
+
+
+def parse_summary(buf) -> dict:
+    """Summary dict from a device or host uint8 tensor of SUMMARY_BYTES."""
+    raw = bytes(buf.cpu().numpy().tobytes())
+    return summary_to_dict(rsaw_summary.from_buffer_copy(raw))
+
+
+def gen_chains_raw(cfg: rsaw_config, out: rsaw_chain_out | None, d_summary: int,
+                   d_hist_w: int, d_hist_n: int, stream: int):
+    """Direct call of rsaw_gen_chains with raw device addresses (0 = NULL)."""
+    lib = load()
+    _check(lib.rsaw_gen_chains(C.byref(cfg), C.byref(out) if out is not None else None,
+                               d_summary or None, d_hist_w or None, d_hist_n or None,
+                               stream or None))
+
+
+def gen_chains(geometry, N, k, n_chains, seed, *, coord=None, chain_offset=0,
+               bond_length=1.0, bead_diameter=1.0, hist_bins=0, exact_w=False,
+               per_chain=True, device=None, stream=None, sync=True):
+    """Grow ``n_chains`` chains on the GPU and reduce them.
+
+    Returns ``(out, summary)``: ``out`` is a dict of device tensors (log_w,
+    r_end [3, M], r2, rg2, n_grown, and n2rg2 / w_exact on the lattice), empty
+    when ``per_chain`` is false; ``summary`` is a dict (host) when ``sync`` is
+    true, else the raw device uint8 tensor (parse with ``parse_summary``).
+    """
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RsawError(5, "no GPU: librsaw runs on MI355X only (no CPU fallback)")
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    cfg = make_config(geometry, N, k, n_chains, seed, coord=coord, chain_offset=chain_offset,
+                      bond_length=bond_length, bead_diameter=bead_diameter,
+                      hist_bins=hist_bins, exact_w=exact_w)
+    M = int(n_chains)
+    lattice = cfg.geometry == RSAW_LATTICE_SC
+    out = {}
+    o = rsaw_chain_out()
+    if per_chain:
+        ctype = {RSAW_I16: torch.int16, RSAW_I32: torch.int32, RSAW_F64: torch.float64}[cfg.coord_type]
+        out["log_w"] = torch.empty(M, dtype=torch.float64, device=dev)
+        out["r_end"] = torch.empty((3, M), dtype=ctype, device=dev)
+        out["r2"] = torch.empty(M, dtype=torch.float64, device=dev)
+        out["rg2"] = torch.empty(M, dtype=torch.float64, device=dev)
+        out["n_grown"] = torch.empty(M, dtype=torch.int16, device=dev)  # uint16 bits
+        o.log_w, o.r_end, o.r2, o.rg2, o.n_grown = (out[n].data_ptr() for n in
+                                                      ("log_w", "r_end", "r2", "rg2", "n_grown"))
+        if lattice:
+            out["n2rg2"] = torch.empty(M, dtype=torch.int64, device=dev)
+            o.n2rg2 = out["n2rg2"].data_ptr()
+            if exact_w:
+                out["w_exact"] = torch.empty(M, dtype=torch.uint64, device=dev)
+                o.w_exact = out["w_exact"].data_ptr()
+    summ = torch.empty(SUMMARY_BYTES, dtype=torch.uint8, device=dev)
+    hw = torch.empty(max(hist_bins, 0), dtype=torch.float64, device=dev) if hist_bins else None
+    hn = torch.empty(max(hist_bins, 0), dtype=torch.uint64, device=dev) if hist_bins else None
+    if stream is None:
+        stream = torch.cuda.current_stream(dev).cuda_stream
+    with torch.cuda.device(dev):
+        gen_chains_raw(cfg, o, summ.data_ptr(), hw.data_ptr() if hw is not None else 0,
+                       hn.data_ptr() if hn is not None else 0, stream)
+    if hist_bins:
+        out["hist_w"] = hw
+        out["hist_n"] = hn
+    if not sync:
+        return out, summ
+    s = parse_summary(summ)
+    if s["status"] != 0:
+        raise RsawError(s["status"], "device reported a rejection-cap hit")
+    return out, s
+
+
+def version() -> int:
+    return int(load().rsaw_version())
+
+
+def shutdown():
+    load().rsaw_shutdown()

@@ -1,0 +1,184 @@
+// Lattice chain growth on the simple cubic lattice (Sec. 3.3.2, Algorithm 1;
+// weight of Eq. 3), one chain per lane, chain state in VGPRs.
+//
+// Monomer word (one 32-bit VGPR per monomer, fully unrolled over NMAX):
+//   byte 0 : Q = x + 2y + 3z  (mod 256)
+//   byte 1 : x + 128,  byte 2 : y + 128,  byte 3 : z + 128
+// Coordinates of an N <= 128 chain stay in [-127, 127], so bytes 1..3 never
+// wrap and never become zero.
+//
+// Pair test of step i (tip t = monomer i-1), for each earlier monomer j of the
+// parity that can touch the tip's neighbours (j = i-2, i-4, ...; the cubic
+// lattice is bipartite, so the other parity never neighbours the tip):
+//   L    = v_msad_u8(r_j, t & ~0xFF)   L1 distance; byte 0 is masked because
+//                                      the reference byte is zero
+//   bit  = sat(2 - L)                  1 iff r_j is a neighbour of t
+//   code = (Q_j - Q_t + 3) mod 32      = 0..6 \ {3}: -z, -y, -x, +x, +y, +z
+//   occ |= bit << code                 v_lshl_or_b32
+// Four VALU operations per pair, no memory access.  The six neighbour codes
+// are also the candidates' canonical order, so free = ~occ & 0x77 is already
+// the ordered candidate mask and the pick is a table lookup.
+#include "rsaw_device.hpp"
+
+#include <type_traits>
+
+namespace rsaw {
+
+// Compile-time loop: f(integral_constant<int, I>) for I = B .. E-1, so that
+// every index into the register-resident chain is a constant.
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// LUT[mask * 8 + r]: the move to the r-th free candidate of the 7-bit mask,
+// packed as (coordinate delta in bytes 1..3) | (dQ mod 256 in byte 0).
+__device__ __forceinline__ uint32_t lattice_move(uint32_t idx)
+{
+    const uint32_t mask = idx >> 3, r = idx & 7u;
+    uint32_t seen = 0;
+    for (uint32_t c = 0; c < 7; ++c) {
+        if (c == 3 || !((mask >> c) & 1u)) continue;
+        if (seen == r) {
+            const int dq = (int)c - 3;
+            const int axis = dq < 0 ? -dq : dq; // 1 = x, 2 = y, 3 = z
+            const int32_t dcoord = (dq < 0 ? -1 : 1) * (int32_t)(1u << (8 * axis));
+            return ((uint32_t)dcoord & 0xFFFFFF00u) | ((uint32_t)dq & 0xFFu);
+        }
+        ++seen;
+    }
+    return 0;
+}
+
+constexpr int kLutSize = 120 * 8; // masks up to 0x77
+
+template <int NMAX, bool EXACT, typename CT>
+__global__ __launch_bounds__(256) void grow_lattice_reg(GrowArgs a)
+{
+    __shared__ uint32_t lut[kLutSize];
+    __shared__ double logm[8];
+    for (int t = threadIdx.x; t < kLutSize; t += blockDim.x) lut[t] = lattice_move((uint32_t)t);
+    if (threadIdx.x < 8) logm[threadIdx.x] = a.logm[threadIdx.x];
+    __syncthreads();
+
+    const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = c < a.n_chains;
+    const uint64_t g = a.chain_offset + c;
+    const int N = a.n_monomers;
+
+    uint32_t pos[NMAX];
+    static_for<0, NMAX>([&](auto J) { pos[J.value] = 0x80808000u; }); // origin, Q = 0
+    uint32_t tip = 0x80808000u;
+    bool alive = valid;
+    int grown = 1;
+    double lw = 0.0;
+    uint64_t wx = 1;
+    bool rng_fail = false;
+    Philox4 blk{0, 0, 0, 0};
+
+    static_for<1, NMAX>([&](auto I) {
+        constexpr int i = I.value;
+        if (i >= N) return;
+        // candidates: occupied-neighbour mask from the same-parity monomers
+        const uint32_t tref = tip & 0xFFFFFF00u;
+        const uint32_t tq = tip - 3u;
+        uint32_t occ = 0;
+        static_for<0, i / 2>([&](auto Q) {
+            constexpr int j = i - 2 - 2 * Q.value;
+            const uint32_t L = __builtin_amdgcn_msad_u8(pos[j], tref, 0u);
+            const uint32_t bit = __builtin_elementwise_sub_sat(2u, L);
+            occ = (bit << ((pos[j] - tq) & 31u)) | occ;
+        });
+        const uint32_t freem = ~occ & 0x77u;
+        const uint32_t m = __builtin_popcount(freem);
+
+        // primary selection word: one Philox block per four steps
+        if constexpr (i == 1 || (i & 3) == 0) blk = draw(a.seed, g, (uint32_t)(i >> 2), kSlotSelect, 0);
+        const uint32_t x = (i & 3) == 0 ? blk.x0 : ((i & 3) == 1 ? blk.x1 : ((i & 3) == 2 ? blk.x2 : blk.x3));
+        const uint64_t p = (uint64_t)x * m;
+        uint32_t r = (uint32_t)(p >> 32);
+        if (__builtin_expect(alive && m != 0 && (uint32_t)p < 4u, 0))
+            r = lemire_redraw(a.seed, g, (uint32_t)i, m, x, &rng_fail);
+
+        const bool step_ok = alive && m != 0;
+        const uint32_t mv = lut[(freem << 3) | (r & 7u)];
+        const uint32_t nxt = ((tip & 0xFFFFFF00u) + (mv & 0xFFFFFF00u)) | ((tip + mv) & 0xFFu);
+        if (alive && m == 0) {
+            alive = false;
+            grown = i;
+        }
+        tip = step_ok ? nxt : tip;
+        pos[i] = tip;
+        if (step_ok) {
+            lw = lw + logm[m];
+            if (EXACT) wx = wx * (uint64_t)m;
+        }
+    });
+    if (alive) grown = N;
+
+    // observables over the g placed monomers, from the biased coordinate bytes
+    uint32_t sx = 0, sy = 0, sz = 0, s2 = 0;
+    static_for<0, NMAX>([&](auto J) {
+        constexpr int j = J.value;
+        const uint32_t w = j < grown ? (pos[j] & 0xFFFFFF00u) : 0u;
+        sx = __builtin_amdgcn_udot4(w, 0x00000100u, sx, false);
+        sy = __builtin_amdgcn_udot4(w, 0x00010000u, sy, false);
+        sz = __builtin_amdgcn_udot4(w, 0x01000000u, sz, false);
+        s2 = __builtin_amdgcn_udot4(w, w, s2, false);
+    });
+    const int64_t gg = grown;
+    const int64_t Sx = (int64_t)sx - 128 * gg, Sy = (int64_t)sy - 128 * gg, Sz = (int64_t)sz - 128 * gg;
+    const int64_t S2 = (int64_t)s2 - 256 * ((int64_t)sx + (int64_t)sy + (int64_t)sz) + 3 * 16384 * gg;
+    const int64_t nn = gg * S2 - (Sx * Sx + Sy * Sy + Sz * Sz);
+    const int32_t ex = (int32_t)((tip >> 8) & 0xFFu) - 128;
+    const int32_t ey = (int32_t)((tip >> 16) & 0xFFu) - 128;
+    const int32_t ez = (int32_t)(tip >> 24) - 128;
+    const double logw = alive ? lw : -__builtin_huge_val();
+
+    if (valid) {
+        if (a.log_w) a.log_w[c] = logw;
+        if (EXACT && a.w_exact) a.w_exact[c] = alive ? wx : 0ull;
+        if (a.r_end) {
+            CT *re = (CT *)a.r_end;
+            re[c] = (CT)ex;
+            re[a.n_chains + c] = (CT)ey;
+            re[2 * a.n_chains + c] = (CT)ez;
+        }
+        if (a.r2) a.r2[c] = (double)(ex * ex + ey * ey + ez * ez);
+        if (a.n2rg2) a.n2rg2[c] = nn;
+        if (a.rg2) a.rg2[c] = (double)nn / ((double)gg * (double)gg);
+        if (a.n_grown) a.n_grown[c] = (uint16_t)grown;
+    }
+    if (rng_fail) atomicExch(a.status, 6);
+    const uint64_t bits = alive ? (uint64_t)__double_as_longlong(lw) : 0ull;
+    const uint64_t wmax = wave_max_u64(bits);
+    if ((threadIdx.x & 63) == 0 && wmax != 0) atomicMax(a.log_w_max_bits, (unsigned long long)wmax);
+}
+
+template <int NMAX, bool EXACT, typename CT>
+static hipError_t launch(const GrowArgs &a, hipStream_t s)
+{
+    const uint64_t blocks = (a.n_chains + 255) / 256;
+    hipLaunchKernelGGL((grow_lattice_reg<NMAX, EXACT, CT>), dim3((uint32_t)blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// Dispatch on the N bucket, exact-weight flag and output coordinate type.
+hipError_t launch_grow_lattice(const GrowArgs &a, bool exact, bool i16, hipStream_t s)
+{
+    const int N = a.n_monomers;
+    if (exact) {
+        // RSAW_EXACT_W is limited to N <= 28 by the caller
+        if (N <= 16) return i16 ? launch<16, true, int16_t>(a, s) : launch<16, true, int32_t>(a, s);
+        return i16 ? launch<32, true, int16_t>(a, s) : launch<32, true, int32_t>(a, s);
+    }
+    if (N <= 16) return i16 ? launch<16, false, int16_t>(a, s) : launch<16, false, int32_t>(a, s);
+    if (N <= 32) return i16 ? launch<32, false, int16_t>(a, s) : launch<32, false, int32_t>(a, s);
+    return i16 ? launch<64, false, int16_t>(a, s) : launch<64, false, int32_t>(a, s);
+}
+
+} // namespace rsaw

@@ -1,0 +1,114 @@
+// Device-side building blocks of librsaw: the Philox4x32-10 block function,
+// Lemire's uniform pick, wave-level helpers and the kernel argument blocks.
+//
+// Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) keyed by
+// the 64-bit seed; the counter is (lo32(g), hi32(g), c2, slot << 16 | attempt)
+// with g the global chain index.  Word use per growth step i:
+//   slot 0xFFFF, c2 = i >> 2      : primary selection word i & 3 (both geometries)
+//   slot 0xFFFE, c2 = i, attempt a: redraw words of Lemire's rejection
+//   slot t < 64, c2 = i, attempt a: real-space trial t, Marsaglia attempt a
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rsaw {
+
+constexpr uint32_t kSlotSelect = 0xFFFFu;
+constexpr uint32_t kSlotRedraw = 0xFFFEu;
+constexpr uint32_t kMaxAttempt = 65536u;
+
+struct Philox4 {
+    uint32_t x0, x1, x2, x3;
+};
+
+// Ten Philox rounds; the key schedule adds the Weyl constants after each round.
+__device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                 uint32_t c3, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return Philox4{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ Philox4 draw(uint64_t seed, uint64_t g, uint32_t c2, uint32_t slot,
+                                        uint32_t attempt)
+{
+    return philox4x32_10((uint32_t)g, (uint32_t)(g >> 32), c2, (slot << 16) | attempt,
+                         (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+__device__ __forceinline__ uint32_t word(const Philox4 &b, uint32_t w)
+{
+    return w == 0 ? b.x0 : (w == 1 ? b.x1 : (w == 2 ? b.x2 : b.x3));
+}
+
+// Lemire's rejection after a primary word x gave lo32(x m) below 2^32 mod m:
+// continue with the redraw words of step `step`.  Returns the index in [0, m)
+// or sets *fail when the attempt cap is reached.
+__device__ __noinline__ uint32_t lemire_redraw(uint64_t seed, uint64_t g, uint32_t step,
+                                               uint32_t m, uint32_t x, bool *fail)
+{
+    const uint32_t threshold = (uint32_t)((uint64_t)0x100000000ull % m);
+    uint64_t p = (uint64_t)x * m;
+    if ((uint32_t)p >= threshold) return (uint32_t)(p >> 32);
+    for (uint32_t a = 0; a < kMaxAttempt; ++a) {
+        const Philox4 b = draw(seed, g, step, kSlotRedraw, a);
+        const uint32_t ws[4] = {b.x0, b.x1, b.x2, b.x3};
+        for (int w = 0; w < 4; ++w) {
+            p = (uint64_t)ws[w] * m;
+            if ((uint32_t)p >= threshold) return (uint32_t)(p >> 32);
+        }
+    }
+    *fail = true;
+    return 0;
+}
+
+// Wave-wide max of a 64-bit value (all 64 lanes must be active).
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel argument blocks (passed by value).
+// ---------------------------------------------------------------------------
+struct GrowArgs {
+    uint64_t seed;
+    uint64_t chain_offset;
+    uint64_t n_chains;
+    int32_t n_monomers;
+    int32_t k_trials;
+    double bond_length;
+    double sigma2;
+    // per-chain outputs (device, any may be null)
+    double *log_w;
+    uint64_t *w_exact;
+    void *r_end;
+    double *r2;
+    double *rg2;
+    int64_t *n2rg2;
+    uint16_t *n_grown;
+    // reduction side channels
+    unsigned long long *log_w_max_bits; // atomicMax of the bit pattern (log W >= 0)
+    int32_t *status;                    // RSAW_E_RNG on a rejection-cap hit
+    double logm[65];                    // ln(m) correctly rounded, m = 0..64
+};
+
+} // namespace rsaw

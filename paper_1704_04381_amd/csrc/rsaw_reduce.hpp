@@ -1,0 +1,43 @@
+// Argument block and per-block partial of the ensemble reduction kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rsaw.h"
+
+namespace rsaw {
+
+constexpr int kNumSums = 8; // S0, S2, wR2, w2R2, w2R2^2, wRg2, w2Rg2, w2Rg2^2
+constexpr int kMaxBins = 256;
+
+struct BlockPartial {
+    double s[kNumSums];
+    uint64_t alive, steps;
+    uint64_t ex[6]; // three 128-bit exact sums as (lo, hi)
+};
+
+struct ReduceArgs {
+    uint64_t n_chains;
+    uint64_t chunk; // chains per block, a multiple of 256
+    int32_t n_monomers;
+    int32_t bins;
+    int32_t exact;
+    const double *log_w;
+    const double *r2;
+    const double *rg2;
+    const uint16_t *n_grown;
+    const uint64_t *w_exact;
+    const int64_t *n2rg2;
+    const unsigned long long *lmax_bits;
+    const int32_t *status;
+    BlockPartial *partials;
+    double *part_hist_w;
+    uint64_t *part_hist_n;
+};
+
+hipError_t launch_reduce_init(unsigned long long *lmax_bits, int32_t *status, hipStream_t s);
+hipError_t launch_reduce(const ReduceArgs &a, uint32_t n_blocks, rsaw_summary *out,
+                         double *hist_w, uint64_t *hist_n, hipStream_t s);
+
+} // namespace rsaw

@@ -1,0 +1,254 @@
+"""Parity of the HIP path (librsaw through its C ABI) with the oracle.
+
+Lattice: every per-chain output (log W, exact W, end vector, R^2, g^2 Rg^2,
+Rg^2, monomers placed) must match the oracle bit for bit; the exact 128-bit
+ensemble sums too.  Real space: the same per-chain outputs, required within
+1e-12 relative (the decisions use correctly rounded sqrt and division and no
+contraction, so they come out identical in practice).  Floating-point
+ensemble sums: 1e-12 relative; the derivation is in the module constant
+below.  Sizes span several 256-chain tiles with a ragged tail; the headline
+sizes are checked on sampled chains plus a full re-reduction by the oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+import paper_1704_04381_amd as rs
+from paper_1704_04381_amd.workloads import WORKLOADS
+
+pytestmark = pytest.mark.gpu
+
+# Ensemble sums of positive terms: the GPU sums each thread's chains in order,
+# then two fixed trees; the oracle sums sequentially with compensation.  Both
+# are within ~log2(M) * 2^-53 ~ 3e-15 of the exact sum for M <= 10^7, and the
+# device exp() differs from the host's by at most 1 ulp per term.  1e-12 leaves
+# a wide margin while still catching any dropped or double-counted chain
+# (a single chain weighs at least 1/ESS of the sum).
+RTOL_SUM = 1e-12
+RTOL_REAL = 1e-12
+
+SUM_KEYS = ["sum_w", "sum_w2", "sum_w_r2", "sum_w2_r2", "sum_w2_r2sq", "sum_w_rg2",
+            "sum_w2_rg2", "sum_w2_rg2sq", "log_c_est", "r2_mean", "rg2_mean", "ess"]
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+def _gpu(geometry, N, k, M, seed, **kw):
+    print(f"[gpu] {geometry} N={N} k={k} M={M} seed={seed} {kw}", flush=True)
+    out, s = rs.gen_chains(geometry, N, k, M, seed, **kw)
+    torch.cuda.synchronize()
+    return {n: _np(t) for n, t in out.items()}, s
+
+
+def _check_summary(s, ref, M, exact_ref=None):
+    assert s["status"] == 0
+    assert s["n_chains"] == M
+    assert s["n_alive"] == ref["alive"]
+    assert s["steps"] == ref["steps"]
+    if ref["alive"] == 0:
+        assert s["log_c_est"] == -math.inf
+        return
+    assert s["log_w_max"] == ref["log_w_max"]
+    for key in SUM_KEYS:
+        a, b = s[key], ref[key]
+        assert abs(a - b) <= RTOL_SUM * abs(b), (key, a, b)
+    for key in ("r2_err", "rg2_err", "c_rel_err"):
+        a, b = s[key], ref[key]
+        if math.isfinite(b):
+            assert abs(a - b) <= 1e-6 * abs(b) + 1e-300, (key, a, b)
+    if exact_ref is not None:
+        assert s["exact_valid"] == 1
+        assert s["sum_w_exact"] == exact_ref["sum_w"]
+        assert s["sum_w_r2_exact"] == exact_ref["sum_w_r2"]
+        assert s["sum_w_n2rg2_exact"] == exact_ref["sum_w_n2rg2"]
+
+
+def _lattice_case(N, M, seed, coord="i32", exact_w=False, bins=0, offset=0):
+    out, s = _gpu("lattice", N, 6, M, seed, coord=coord, exact_w=exact_w, hist_bins=bins,
+                  chain_offset=offset)
+    ref = oracle.gen_lattice(seed, N, M, chain_offset=offset)
+    np.testing.assert_array_equal(out["n_grown"].view(np.uint16), ref["n_grown"])
+    np.testing.assert_array_equal(out["log_w"], ref["log_w"])
+    np.testing.assert_array_equal(out["r_end"].astype(np.int32), ref["r_end"])
+    np.testing.assert_array_equal(out["r2"], ref["r2"].astype(np.float64))
+    np.testing.assert_array_equal(out["n2rg2"], ref["n2rg2"])
+    np.testing.assert_array_equal(out["rg2"], ref["rg2"])
+    if exact_w:
+        np.testing.assert_array_equal(out["w_exact"], ref["w_exact"])
+    red = oracle.reduce(N, ref["log_w"], ref["r2"], ref["rg2"], ref["n_grown"], bins=bins)
+    ex = oracle.reduce_exact(ref["w_exact"], ref["r2"], ref["n2rg2"]) if exact_w else None
+    _check_summary(s, red, M, ex)
+    if bins:
+        np.testing.assert_array_equal(out["hist_n"], red["hist_n"])
+        np.testing.assert_allclose(out["hist_w"], red["hist_w"], rtol=RTOL_SUM, atol=0)
+    return out, s
+
+
+@pytest.mark.parametrize("N,M,seed", [(16, 20_000, 1), (16, 777, 5), (28, 3001, 2)])
+def test_lattice_exact_weights(N, M, seed):
+    _lattice_case(N, M, seed, coord="i32", exact_w=True)
+
+
+@pytest.mark.parametrize("N,M,seed,coord", [(64, 6_000, 1, "i16"), (64, 2_561, 3, "i32"),
+                                            (33, 4_100, 4, "i16"), (17, 1_000, 6, "i32"),
+                                            (1, 300, 7, "i32"), (2, 300, 8, "i16"),
+                                            (3, 257, 9, "i32"), (5, 10_000, 10, "i16")])
+def test_lattice_bit_exact(N, M, seed, coord):
+    _lattice_case(N, M, seed, coord=coord, bins=256 if N > 1 else 0)
+
+
+def test_lattice_dead_chains_bit_exact():
+    # N = 64 chains get trapped often enough to exercise the dead-end path
+    out, _ = _lattice_case(64, 40_000, 11, coord="i16", bins=256)
+    assert (out["n_grown"].view(np.uint16) < 64).sum() > 10
+
+
+def _real_case(N, k, M, seed, b=1.0, sigma=1.0, bins=0, offset=0):
+    out, s = _gpu("real", N, k, M, seed, bond_length=b, bead_diameter=sigma, hist_bins=bins,
+                  chain_offset=offset)
+    ref = oracle.gen_real(seed, N, k, M, b=b, sigma=sigma, chain_offset=offset)
+    np.testing.assert_array_equal(out["n_grown"].view(np.uint16), ref["n_grown"])
+    alive = np.isfinite(ref["log_w"])
+    np.testing.assert_array_equal(np.isfinite(out["log_w"]), alive)
+    np.testing.assert_allclose(out["log_w"][alive], ref["log_w"][alive], rtol=RTOL_REAL, atol=0)
+    for key in ("r2", "rg2"):
+        np.testing.assert_allclose(out[key], ref[key], rtol=RTOL_REAL, atol=1e-300)
+    scale = np.maximum(np.abs(ref["r_end"]).max(), 1.0)
+    np.testing.assert_allclose(out["r_end"], ref["r_end"], rtol=0, atol=RTOL_REAL * scale)
+    red = oracle.reduce(N, ref["log_w"], ref["r2"], ref["rg2"], ref["n_grown"], bins=bins)
+    _check_summary(s, red, M)
+    if bins:
+        np.testing.assert_array_equal(out["hist_n"], red["hist_n"])
+        np.testing.assert_allclose(out["hist_w"], red["hist_w"], rtol=RTOL_SUM, atol=0)
+    exact = all(np.array_equal(out[kk], ref[kk]) for kk in ("log_w", "r2", "rg2", "r_end"))
+    print(f"[gpu] real N={N} k={k}: per-chain outputs bit-identical: {exact}", flush=True)
+    return out, s, exact
+
+
+@pytest.mark.parametrize("N,k,M,seed", [(64, 8, 1_500, 1), (17, 8, 2_003, 2), (3, 8, 999, 3),
+                                        (2, 8, 100, 4), (1, 8, 64, 5), (24, 1, 700, 6),
+                                        (24, 5, 700, 7), (20, 16, 600, 8), (12, 33, 300, 9),
+                                        (10, 64, 200, 10)])
+def test_real_parity(N, k, M, seed):
+    _, _, exact = _real_case(N, k, M, seed, bins=128)
+    assert exact
+
+
+def test_real_ideal_chain_and_bond_length():
+    out, s, exact = _real_case(30, 8, 1_000, 12, b=1.5, sigma=0.0)
+    assert exact
+    assert np.all(out["log_w"] == out["log_w"][0])
+
+
+def test_real_dense_spheres_with_dead_chains():
+    # sigma > b makes dead ends frequent
+    out, s, exact = _real_case(40, 4, 3_000, 13, b=1.0, sigma=1.4)
+    assert (out["n_grown"].view(np.uint16) < 40).sum() > 10
+    assert exact
+
+
+def test_empty_ensemble():
+    out, s = _gpu("lattice", 16, 6, 0, 1, hist_bins=16)
+    assert s["n_chains"] == 0 and s["n_alive"] == 0 and s["log_c_est"] == -math.inf
+    assert out["hist_n"].sum() == 0
+
+
+def test_split_ranges_equal_one_launch_and_determinism():
+    M = 10_000
+    full, s_full = _gpu("lattice", 64, 6, M, 21, coord="i16", hist_bins=64)
+    again, s_again = _gpu("lattice", 64, 6, M, 21, coord="i16", hist_bins=64)
+    for key in full:
+        np.testing.assert_array_equal(full[key], again[key])
+    assert s_full == s_again
+    a, _ = _gpu("lattice", 64, 6, 4_321, 21, coord="i16")
+    b, _ = _gpu("lattice", 64, 6, M - 4_321, 21, coord="i16", chain_offset=4_321)
+    for key in ("log_w", "r2", "rg2", "n2rg2", "n_grown"):
+        np.testing.assert_array_equal(np.concatenate([a[key], b[key]]), full[key])
+    np.testing.assert_array_equal(np.concatenate([a["r_end"], b["r_end"]], axis=1), full["r_end"])
+    ra, _ = _gpu("real", 40, 8, 3_000, 22)
+    rb, _ = _gpu("real", 40, 8, 3_000, 22)
+    for key in ra:
+        np.testing.assert_array_equal(ra[key], rb[key])
+
+
+def _sampled_indices(M, n, seed):
+    rng = np.random.default_rng(seed)
+    idx = np.unique(np.concatenate([np.arange(0, M, max(1, M // n)), rng.integers(0, M, n),
+                                    [0, M - 1]]))
+    return idx
+
+
+def test_headline_lattice_n64_sampled():
+    """Full-size lattice workload: sampled chains against the oracle chain by
+    chain, and the full reduction against the oracle's reduction of the same
+    per-chain outputs."""
+    w = WORKLOADS["lattice_n64"]
+    out, s = _gpu(w["geometry"], w["N"], w["k"], w["n_chains"], w["seed"], coord=w["coord"],
+                  hist_bins=w["hist_bins"])
+    M, N = w["n_chains"], w["N"]
+    idx = _sampled_indices(M, 1500, 99)
+    for c in idx:
+        ch = oracle.lattice_chain(w["seed"], int(c), N)
+        assert out["log_w"][c] == ch["log_w"]
+        assert int(out["n_grown"].view(np.uint16)[c]) == ch["n_grown"]
+        assert tuple(int(v) for v in out["r_end"][:, c]) == tuple(int(v) for v in ch["end"])
+        assert out["n2rg2"][c] == ch["n2rg2"]
+        assert out["rg2"][c] == ch["rg2"]
+    red = oracle.reduce(N, out["log_w"], out["r2"], out["rg2"],
+                        out["n_grown"].view(np.uint16).astype(np.int32), bins=w["hist_bins"])
+    _check_summary(s, red, M)
+    np.testing.assert_array_equal(out["hist_n"], red["hist_n"])
+    np.testing.assert_allclose(out["hist_w"], red["hist_w"], rtol=RTOL_SUM, atol=0)
+    assert s["n_alive"] > 0.9 * M
+
+
+def test_headline_real_n64_sampled():
+    w = WORKLOADS["real_n64"]
+    out, s = _gpu(w["geometry"], w["N"], w["k"], w["n_chains"], w["seed"],
+                  bond_length=w["bond_length"], bead_diameter=w["bead_diameter"],
+                  hist_bins=w["hist_bins"])
+    M, N, k = w["n_chains"], w["N"], w["k"]
+    idx = _sampled_indices(M, 400, 98)
+    for c in idx:
+        ch = oracle.real_chain(w["seed"], int(c), N, k)
+        assert int(out["n_grown"].view(np.uint16)[c]) == ch["n_grown"]
+        if math.isfinite(ch["log_w"]):
+            assert abs(out["log_w"][c] - ch["log_w"]) <= RTOL_REAL * ch["log_w"]
+        else:
+            assert out["log_w"][c] == -math.inf
+        assert abs(out["r2"][c] - ch["r2"]) <= RTOL_REAL * ch["r2"]
+        assert abs(out["rg2"][c] - ch["rg2"]) <= RTOL_REAL * ch["rg2"]
+    red = oracle.reduce(N, out["log_w"], out["r2"], out["rg2"],
+                        out["n_grown"].view(np.uint16).astype(np.int32), bins=w["hist_bins"])
+    _check_summary(s, red, M)
+    np.testing.assert_array_equal(out["hist_n"], red["hist_n"])
+
+
+def test_headline_lattice_n16_full():
+    w = WORKLOADS["lattice_n16"]
+    _lattice_case(w["N"], w["n_chains"], w["seed"], coord=w["coord"], exact_w=True)
+
+
+def test_ensemble_averages_agree_within_3_sigma():
+    """Independent seeds: GPU and oracle ensembles are statistically equal."""
+    _, g = _gpu("real", 32, 8, 200_000, 31)
+    ref = oracle.gen_real(32, 32, 8, 40_000)
+    r = oracle.reduce(32, ref["log_w"], ref["r2"], ref["rg2"], ref["n_grown"])
+    for key in ("r2", "rg2"):
+        d = g[f"{key}_mean"] - r[f"{key}_mean"]
+        se = math.hypot(g[f"{key}_err"], r[f"{key}_err"])
+        assert abs(d) < 3 * se, (key, d, se)
+    _, g = _gpu("lattice", 64, 6, 1_000_000, 33, coord="i16")
+    ref = oracle.gen_lattice(34, 64, 100_000)
+    r = oracle.reduce(64, ref["log_w"], ref["r2"], ref["rg2"], ref["n_grown"])
+    for key in ("r2", "rg2"):
+        d = g[f"{key}_mean"] - r[f"{key}_mean"]
+        se = math.hypot(g[f"{key}_err"], r[f"{key}_err"])
+        assert abs(d) < 3 * se, (key, d, se)
+    assert abs(g["log_c_est"] - r["log_c_est"]) < 3 * math.hypot(g["c_rel_err"], r["c_rel_err"])
