@@ -73,6 +73,10 @@ def _load():
         lib.oro_reduce.restype = None
         lib.oro_reduce_exact.argtypes = [u64, vp, vp, vp, vp]
         lib.oro_reduce_exact.restype = None
+        lib.oro_lemire16.argtypes = [C.c_uint32, C.c_uint32, vp]
+        lib.oro_lemire16.restype = C.c_int
+        lib.oro_pick.argtypes = [u64, u64, C.c_uint32, C.c_uint32, vp, vp]
+        lib.oro_pick.restype = C.c_int
         _lib = lib
         return lib
 
@@ -97,6 +101,22 @@ def philox(counter, seed):
     out = np.zeros(4, dtype=np.uint32)
     lib.oro_philox4x32_10(_p(ctr), C.c_uint64(seed), _p(out))
     return out
+
+
+def lemire16(x, m):
+    """Lemire acceptance of one 16-bit word for [0, m): index or None."""
+    lib = _load()
+    idx = np.zeros(1, dtype=np.uint32)
+    return int(idx[0]) if lib.oro_lemire16(x, m, _p(idx)) else None
+
+
+def pick(seed, chain, step, m):
+    """(index, rejected half-words) of the uniform pick of step ``step``."""
+    lib = _load()
+    idx = np.zeros(1, dtype=np.uint32)
+    rej = np.zeros(1, dtype=np.uint32)
+    _check(lib.oro_pick(seed, chain, step, m, _p(idx), _p(rej)), "pick")
+    return int(idx[0]), int(rej[0])
 
 
 def unit_vector(seed, chain, step, trial):

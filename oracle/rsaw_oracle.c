@@ -28,7 +28,7 @@
  * numbers: as easy as 1, 2, 3", SC'11), keyed by the 64-bit seed; the
  * 128-bit counter names (chain, step, slot, attempt) so that every chain can
  * be recomputed alone.  Uniform integers in [0, m) use Lemire's multiply-and-
- * reject method (ACM TOMACS 29(1), 2019).  Unit vectors use Marsaglia's
+ * reject method (ACM TOMACS 29(1), 2019) on 16-bit words.  Unit vectors use Marsaglia's
  * disc method (Ann. Math. Stat. 43 (1972) 645).
  *
  * Floating point: IEEE binary64, round to nearest, built without
@@ -81,39 +81,76 @@ static void draw_block(uint64_t seed, uint64_t chain, uint32_t c2,
     oro_philox4x32_10(ctr, seed, out);
 }
 
-#define SLOT_SELECT 0xFFFFu   /* primary selection word, one block per 4 steps */
-#define SLOT_REDRAW 0xFFFEu   /* Lemire redraw words for step i                */
+#define SLOT_SELECT 0xFFFFu   /* primary selection half-words, one block per 8 steps */
+#define SLOT_REDRAW 0xFFFEu   /* Lemire redraw half-words for step i                */
 #define MAX_ATTEMPT 65536u
 
+/* 16-bit half h (0..7) of a Philox block: word h / 2, low half for even h. */
+static uint32_t half_word(const uint32_t blk[4], uint32_t h)
+{
+    uint32_t w = blk[h >> 1];
+    return (h & 1u) ? (w >> 16) : (w & 0xFFFFu);
+}
+
 /* ------------------------------------------------------------------------ */
-/* Uniform index in [0, m): Lemire's method.  The word stream for step i is  */
-/* the primary word (word i mod 4 of block (i / 4, SLOT_SELECT)), then the   */
-/* four words of block (i, SLOT_REDRAW, attempt 0), then attempt 1, ...      */
-/* Accept x when lo32(x m) >= 2^32 mod m; the index is hi32(x m).            */
+/* Uniform index in [0, m): Lemire's method on 16-bit words.  The word       */
+/* stream for step i is the primary half-word (half i mod 8 of block         */
+/* (i / 8, SLOT_SELECT)), then the eight halves of block (i, SLOT_REDRAW,    */
+/* attempt 0), then attempt 1, ...  Accept x when (x m) mod 2^16 >=          */
+/* 2^16 mod m; the index is (x m) / 2^16.                                    */
 /* ------------------------------------------------------------------------ */
-static int pick_uniform(uint64_t seed, uint64_t chain, uint32_t step,
-                        uint32_t m, uint32_t *index)
+int oro_lemire16(uint32_t x, uint32_t m, uint32_t *index)
+{
+    uint32_t threshold = 65536u % m;
+    uint32_t p = x * m;
+    if ((p & 0xFFFFu) < threshold) return 0;
+    *index = p >> 16;
+    return 1;
+}
+
+/* The pick of step i; *redraws counts the rejected half-words. */
+int oro_pick(uint64_t seed, uint64_t chain, uint32_t step, uint32_t m,
+             uint32_t *index, uint32_t *redraws)
 {
     uint32_t blk[4];
-    draw_block(seed, chain, step >> 2, SLOT_SELECT, 0, blk);
-    uint32_t x = blk[step & 3u];
-    uint32_t threshold = (uint32_t)((((uint64_t)1) << 32) % m);
-    uint64_t p = (uint64_t)x * (uint64_t)m;
-    if ((uint32_t)p >= threshold) {
-        *index = (uint32_t)(p >> 32);
+    uint32_t rejected = 0;
+    draw_block(seed, chain, step >> 3, SLOT_SELECT, 0, blk);
+    if (oro_lemire16(half_word(blk, step & 7u), m, index)) {
+        if (redraws) *redraws = 0;
         return ORO_OK;
     }
+    ++rejected;
     for (uint32_t a = 0; a < MAX_ATTEMPT; ++a) {
         draw_block(seed, chain, step, SLOT_REDRAW, a, blk);
-        for (int w = 0; w < 4; ++w) {
-            p = (uint64_t)blk[w] * (uint64_t)m;
-            if ((uint32_t)p >= threshold) {
-                *index = (uint32_t)(p >> 32);
+        for (uint32_t h = 0; h < 8; ++h) {
+            if (oro_lemire16(half_word(blk, h), m, index)) {
+                if (redraws) *redraws = rejected;
                 return ORO_OK;
             }
+            ++rejected;
         }
     }
     return ORO_E_RNG;
+}
+
+static int pick_uniform(uint64_t seed, uint64_t chain, uint32_t step,
+                        uint32_t m, uint32_t *index)
+{
+    return oro_pick(seed, chain, step, m, index, NULL);
+}
+
+/* ------------------------------------------------------------------------ */
+/* log W (Eq. 3): W = prod_i m_i = prod_m m^(n_m), with n_m the number of     */
+/* steps that had m free candidates.  log W = sum over m = 1 .. K, ascending, */
+/* of n_m * log(m), each product and sum rounded once in binary64.  This is   */
+/* the same quantity as the step-by-step sum of log m_i, with K - 1 products  */
+/* and additions instead of one addition per step.                          */
+/* ------------------------------------------------------------------------ */
+static double log_weight(const int64_t *n_of_m, int K)
+{
+    double lw = 0.0;
+    for (int m = 1; m <= K; ++m) lw = lw + (double)n_of_m[m] * log((double)m);
+    return lw;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -130,7 +167,7 @@ static const int32_t LATTICE_DIR[6][3] = {
  * Outputs (each pointer may be NULL):
  *   xyz[3*N]   coordinates of the placed monomers (rest untouched)
  *   m_seq[N]   m_i for step i (m_seq[0] = 0; steps past a dead end untouched)
- *   log_w      sum over steps of log(m_i); -inf for a dead chain
+ *   log_w      log W = sum over m of n_m log(m) (see log_weight); -inf if dead
  *   w_exact    product of m_i as an integer; 0 for a dead chain;
  *              UINT64_MAX-saturated with *w_exact_ok = 0 when it overflows
  *   n_grown    number of monomers placed (N for a complete chain)
@@ -148,7 +185,7 @@ int oro_lattice_chain(uint64_t seed, uint64_t chain, int32_t N,
     int32_t *pos = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)N);
     if (!pos) return ORO_E_NOMEM;
     pos[0] = 0; pos[1] = 0; pos[2] = 0;
-    double lw = 0.0;
+    int64_t n_of_m[7] = {0, 0, 0, 0, 0, 0, 0}; /* steps with m_i = m */
     uint64_t w = 1;
     int w_ok = 1;
     int32_t g = 1;
@@ -191,7 +228,7 @@ int oro_lattice_chain(uint64_t seed, uint64_t chain, int32_t N,
         pos[3 * i + 1] = tip[1] + LATTICE_DIR[chosen][1];
         pos[3 * i + 2] = tip[2] + LATTICE_DIR[chosen][2];
         g = i + 1;
-        lw = lw + log((double)m);
+        n_of_m[m] += 1;
         if (w_ok && w > UINT64_MAX / m) w_ok = 0;
         if (w_ok) w = w * m;
     }
@@ -199,6 +236,8 @@ int oro_lattice_chain(uint64_t seed, uint64_t chain, int32_t N,
         free(pos);
         return status;
     }
+
+    double lw = log_weight(n_of_m, 6);
 
     /* Observables of the placed monomers 0 .. g-1. */
     int64_t sx = 0, sy = 0, sz = 0, s2 = 0;
@@ -284,7 +323,8 @@ int oro_real_chain(uint64_t seed, uint64_t chain, int32_t N, int32_t k,
     int free_[64];
     double sigma2 = sigma * sigma;
     pos[0] = 0.0; pos[1] = 0.0; pos[2] = 0.0;
-    double lw = 0.0;
+    int64_t n_of_m[65];
+    for (int q = 0; q <= 64; ++q) n_of_m[q] = 0;
     int32_t g = 1;
     int dead = 0;
     int status = ORO_OK;
@@ -327,12 +367,13 @@ int oro_real_chain(uint64_t seed, uint64_t chain, int32_t N, int32_t k,
         pos[3 * i + 1] = cand[chosen][1];
         pos[3 * i + 2] = cand[chosen][2];
         g = i + 1;
-        lw = lw + log((double)m);
+        n_of_m[m] += 1;
     }
     if (status != ORO_OK) {
         free(pos);
         return status;
     }
+    double lw = log_weight(n_of_m, k);
 
     double sx = 0.0, sy = 0.0, sz = 0.0;
     for (int32_t i = 0; i < g; ++i) {

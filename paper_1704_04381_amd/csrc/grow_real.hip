@@ -10,9 +10,11 @@
 //   2. it tests the candidate against beads 0 .. i-2 of its chain:
 //      ((dx dx + dy dy) + dz dz) < sigma^2 means overlap (no contraction);
 //   3. a ballot over the group gives the free mask; m = popcount;
-//   4. Lemire's pick (primary word from the 4-step selection block) chooses
+//   4. Lemire's pick (16-bit word from the 8-step selection block) chooses
 //      the r-th free trial; its candidate is broadcast with a lane shuffle and
-//      written to LDS as bead i by its owner.
+//      written to LDS as bead i by its owner;
+//   5. lane m - 1 of the group counts the steps with m free trials, and
+//      log W = sum_m n_m log m is formed once after the last step.
 // The final observables (two-pass Rg^2, R^2) are computed by lane 0 of each
 // group in bead order, exactly as the definitions read.
 #include "rsaw_device.hpp"
@@ -50,7 +52,7 @@ __global__ __launch_bounds__(256) void grow_real_tp(GrowArgs a)
     double tx = 0.0, ty = 0.0, tz = 0.0;
     bool alive = valid;
     int grown = 1;
-    double lw = 0.0;
+    uint32_t n_mine = 0; // steps with m = t + 1 (lane t counts one value of m)
     bool rng_fail = false;
     Philox4 sel{0, 0, 0, 0};
 
@@ -93,13 +95,13 @@ __global__ __launch_bounds__(256) void grow_real_tp(GrowArgs a)
         const uint64_t gm = (bal >> gbase) & gmask_bits;
         const uint32_t m = (uint32_t)__popcll(gm);
 
-        // 4. uniform pick among the free trials
-        if (i == 1 || (i & 3) == 0) sel = draw(a.seed, g, (uint32_t)(i >> 2), kSlotSelect, 0);
-        const uint32_t x = word(sel, (uint32_t)(i & 3));
-        const uint64_t p = (uint64_t)x * m;
-        uint32_t r = (uint32_t)(p >> 32);
-        if (__builtin_expect(alive && m != 0 && (uint32_t)p < 64u, 0))
-            r = lemire_redraw(a.seed, g, (uint32_t)i, m, x, &rng_fail);
+        // 4. uniform pick among the free trials (16-bit Lemire word)
+        if (i == 1 || (i & 7) == 0) sel = draw(a.seed, g, (uint32_t)(i >> 3), kSlotSelect, 0);
+        const uint32_t x = half_word(sel, (uint32_t)(i & 7));
+        const uint32_t p = x * m;
+        uint32_t r = p >> 16;
+        if (__builtin_expect(alive && (p & 0xFFFFu) < m, 0))
+            r = lemire_redraw16(a.seed, g, (uint32_t)i, m, x, &rng_fail);
         const uint64_t below = (t == 0) ? 0ull : (gm & ((1ull << t) - 1ull));
         const bool chosen = fr && ((uint32_t)__popcll(below) == r);
         const uint64_t cb = __ballot(chosen);
@@ -119,13 +121,22 @@ __global__ __launch_bounds__(256) void grow_real_tp(GrowArgs a)
                 ri[0] = nx; ri[1] = ny; ri[2] = nz;
             }
             tx = nx; ty = ny; tz = nz;
-            lw = lw + logm[m];
+            n_mine += (m == (uint32_t)t + 1u) ? 1u : 0u;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     if (alive) grown = N;
+
+    // log W = sum over m = 1..k, ascending, of n_m log m (Eq. 3 grouped by
+    // value); n_m is held by lane m - 1 of the group
+    double lw = 0.0;
+    for (int mm = 1; mm <= k; ++mm) {
+        const uint32_t nm = __shfl(n_mine, gbase + mm - 1, 64);
+        lw = lw + (double)nm * logm[mm];
+    }
+    if (!alive) lw = -__builtin_huge_val();
 
     // observables, lane 0 of the group, in bead order
     if (t == 0 && valid) {
@@ -148,7 +159,7 @@ __global__ __launch_bounds__(256) void grow_real_tp(GrowArgs a)
         const double ex = re[0], ey = re[1], ez = re[2];
         double r2 = ex * ex + ey * ey;
         r2 = r2 + ez * ez;
-        if (a.log_w) a.log_w[c] = alive ? lw : -__builtin_huge_val();
+        if (a.log_w) a.log_w[c] = lw;
         if (a.r_end) {
             double *o = (double *)a.r_end;
             o[c] = ex; o[a.n_chains + c] = ey; o[2 * a.n_chains + c] = ez;

@@ -6,8 +6,8 @@
 // Determinism: every sum is taken in a fixed order.  Each thread of a block
 // sums its chains in index order, the block combines its 256 threads by a
 // fixed tree, and the final kernel combines the block partials in block order
-// by another fixed tree.  The histogram is accumulated per wave in LDS, one
-// lane at a time in lane order, and combined in wave order, then block order.
+// by another fixed tree.  The R^2 histogram is summed in fixed point with
+// integer atomics (exact and order-independent), see split_limbs.
 #include "rsaw_device.hpp"
 #include "rsaw_reduce.hpp"
 
@@ -15,12 +15,16 @@
 
 namespace rsaw {
 
-__global__ void reduce_init(unsigned long long *lmax_bits, int32_t *status)
+// Zero the max-log-W cell, the status word and the histogram accumulators.
+__global__ void reduce_init(unsigned long long *lmax_bits, int32_t *status,
+                            unsigned long long *hist_acc, int n_acc)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) {
         *lmax_bits = 0ull;
         *status = 0;
     }
+    for (int q = t; q < n_acc; q += gridDim.x * blockDim.x) hist_acc[q] = 0ull;
 }
 
 constexpr int kRT = 256; // reduce block size (4 waves)
@@ -42,14 +46,32 @@ __device__ __forceinline__ void add_into(ThreadSums &a, const ThreadSums &b)
     a.ex[2] += b.ex[2];
 }
 
+// Histogram weights are accumulated as fixed-point integers: w in [0, 1] is
+// split into three 32-bit limbs (w = l0 2^-32 + l1 2^-64 + l2 2^-96 + t with
+// 0 <= t < 2^-96; each step of the split is exact in binary64).  Integer
+// sums do not depend on the order of the additions, so LDS and global
+// atomics give bit-identical results run to run.  Each limb sum stays below
+// 2^32 M < 2^64.
+__device__ __forceinline__ void split_limbs(double w, uint64_t &l0, uint64_t &l1, uint64_t &l2)
+{
+    double t = w * 0x1p32;
+    const double f0 = floor(t);
+    t = (t - f0) * 0x1p32;
+    const double f1 = floor(t);
+    t = (t - f1) * 0x1p32;
+    const double f2 = floor(t);
+    l0 = (uint64_t)f0;
+    l1 = (uint64_t)f1;
+    l2 = (uint64_t)f2;
+}
+
 __global__ __launch_bounds__(kRT) void reduce_partials(ReduceArgs a)
 {
     extern __shared__ unsigned char smem[];
-    ThreadSums *ts = (ThreadSums *)smem;                            // [kRT]
-    double *hw = (double *)(smem + sizeof(ThreadSums) * kRT);      // [4][bins]
-    uint64_t *hn = (uint64_t *)(hw + 4 * a.bins);                   // [4][bins]
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    for (int q = tid; q < 4 * a.bins; q += kRT) { hw[q] = 0.0; hn[q] = 0; }
+    ThreadSums *ts = (ThreadSums *)smem;                                   // [kRT]
+    unsigned long long *hacc = (unsigned long long *)(smem + sizeof(ThreadSums) * kRT); // [4][bins]
+    const int tid = threadIdx.x;
+    for (int q = tid; q < 4 * a.bins; q += kRT) hacc[q] = 0ull;
     __syncthreads();
 
     const double L = __longlong_as_double((long long)*a.lmax_bits);
@@ -63,54 +85,38 @@ __global__ __launch_bounds__(kRT) void reduce_partials(ReduceArgs a)
     for (int q = 0; q < kNumSums; ++q) my.s[q] = 0.0;
     my.alive = 0; my.steps = 0; my.ex[0] = 0; my.ex[1] = 0; my.ex[2] = 0;
 
-    for (uint64_t base = begin; base < end; base += kRT) {
-        const uint64_t q = base + tid;
-        const bool ok = q < end;
-        double w = 0.0, A = 0.0;
-        bool live = false;
-        if (ok) {
-            const double lw = a.log_w[q];
-            my.steps += (uint64_t)a.n_grown[q] - 1u;
-            live = lw > -__builtin_huge_val();
-            if (live) {
-                w = exp(lw - L);
-                A = a.r2[q];
-                const double G = a.rg2[q];
-                const double ww = w * w;
-                my.alive += 1;
-                my.s[0] = my.s[0] + w;
-                my.s[1] = my.s[1] + ww;
-                my.s[2] = my.s[2] + w * A;
-                my.s[3] = my.s[3] + ww * A;
-                my.s[4] = my.s[4] + ww * A * A;
-                my.s[5] = my.s[5] + w * G;
-                my.s[6] = my.s[6] + ww * G;
-                my.s[7] = my.s[7] + ww * G * G;
-                if (a.exact) {
-                    const unsigned __int128 W = a.w_exact[q];
-                    my.ex[0] += W;
-                    my.ex[1] += W * (unsigned __int128)(uint64_t)A;
-                    my.ex[2] += W * (unsigned __int128)(uint64_t)a.n2rg2[q];
-                }
-            }
+    for (uint64_t q = begin + tid; q < end; q += kRT) {
+        const double lw = a.log_w[q];
+        my.steps += (uint64_t)a.n_grown[q] - 1u;
+        if (!(lw > -__builtin_huge_val())) continue;
+        const double w = exp(lw - L);
+        const double A = a.r2[q];
+        const double G = a.rg2[q];
+        const double ww = w * w;
+        my.alive += 1;
+        my.s[0] = my.s[0] + w;
+        my.s[1] = my.s[1] + ww;
+        my.s[2] = my.s[2] + w * A;
+        my.s[3] = my.s[3] + ww * A;
+        my.s[4] = my.s[4] + ww * A * A;
+        my.s[5] = my.s[5] + w * G;
+        my.s[6] = my.s[6] + ww * G;
+        my.s[7] = my.s[7] + ww * G * G;
+        if (a.exact) {
+            const unsigned __int128 W = a.w_exact[q];
+            my.ex[0] += W;
+            my.ex[1] += W * (unsigned __int128)(uint64_t)A;
+            my.ex[2] += W * (unsigned __int128)(uint64_t)a.n2rg2[q];
         }
         if (a.bins > 0) {
-            int bin = 0;
-            if (live) {
-                const double fb = floor((A * (double)a.bins) / nsq1);
-                bin = fb < 0.0 ? 0 : (fb >= (double)a.bins ? a.bins - 1 : (int)fb);
-            }
-            double *hwv = hw + wave * a.bins;
-            uint64_t *hnv = hn + wave * a.bins;
-            for (int l = 0; l < 64; ++l) {
-                if (lane == l && live) {
-                    hwv[bin] = hwv[bin] + w;
-                    hnv[bin] = hnv[bin] + 1;
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            }
+            const double fb = floor((A * (double)a.bins) / nsq1);
+            const int bin = fb < 0.0 ? 0 : (fb >= (double)a.bins ? a.bins - 1 : (int)fb);
+            uint64_t l0, l1, l2;
+            split_limbs(w, l0, l1, l2);
+            atomicAdd(&hacc[bin], (unsigned long long)l0);
+            atomicAdd(&hacc[a.bins + bin], (unsigned long long)l1);
+            atomicAdd(&hacc[2 * a.bins + bin], (unsigned long long)l2);
+            atomicAdd(&hacc[3 * a.bins + bin], 1ull);
         }
     }
 
@@ -130,15 +136,9 @@ __global__ __launch_bounds__(kRT) void reduce_partials(ReduceArgs a)
             bp.ex[2 * q + 1] = (uint64_t)(ts[0].ex[q] >> 64);
         }
     }
-    for (int bi = tid; bi < a.bins; bi += kRT) {
-        double sw = hw[bi];
-        uint64_t sn = hn[bi];
-        for (int w = 1; w < 4; ++w) {
-            sw = sw + hw[w * a.bins + bi];
-            sn += hn[w * a.bins + bi];
-        }
-        a.part_hist_w[(size_t)blockIdx.x * a.bins + bi] = sw;
-        a.part_hist_n[(size_t)blockIdx.x * a.bins + bi] = sn;
+    for (int q = tid; q < 4 * a.bins; q += kRT) {
+        const unsigned long long v = hacc[q];
+        if (v) atomicAdd(&a.hist_acc[q], v);
     }
 }
 
@@ -203,20 +203,17 @@ __global__ __launch_bounds__(kRT) void reduce_final(ReduceArgs a, uint32_t n_blo
         out->status = *a.status;
     }
     for (int bi = tid; bi < a.bins; bi += kRT) {
-        double sw = 0.0;
-        uint64_t sn = 0;
-        for (uint32_t b = 0; b < n_blocks; ++b) {
-            sw = sw + a.part_hist_w[(size_t)b * a.bins + bi];
-            sn += a.part_hist_n[(size_t)b * a.bins + bi];
-        }
+        const unsigned long long *h = a.hist_acc;
+        const double sw = (double)h[bi] * 0x1p-32 + (double)h[a.bins + bi] * 0x1p-64 +
+                          (double)h[2 * a.bins + bi] * 0x1p-96;
         if (hist_w) hist_w[bi] = sw;
-        if (hist_n) hist_n[bi] = sn;
+        if (hist_n) hist_n[bi] = h[3 * a.bins + bi];
     }
 }
 
 size_t reduce_partials_shmem(int bins)
 {
-    return sizeof(ThreadSums) * kRT + (size_t)4 * bins * (sizeof(double) + sizeof(uint64_t));
+    return sizeof(ThreadSums) * kRT + (size_t)4 * bins * sizeof(unsigned long long);
 }
 
 hipError_t launch_reduce(const ReduceArgs &a, uint32_t n_blocks, rsaw_summary *out,
@@ -231,9 +228,10 @@ hipError_t launch_reduce(const ReduceArgs &a, uint32_t n_blocks, rsaw_summary *o
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_init(unsigned long long *lmax_bits, int32_t *status, hipStream_t s)
+hipError_t launch_reduce_init(unsigned long long *lmax_bits, int32_t *status,
+                              unsigned long long *hist_acc, int n_acc, hipStream_t s)
 {
-    hipLaunchKernelGGL(reduce_init, dim3(1), dim3(64), 0, s, lmax_bits, status);
+    hipLaunchKernelGGL(reduce_init, dim3(4), dim3(256), 0, s, lmax_bits, status, hist_acc, n_acc);
     return hipGetLastError();
 }
 

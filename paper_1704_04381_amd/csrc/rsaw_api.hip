@@ -158,8 +158,7 @@ rsaw_status gen_impl(const rsaw_config *cfg, const rsaw_chain_out *out, rsaw_sum
     const size_t off_status = off; off = align256(off + sizeof(int32_t));
     const size_t off_summary = off; off = align256(off + sizeof(rsaw_summary));
     const size_t off_part = off; off = align256(off + (size_t)n_blocks * sizeof(rsaw::BlockPartial));
-    const size_t off_hw = off; off = align256(off + (size_t)n_blocks * bins * sizeof(double));
-    const size_t off_hn = off; off = align256(off + (size_t)n_blocks * bins * sizeof(uint64_t));
+    const size_t off_hacc = off; off = align256(off + (size_t)4 * bins * sizeof(unsigned long long));
     const bool need_lw = reduce && !o.log_w, need_r2 = reduce && !o.r2, need_rg2 = reduce && !o.rg2,
                need_ng = reduce && !o.n_grown, need_wx = reduce && exact && !o.w_exact,
                need_nn = reduce && exact && lattice && !o.n2rg2;
@@ -186,7 +185,8 @@ rsaw_status gen_impl(const rsaw_config *cfg, const rsaw_chain_out *out, rsaw_sum
     unsigned long long *lmax = (unsigned long long *)(ws + off_lmax);
     int32_t *status = (int32_t *)(ws + off_status);
 
-    e = rsaw::launch_reduce_init(lmax, status, s);
+    unsigned long long *hacc = (unsigned long long *)(ws + off_hacc);
+    e = rsaw::launch_reduce_init(lmax, status, hacc, 4 * bins, s);
     if (e != hipSuccess) return hip_fail(e, "reduce_init launch");
 
     if (M > 0) {
@@ -231,8 +231,7 @@ rsaw_status gen_impl(const rsaw_config *cfg, const rsaw_chain_out *out, rsaw_sum
         r.lmax_bits = lmax;
         r.status = status;
         r.partials = (rsaw::BlockPartial *)(ws + off_part);
-        r.part_hist_w = (double *)(ws + off_hw);
-        r.part_hist_n = (uint64_t *)(ws + off_hn);
+        r.hist_acc = hacc;
         rsaw_summary *dsum = d_summary ? d_summary : (rsaw_summary *)(ws + off_summary);
         e = rsaw::launch_reduce(r, n_blocks, dsum, d_hist_w, d_hist_n, s);
         if (e != hipSuccess) return hip_fail(e, "reduce kernel launch");

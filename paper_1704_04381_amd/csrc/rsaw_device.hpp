@@ -4,8 +4,8 @@
 // Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) keyed by
 // the 64-bit seed; the counter is (lo32(g), hi32(g), c2, slot << 16 | attempt)
 // with g the global chain index.  Word use per growth step i:
-//   slot 0xFFFF, c2 = i >> 2      : primary selection word i & 3 (both geometries)
-//   slot 0xFFFE, c2 = i, attempt a: redraw words of Lemire's rejection
+//   slot 0xFFFF, c2 = i >> 3      : primary 16-bit selection word, half i & 7
+//   slot 0xFFFE, c2 = i, attempt a: redraw half-words of Lemire's rejection
 //   slot t < 64, c2 = i, attempt a: real-space trial t, Marsaglia attempt a
 #pragma once
 
@@ -54,21 +54,29 @@ __device__ __forceinline__ uint32_t word(const Philox4 &b, uint32_t w)
     return w == 0 ? b.x0 : (w == 1 ? b.x1 : (w == 2 ? b.x2 : b.x3));
 }
 
-// Lemire's rejection after a primary word x gave lo32(x m) below 2^32 mod m:
-// continue with the redraw words of step `step`.  Returns the index in [0, m)
-// or sets *fail when the attempt cap is reached.
-__device__ __noinline__ uint32_t lemire_redraw(uint64_t seed, uint64_t g, uint32_t step,
-                                               uint32_t m, uint32_t x, bool *fail)
+// 16-bit half h (0..7) of a block: word h / 2, low half for even h.
+__device__ __forceinline__ uint32_t half_word(const Philox4 &b, uint32_t h)
 {
-    const uint32_t threshold = (uint32_t)((uint64_t)0x100000000ull % m);
-    uint64_t p = (uint64_t)x * m;
-    if ((uint32_t)p >= threshold) return (uint32_t)(p >> 32);
+    const uint32_t w = word(b, h >> 1);
+    return (h & 1u) ? (w >> 16) : (w & 0xFFFFu);
+}
+
+// Lemire's method on 16-bit words, slow path: the primary word x of step
+// `step` is accepted when (x m) mod 2^16 >= 2^16 mod m, else the eight
+// halves of each redraw block (slot 0xFFFE, attempt 0, 1, ...) are tried in
+// order.  Returns (x m) / 2^16 of the accepted word, or sets *fail at the
+// attempt cap.  m >= 1.
+__device__ __noinline__ uint32_t lemire_redraw16(uint64_t seed, uint64_t g, uint32_t step,
+                                                 uint32_t m, uint32_t x, bool *fail)
+{
+    const uint32_t threshold = 65536u % m;
+    uint32_t p = x * m;
+    if ((p & 0xFFFFu) >= threshold) return p >> 16;
     for (uint32_t a = 0; a < kMaxAttempt; ++a) {
         const Philox4 b = draw(seed, g, step, kSlotRedraw, a);
-        const uint32_t ws[4] = {b.x0, b.x1, b.x2, b.x3};
-        for (int w = 0; w < 4; ++w) {
-            p = (uint64_t)ws[w] * m;
-            if ((uint32_t)p >= threshold) return (uint32_t)(p >> 32);
+        for (uint32_t h = 0; h < 8; ++h) {
+            p = half_word(b, h) * m;
+            if ((p & 0xFFFFu) >= threshold) return p >> 16;
         }
     }
     *fail = true;

@@ -32,11 +32,11 @@ struct ReduceArgs {
     const unsigned long long *lmax_bits;
     const int32_t *status;
     BlockPartial *partials;
-    double *part_hist_w;
-    uint64_t *part_hist_n;
+    unsigned long long *hist_acc; // [4][bins]: limbs 0, 1, 2 of sum w, and counts
 };
 
-hipError_t launch_reduce_init(unsigned long long *lmax_bits, int32_t *status, hipStream_t s);
+hipError_t launch_reduce_init(unsigned long long *lmax_bits, int32_t *status,
+                              unsigned long long *hist_acc, int n_acc, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs &a, uint32_t n_blocks, rsaw_summary *out,
                          double *hist_w, uint64_t *hist_n, hipStream_t s);
 

@@ -89,10 +89,8 @@ def test_ideal_chain_sigma_zero(N, k, b):
     o = oracle.gen_real(17, N, k, M, b=b, sigma=0.0)
     n = N - 1
     assert np.all(o["n_grown"] == N)
-    lw_seq = 0.0
-    for _ in range(n):
-        lw_seq = lw_seq + math.log(k)
-    assert np.all(o["log_w"] == lw_seq)
+    # log W = n_k log k: one product, rounded once (the count-based rule)
+    assert np.all(o["log_w"] == float(n) * math.log(k))
     for A, exact in ((o["r2"], n * b * b), (o["rg2"], b * b * (N * N - 1) / (6 * N))):
         se = A.std() / math.sqrt(M)
         assert abs(A.mean() - exact) < 5 * se, (A.mean(), exact, se)
