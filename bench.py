@@ -28,6 +28,33 @@ if REPO not in sys.path:
 # full-rate 32-bit integer or binary64 add/mul per lane per clock).
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(REPO, "profiles", "grow_traffic.json")
+CSRC = os.path.join(REPO, "paper_1704_04381_amd", "csrc")
+
+
+def kernel_source_hash(kernel_file: str) -> str:
+    """SHA-256 of one kernel source plus the shared device header."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in (kernel_file, "rsaw_device.hpp"):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, kernel_file: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, scaled by the copy-kernel
+    calibration; None when no summary exists or the kernel source changed
+    since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)[workload]
+    except (OSError, KeyError, ValueError):
+        return None
+    if rec.get("kernel") != kernel or rec.get("source_sha256") != kernel_source_hash(kernel_file):
+        return None
+    return rec["bytes_per_launch"]
 
 
 def lattice_alg_ops_per_chain(N: int) -> int:
@@ -35,11 +62,12 @@ def lattice_alg_ops_per_chain(N: int) -> int:
 
     Per step i: the pair tests against the monomers that can neighbour the
     tip (floor(i/2) of them on the bipartite cubic lattice), 4 operations
-    each (L1 distance, neighbour flag, direction code, mask insert); a
-    quarter of one Philox4x32-10 block (10 rounds x 6 operations / 4); and
-    10 operations to count, pick and apply the move and add log m_i.
+    each (L1 distance, neighbour flag, direction code, mask insert); one
+    eighth of a Philox4x32-10 block, the 16 bits the pick consumes (10
+    rounds x 6 operations / 8, rounded up to 8); and 10 operations to
+    count, pick and apply the move and tally m_i for log W.
     """
-    return sum(4 * (i // 2) + 15 + 10 for i in range(1, N))
+    return sum(4 * (i // 2) + 8 + 10 for i in range(1, N))
 
 
 def real_alg_ops_per_chain(N: int, k: int) -> float:
@@ -67,7 +95,7 @@ def _percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (pos - lo)
 
 
-def run_gpu(w, steps, warmup, torch, rs, profile_kernel=True):
+def run_gpu(w, steps, warmup, torch, rs):
     dev = torch.device("cuda", 0)
     M, N = w["n_chains"], w["N"]
     cfg = rs.make_config(w["geometry"], N, w["k"], M, w["seed"], coord=w["coord"],
@@ -102,6 +130,10 @@ def run_gpu(w, steps, warmup, torch, rs, profile_kernel=True):
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(steps)]
     torch.cuda.synchronize()
+    # The library brackets each growth-kernel launch with HIP events on the
+    # stream it launches on; read back after the timed region.
+    rs.kernel_time()
+    rs.kernel_timing(True)
     t0 = time.perf_counter()
     for a, b in ev:
         a.record(stream)
@@ -109,24 +141,16 @@ def run_gpu(w, steps, warmup, torch, rs, profile_kernel=True):
         b.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    rs.kernel_timing(False)
+    k_ms, k_n = rs.kernel_time()
+    if k_n != steps:
+        raise RuntimeError(f"timed {k_n} growth launches, expected {steps}")
     lat = [a.elapsed_time(b) for a, b in ev]
     summary = rs.parse_summary(summ)
     if summary["status"] != 0:
         raise RuntimeError(f"device status {summary['status']}")
 
-    grow_ms = None
-    if profile_kernel:
-        # The growth kernel alone (plus a one-thread init kernel), bracketed by
-        # events on the stream it is launched on.
-        ge = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(steps)]
-        for a, b in ge:
-            a.record(stream)
-            rs.gen_chains_raw(cfg, o, 0, 0, 0, sh)
-            b.record(stream)
-        torch.cuda.synchronize()
-        grow_ms = sum(a.elapsed_time(b) for a, b in ge) / len(ge)
-    return dict(wall=wall, lat=lat, summary=summary, grow_ms=grow_ms)
+    return dict(wall=wall, lat=lat, summary=summary, grow_ms=k_ms / k_n)
 
 
 def cpu_baseline(w, sample_chains, threads):
@@ -227,7 +251,10 @@ def main():
                    "n_chains": M, "seed": w["seed"], "coord": w["coord"],
                    "hist_bins": w["hist_bins"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
-                     "unit": "Tops/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                     "unit": "Tops/s", "frac": achieved / VALU_PEAK_TOPS,
+                     "traffic": (measured_traffic("grow_lattice_reg", "grow_lattice.hip", args.workload)
+                                 if w["geometry"] == "lattice" else
+                                 measured_traffic("grow_real_tp", "grow_real.hip", args.workload)),
                      "kernel": "grow_lattice_reg" if w["geometry"] == "lattice" else "grow_real_tp",
                      "kernel_ms": r["grow_ms"], "alg_ops_per_launch": alg_ops},
         "physics": {k: r["summary"][k] for k in ("n_alive", "log_c_est", "r2_mean", "r2_err",
@@ -253,7 +280,7 @@ def main():
         }
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
-        sample = args.cpu_sample or (320_000 if w["geometry"] == "lattice" else 40_000)
+        sample = args.cpu_sample or (1_000_000 if w["geometry"] == "lattice" else 300_000)
         line["cpu_baseline"] = cpu_baseline(w, sample, threads)
     print(json.dumps(line), flush=True)
 

@@ -175,8 +175,27 @@ const char *rsaw_last_error(void);
 /* Library version as an integer: major * 10000 + minor * 100 + patch. */
 int32_t rsaw_version(void);
 
-/* Release the internal device workspace of every device (safe to call
- * repeatedly; later calls re-create it on demand). */
+/*
+ * rsaw_kernel_timing — per-launch timing of the growth kernel, for
+ * benchmarking (off by default).  While enabled (enable != 0), every
+ * rsaw_gen_chains / rsaw_gen_chains_sync call that grows chains records a
+ * HIP event right before and right after its growth-kernel launch, on the
+ * call's stream.  Disabling keeps the pairs already recorded.
+ * Returns RSAW_OK.
+ */
+rsaw_status rsaw_kernel_timing(int32_t enable);
+
+/*
+ * rsaw_kernel_time — waits for every event pair recorded since the last
+ * call, writes their summed elapsed time in milliseconds to *total_ms and
+ * their number to *launches (host pointers, either may be NULL), and
+ * forgets them.  RSAW_E_DEVICE if a HIP event call fails (the pairs are
+ * forgotten all the same).
+ */
+rsaw_status rsaw_kernel_time(double *total_ms, uint64_t *launches);
+
+/* Release the internal device workspace of every device and the timing
+ * events (safe to call repeatedly; later calls re-create them on demand). */
 void rsaw_shutdown(void);
 
 #ifdef __cplusplus

@@ -57,7 +57,8 @@ SUMMARY_BYTES = C.sizeof(rsaw_summary)
 
 # Every symbol include/rsaw.h declares.
 EXPORTS = ["rsaw_gen_chains", "rsaw_gen_chains_sync", "rsaw_status_string",
-           "rsaw_last_error", "rsaw_version", "rsaw_shutdown"]
+           "rsaw_last_error", "rsaw_version", "rsaw_kernel_timing", "rsaw_kernel_time",
+           "rsaw_shutdown"]
 
 _lib = None
 _lock = threading.Lock()
@@ -92,6 +93,10 @@ def load(path: str = LIB_PATH):
         lib.rsaw_last_error.restype = C.c_char_p
         lib.rsaw_version.argtypes = []
         lib.rsaw_version.restype = C.c_int32
+        lib.rsaw_kernel_timing.argtypes = [C.c_int32]
+        lib.rsaw_kernel_timing.restype = C.c_int
+        lib.rsaw_kernel_time.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
+        lib.rsaw_kernel_time.restype = C.c_int
         lib.rsaw_shutdown.argtypes = []
         lib.rsaw_shutdown.restype = None
         _lib = lib
@@ -198,6 +203,19 @@ def gen_chains(geometry, N, k, n_chains, seed, *, coord=None, chain_offset=0,
 
 def version() -> int:
     return int(load().rsaw_version())
+
+
+def kernel_timing(enable: bool) -> None:
+    """Switch growth-kernel event timing on or off (rsaw_kernel_timing)."""
+    _check(load().rsaw_kernel_timing(1 if enable else 0))
+
+
+def kernel_time() -> tuple[float, int]:
+    """(summed ms, launches) of the growth kernels timed since the last read."""
+    ms = C.c_double(0.0)
+    n = C.c_uint64(0)
+    _check(load().rsaw_kernel_time(C.byref(ms), C.byref(n)))
+    return ms.value, n.value
 
 
 def shutdown():

@@ -10,6 +10,7 @@
 #include <mutex>
 #include <string>
 #include <utility>
+#include <vector>
 
 #include "rsaw.h"
 #include "rsaw_device.hpp"
@@ -68,6 +69,56 @@ rsaw_status workspace(int dev, hipStream_t s, size_t need, void **out)
         w.bytes = sz;
     }
     *out = w.base;
+    return RSAW_OK;
+}
+
+// Growth-kernel timing: event pairs recorded around launches while enabled.
+struct EventPair {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
+std::mutex g_tm_lock;
+bool g_tm_enabled = false;
+std::vector<EventPair> g_tm_recorded, g_tm_free;
+
+// Record the start event of a timed launch; false (and no pair) when timing is off.
+rsaw_status timing_start(hipStream_t s, EventPair *pair, bool *timed)
+{
+    std::lock_guard<std::mutex> lk(g_tm_lock);
+    *timed = false;
+    if (!g_tm_enabled) return RSAW_OK;
+    EventPair p;
+    if (!g_tm_free.empty()) {
+        p = g_tm_free.back();
+        g_tm_free.pop_back();
+    } else {
+        hipError_t e = hipEventCreate(&p.start);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+        e = hipEventCreate(&p.stop);
+        if (e != hipSuccess) {
+            (void)hipEventDestroy(p.start);
+            return hip_fail(e, "hipEventCreate");
+        }
+    }
+    hipError_t e = hipEventRecord(p.start, s);
+    if (e != hipSuccess) {
+        g_tm_free.push_back(p);
+        return hip_fail(e, "hipEventRecord");
+    }
+    *pair = p;
+    *timed = true;
+    return RSAW_OK;
+}
+
+rsaw_status timing_stop(hipStream_t s, const EventPair &p)
+{
+    std::lock_guard<std::mutex> lk(g_tm_lock);
+    hipError_t e = hipEventRecord(p.stop, s);
+    if (e != hipSuccess) {
+        g_tm_free.push_back(p);
+        return hip_fail(e, "hipEventRecord");
+    }
+    g_tm_recorded.push_back(p);
     return RSAW_OK;
 }
 
@@ -199,6 +250,10 @@ rsaw_status gen_impl(const rsaw_config *cfg, const rsaw_chain_out *out, rsaw_sum
         a.k_trials = cfg->k_trials;
         a.bond_length = cfg->bond_length;
         a.sigma2 = cfg->bead_diameter * cfg->bead_diameter;
+        {
+            const double bs = cfg->bond_length + cfg->bead_diameter;
+            a.cull2 = bs * bs * (1.0 + 0x1p-30);
+        }
         a.log_w = o.log_w;
         a.w_exact = o.w_exact;
         a.r_end = o.r_end;
@@ -209,8 +264,16 @@ rsaw_status gen_impl(const rsaw_config *cfg, const rsaw_chain_out *out, rsaw_sum
         a.log_w_max_bits = lmax;
         a.status = status;
         std::memcpy(a.logm, logm_table(), sizeof(a.logm));
+        EventPair tp;
+        bool timed = false;
+        st = timing_start(s, &tp, &timed);
+        if (st != RSAW_OK) return st;
         e = lattice ? rsaw::launch_grow_lattice(a, exact, cfg->coord_type == RSAW_I16, s)
                     : rsaw::launch_grow_real(a, s);
+        if (timed) {
+            st = timing_stop(s, tp);
+            if (st != RSAW_OK) return st;
+        }
         if (e != hipSuccess) return hip_fail(e, "grow kernel launch");
     }
 
@@ -287,8 +350,49 @@ const char *rsaw_last_error(void) { return g_last_error.c_str(); }
 
 int32_t rsaw_version(void) { return 100; }
 
+rsaw_status rsaw_kernel_timing(int32_t enable)
+{
+    g_last_error.clear();
+    std::lock_guard<std::mutex> lk(g_tm_lock);
+    g_tm_enabled = enable != 0;
+    return RSAW_OK;
+}
+
+rsaw_status rsaw_kernel_time(double *total_ms, uint64_t *launches)
+{
+    g_last_error.clear();
+    std::lock_guard<std::mutex> lk(g_tm_lock);
+    double sum = 0.0;
+    uint64_t n = 0;
+    rsaw_status st = RSAW_OK;
+    for (const EventPair &p : g_tm_recorded) {
+        float ms = 0.0f;
+        hipError_t e = hipEventSynchronize(p.stop);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, p.start, p.stop);
+        if (e != hipSuccess && st == RSAW_OK) st = hip_fail(e, "kernel timing event");
+        sum += ms;
+        ++n;
+        g_tm_free.push_back(p);
+    }
+    g_tm_recorded.clear();
+    if (total_ms) *total_ms = sum;
+    if (launches) *launches = n;
+    return st;
+}
+
 void rsaw_shutdown(void)
 {
+    {
+        std::lock_guard<std::mutex> lk(g_tm_lock);
+        for (auto *v : {&g_tm_recorded, &g_tm_free}) {
+            for (const EventPair &p : *v) {
+                (void)hipEventSynchronize(p.stop);
+                (void)hipEventDestroy(p.start);
+                (void)hipEventDestroy(p.stop);
+            }
+            v->clear();
+        }
+    }
     std::lock_guard<std::mutex> lk(g_ws_lock);
     for (auto &kv : g_ws) {
         if (kv.second.base) {

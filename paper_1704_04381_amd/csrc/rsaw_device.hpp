@@ -105,6 +105,8 @@ struct GrowArgs {
     int32_t k_trials;
     double bond_length;
     double sigma2;
+    double cull2; // (b + sigma)^2 (1 + 2^-30): beads at or beyond it cannot overlap
+    int32_t lds_row; // real space: row stride of the LDS bead planes, set by the launcher
     // per-chain outputs (device, any may be null)
     double *log_w;
     uint64_t *w_exact;

@@ -79,6 +79,14 @@ def test_null_arguments():
     assert lib.rsaw_status_string(99).decode() == "unknown status"
 
 
+def test_kernel_timing_switch_without_launches():
+    lib = _lib()
+    assert lib.rsaw_kernel_timing(1) == 0
+    assert rs.kernel_time() == (0.0, 0)
+    assert lib.rsaw_kernel_timing(0) == 0
+    assert lib.rsaw_kernel_time(None, None) == 0
+
+
 def test_no_cpu_fallback_without_gpu():
     torch = pytest.importorskip("torch")
     if torch.cuda.is_available():

@@ -177,6 +177,21 @@ def test_split_ranges_equal_one_launch_and_determinism():
         np.testing.assert_array_equal(ra[key], rb[key])
 
 
+def test_kernel_timing_counts_growth_launches():
+    rs.kernel_time()
+    rs.kernel_timing(True)
+    try:
+        _gpu("lattice", 64, 6, 50_000, 3, coord="i16")
+        _gpu("real", 24, 8, 2_000, 3)
+        _gpu("lattice", 16, 6, 0, 3)  # empty: no growth launch, no pair
+    finally:
+        rs.kernel_timing(False)
+    ms, n = rs.kernel_time()
+    assert n == 2 and 0.0 < ms < 10_000.0
+    _gpu("lattice", 16, 6, 1_000, 3)  # timing off: nothing recorded
+    assert rs.kernel_time() == (0.0, 0)
+
+
 def _sampled_indices(M, n, seed):
     rng = np.random.default_rng(seed)
     idx = np.unique(np.concatenate([np.arange(0, M, max(1, M // n)), rng.integers(0, M, n),
