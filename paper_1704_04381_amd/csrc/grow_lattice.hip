@@ -116,8 +116,13 @@ __global__ __launch_bounds__(256) void grow_lattice_reg(GrowArgs a)
         const uint32_t x = (h & 1) ? (wd >> 16) : (wd & 0xFFFFu);
         const uint32_t p = x * m;
         uint32_t r = p >> 16;
-        if (__builtin_expect(alive && (p & 0xFFFFu) < m, 0))
-            r = lemire_redraw16(a.seed, g, (uint32_t)i, m, x, &rng_fail);
+        if (__builtin_expect(alive && (p & 0xFFFFu) < m, 0)) {
+            r = lemire_redraw16(a.seed, g, (uint32_t)i, m, x);
+            if (r == kPickFailed) {
+                rng_fail = true;
+                r = 0;
+            }
+        }
 
         const bool step_ok = alive && m != 0;
         const uint32_t mv = lut[(freem << 3) | (r & 7u)];

@@ -1,51 +1,122 @@
 // Hard-sphere chain growth in continuous space (Sec. 3.3.3, Algorithm 2;
 // weight of Eq. 3).  Trial-parallel mapping: a group of G lanes (G = 8 or the
 // next power of two >= k) serves one chain, lane t of the group owns trial t.
-// Bead coordinates (binary64) live in LDS as [bead][chain of block][xyz], so
-// the 8 chains of a wave read 8 consecutive 24-byte records per bead.
+// Bead coordinates (binary64) live in LDS as three planes X, Y, Z, each laid
+// out [bead][chain of block] with an XOR swizzle of the chain index (see
+// plane_row).
 //
 // Per step i:
-//   1. lane t draws its Marsaglia direction (Philox slot t, first accepted
-//      attempt) and forms the candidate tip + b e;
-//   2. it tests the candidate against beads 0 .. i-2 of its chain:
-//      ((dx dx + dy dy) + dz dz) < sigma^2 means overlap (no contraction);
-//   3. a ballot over the group gives the free mask; m = popcount;
-//   4. Lemire's pick (16-bit word from the 8-step selection block) chooses
+//   1. lane t obtains the Marsaglia direction of trial t (Philox slot t, the
+//      first accepted attempt; attempts 0 and 1 are always drawn) and forms
+//      the candidate c_t = tip + b e;
+//   2. culling: beads i-2 and i-3 are always tested; the G lanes of the
+//      chain split beads 0 .. i-4 (lane t takes every G-th bead) and flag
+//      those whose squared tip distance is below (b + sigma)^2 (1 + 2^-30);
+//      every other bead is farther than sigma from every candidate (see
+//      below), so it cannot overlap;
+//   3. each lane tests its candidate against beads i-2, i-3 and the flagged
+//      beads: ((dx dx + dy dy) + dz dz) < sigma^2 means overlap (no
+//      contraction).  The flag offsets are merged over the wave so that the
+//      loop is uniform; re-testing a culled bead is harmless;
+//   4. a ballot over the group gives the free mask; m = popcount;
+//   5. Lemire's pick (16-bit word from the 8-step selection block) chooses
 //      the r-th free trial; its candidate is broadcast with a lane shuffle and
 //      written to LDS as bead i by its owner;
-//   5. lane m - 1 of the group counts the steps with m free trials, and
+//   6. lane m - 1 of the group counts the steps with m free trials, and
 //      log W = sum_m n_m log m is formed once after the last step.
-// The final observables (two-pass Rg^2, R^2) are computed by lane 0 of each
-// group in bead order, exactly as the definitions read.
+//
+// Culling is exact, not an approximation.  A bead is dropped only when the
+// computed D^2 = ((dx dx + dy dy) + dz dz), dx = x_j - tip_x, is at least
+// T = (b + sigma)^2 (1 + 2^-30).  Each binary64 operation errs by at most
+// 2^-53 relative and all terms are non-negative, so the exact tip distance
+// is D >= (b + sigma)(1 + 2^-32).  The candidate lies within b (1 + 2^-49)
+// + 2^-44 |tip| of the tip (rounding of e, b e and tip + b e), so its exact
+// distance to the bead exceeds sigma + (b + sigma) 2^-32 - b 2^-49 - 2^-44 |tip|,
+// which for |tip| <= 255 b is at least sigma (1 + 2^-33); its computed d^2 is
+// then >= sigma^2 (1 + 2^-33)^2 (1 - 2^-50) > sigma^2: the full test would
+// also have found it free.
 #include "rsaw_device.hpp"
 
 namespace rsaw {
 
+// One Marsaglia attempt from a Philox block: two 53-bit uniforms on [-1, 1)
+// and acceptance of the pair strictly inside the unit disc, off its centre.
+__device__ __forceinline__ bool marsaglia_try(const Philox4 q, double &v1, double &v2, double &s)
+{
+    const int64_t j1 = ((int64_t)(q.x0 >> 5) << 26) + (int64_t)(q.x1 >> 6);
+    const int64_t j2 = ((int64_t)(q.x2 >> 5) << 26) + (int64_t)(q.x3 >> 6);
+    const double u1 = (double)(j1 - (1ll << 52)) * 0x1p-52;
+    const double u2 = (double)(j2 - (1ll << 52)) * 0x1p-52;
+    const double ss = u1 * u1 + u2 * u2;
+    if (ss < 1.0 && ss != 0.0) {
+        v1 = u1; v2 = u2; s = ss;
+        return true;
+    }
+    return false;
+}
+
+// OR of the G-bit groups of a wave-wide ballot: bit q is set when lane q of
+// any group of G lanes had its predicate set.
+template <int G>
+__device__ __forceinline__ uint64_t fold_groups(uint64_t v)
+{
+#pragma unroll
+    for (int sh = 32; sh >= G; sh >>= 1) v |= v >> sh;
+    return G == 64 ? v : (v & ((1ull << G) - 1ull));
+}
+
+// Orders LDS accesses of the lanes of one wave.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Row length (in doubles) of the bead planes for cpb chains per block.
+// Bead j of chain c sits at j row + (c ^ ((j H) mod cpb)), H = 32 / G.  A
+// wave reads binary64 words half a wave at a time over 64 four-byte banks;
+// the culling pass has lane t of chain c read bead b0 + t (b0 a multiple of
+// G), and with cpb = 32 (G = 8, 256 threads) the 32 (t, c) pairs of a half
+// wave then fall on distinct bank pairs, as do the other accesses, where
+// all chains of a wave read the same bead index.  Smaller cpb leaves at
+// most 2-way conflicts.  G = 64 (one chain per wave, t < 32 per half wave)
+// uses an odd row and no swizzle instead.
+__host__ __device__ inline int plane_row(int cpb, int G) { return G == 64 ? (cpb | 1) : cpb; }
+
 template <int G>
 __global__ __launch_bounds__(256) void grow_real_tp(GrowArgs a)
 {
-    extern __shared__ double beads[]; // [N][cpb][3]
+    extern __shared__ double lds[]; // X, Y, Z planes of [N][row], swizzled
     __shared__ double logm[65];
     for (int t = threadIdx.x; t < 65; t += blockDim.x) logm[t] = a.logm[t];
 
     const int cpb = blockDim.x / G;
+    const int row = plane_row(cpb, G);
+    const int swz_mul = G == 64 ? 0 : 32 / G;
+    const int swz_mask = cpb - 1;
+    const int N = a.n_monomers;
+    double *X = lds;
+    double *Y = lds + (size_t)N * row;
+    double *Z = lds + (size_t)2 * N * row;
     const int t = threadIdx.x & (G - 1);
     const int chb = threadIdx.x / G;
     const int lane = threadIdx.x & 63;
     const int gbase = lane & ~(G - 1);
+    // element of bead j of this chain in a plane
+    const auto at = [&](int j) { return j * row + (chb ^ ((j * swz_mul) & swz_mask)); };
     const uint64_t gmask_bits = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
     const uint64_t c = (uint64_t)blockIdx.x * cpb + chb;
     const bool valid = c < a.n_chains;
     const uint64_t g = a.chain_offset + c;
-    const int N = a.n_monomers;
     const int k = a.k_trials;
     const bool has_trial = t < k;
     const double b = a.bond_length;
     const double sigma2 = a.sigma2;
+    const double cull2 = a.cull2;
 
     if (t == 0) {
-        double *r0 = &beads[(size_t)chb * 3];
-        r0[0] = 0.0; r0[1] = 0.0; r0[2] = 0.0;
+        X[at(0)] = 0.0; Y[at(0)] = 0.0; Z[at(0)] = 0.0;
     }
     __syncthreads();
 
@@ -57,51 +128,91 @@ __global__ __launch_bounds__(256) void grow_real_tp(GrowArgs a)
     Philox4 sel{0, 0, 0, 0};
 
     for (int i = 1; i < N; ++i) {
-        // 1. Marsaglia direction of trial t: first attempt with 0 < s < 1
+        // Attempts 0 and 1 are drawn by every lane at once: a wave then waits
+        // for a straggler only when one of its lanes fails both (probability
+        // (1 - pi/4)^2 per lane), instead of running about 3.6 rounds per
+        // step for the slowest of 64 geometric draws.
         double v1 = 0.0, v2 = 0.0, s = 0.5;
-        bool done = !(alive && has_trial);
-        uint32_t att = 0;
+        double w1 = 0.0, w2 = 0.0, ws = 0.5;
+        const bool acc0 = marsaglia_try(draw(a.seed, g, (uint32_t)i, (uint32_t)t, 0), v1, v2, s);
+        const bool acc1 = marsaglia_try(draw(a.seed, g, (uint32_t)i, (uint32_t)t, 1), w1, w2, ws);
+        if (!acc0 && acc1) {
+            v1 = w1; v2 = w2; s = ws;
+        }
+        bool done = !(alive && has_trial) || acc0 || acc1;
+        uint32_t att = 2;
         while (!done) {
-            const Philox4 q = draw(a.seed, g, (uint32_t)i, (uint32_t)t, att);
-            const int64_t j1 = ((int64_t)(q.x0 >> 5) << 26) + (int64_t)(q.x1 >> 6);
-            const int64_t j2 = ((int64_t)(q.x2 >> 5) << 26) + (int64_t)(q.x3 >> 6);
-            const double u1 = (double)(j1 - (1ll << 52)) * 0x1p-52;
-            const double u2 = (double)(j2 - (1ll << 52)) * 0x1p-52;
-            const double ss = u1 * u1 + u2 * u2;
-            if (ss < 1.0 && ss != 0.0) {
-                v1 = u1; v2 = u2; s = ss;
-                done = true;
-            } else if (++att == kMaxAttempt) {
-                rng_fail = true;
-                done = true;
-            }
+            if (marsaglia_try(draw(a.seed, g, (uint32_t)i, (uint32_t)t, att), v1, v2, s)) done = true;
+            else if (++att == kMaxAttempt) { rng_fail = true; done = true; }
         }
         const double qf = 2.0 * sqrt(1.0 - s);
         const double ex = v1 * qf, ey = v2 * qf, ez = 1.0 - 2.0 * s;
         const double cx = tx + b * ex, cy = ty + b * ey, cz = tz + b * ez;
 
-        // 2. overlap test against beads 0 .. i-2 of this chain
-        bool fr = alive && has_trial;
-        for (int j = 0; j <= i - 2; ++j) {
-            const double *r = &beads[((size_t)j * cpb + chb) * 3];
-            const double dx = cx - r[0], dy = cy - r[1], dz = cz - r[2];
+        // 2-3. exact test of this lane's candidate: beads i-2 and i-3 (within
+        // 2b of the tip) directly, beads 0 .. i-4 after the culling pass
+        bool blocked = false; // bitwise accumulation keeps the tests branch-free
+        const auto test_bead = [&](int j) {
+            const int o = at(j);
+            const double dx = cx - X[o], dy = cy - Y[o], dz = cz - Z[o];
             double d2 = dx * dx + dy * dy;
             d2 = d2 + dz * dz;
-            fr = fr && !(d2 < sigma2);
+            blocked = blocked | (d2 < sigma2);
+        };
+        const auto is_near = [&](int j) {
+            const int o = at(j);
+            const double dx = X[o] - tx, dy = Y[o] - ty, dz = Z[o] - tz;
+            double d2 = dx * dx + dy * dy;
+            d2 = d2 + dz * dz;
+            return !(d2 >= cull2);
+        };
+        if (i >= 2) test_bead(i - 2);
+        if (i >= 3) test_bead(i - 3);
+        const int nb = __builtin_amdgcn_readfirstlane(i - 3);
+        for (int b0 = 0; b0 < nb; b0 += 2 * G) {
+            // two blocks of G beads per pass, lane t taking bead b0 + t and
+            // b0 + G + t; the offsets flagged by any chain of the wave are
+            // re-tested exactly by every chain (a culled bead cannot
+            // overlap, so testing it again changes nothing)
+            // (indices clamped so that both loads issue unconditionally)
+            const int j0 = b0 + t, j1 = b0 + G + t;
+            const bool d0 = is_near(j0 < nb ? j0 : nb - 1);
+            const bool d1 = is_near(j1 < nb ? j1 : nb - 1);
+            const bool n0 = alive & (j0 < nb) & d0;
+            const bool n1 = alive & (j1 < nb) & d1;
+            uint64_t u0 = fold_groups<G>(__ballot(n0));
+            uint64_t u1 = fold_groups<G>(__ballot(n1));
+            while (u0) {
+                const int q = __builtin_ctzll(u0);
+                u0 &= u0 - 1;
+                test_bead(b0 + q);
+            }
+            while (u1) {
+                const int q = __builtin_ctzll(u1);
+                u1 &= u1 - 1;
+                test_bead(b0 + G + q);
+            }
         }
 
-        // 3. free mask of the group and m
+        const bool fr = alive & has_trial & !blocked;
+
+        // 4. free mask of the group and m
         const uint64_t bal = __ballot(fr);
         const uint64_t gm = (bal >> gbase) & gmask_bits;
         const uint32_t m = (uint32_t)__popcll(gm);
 
-        // 4. uniform pick among the free trials (16-bit Lemire word)
+        // 5. uniform pick among the free trials (16-bit Lemire word)
         if (i == 1 || (i & 7) == 0) sel = draw(a.seed, g, (uint32_t)(i >> 3), kSlotSelect, 0);
         const uint32_t x = half_word(sel, (uint32_t)(i & 7));
         const uint32_t p = x * m;
         uint32_t r = p >> 16;
-        if (__builtin_expect(alive && (p & 0xFFFFu) < m, 0))
-            r = lemire_redraw16(a.seed, g, (uint32_t)i, m, x, &rng_fail);
+        if (__builtin_expect(alive && (p & 0xFFFFu) < m, 0)) {
+            r = lemire_redraw16(a.seed, g, (uint32_t)i, m, x);
+            if (r == kPickFailed) {
+                rng_fail = true;
+                r = 0;
+            }
+        }
         const uint64_t below = (t == 0) ? 0ull : (gm & ((1ull << t) - 1ull));
         const bool chosen = fr && ((uint32_t)__popcll(below) == r);
         const uint64_t cb = __ballot(chosen);
@@ -117,15 +228,13 @@ __global__ __launch_bounds__(256) void grow_real_tp(GrowArgs a)
         }
         if (alive) {
             if (chosen) {
-                double *ri = &beads[((size_t)i * cpb + chb) * 3];
-                ri[0] = nx; ri[1] = ny; ri[2] = nz;
+                const int o = at(i);
+                X[o] = nx; Y[o] = ny; Z[o] = nz;
             }
             tx = nx; ty = ny; tz = nz;
             n_mine += (m == (uint32_t)t + 1u) ? 1u : 0u;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        wave_sync();
     }
     if (alive) grown = N;
 
@@ -142,21 +251,21 @@ __global__ __launch_bounds__(256) void grow_real_tp(GrowArgs a)
     if (t == 0 && valid) {
         double sx = 0.0, sy = 0.0, sz = 0.0;
         for (int j = 0; j < grown; ++j) {
-            const double *r = &beads[((size_t)j * cpb + chb) * 3];
-            sx = sx + r[0]; sy = sy + r[1]; sz = sz + r[2];
+            const int o = at(j);
+            sx = sx + X[o]; sy = sy + Y[o]; sz = sz + Z[o];
         }
         const double gd = (double)grown;
         const double cmx = sx / gd, cmy = sy / gd, cmz = sz / gd;
         double acc = 0.0;
         for (int j = 0; j < grown; ++j) {
-            const double *r = &beads[((size_t)j * cpb + chb) * 3];
-            const double dx = r[0] - cmx, dy = r[1] - cmy, dz = r[2] - cmz;
+            const int o = at(j);
+            const double dx = X[o] - cmx, dy = Y[o] - cmy, dz = Z[o] - cmz;
             double q = dx * dx + dy * dy;
             q = q + dz * dz;
             acc = acc + q;
         }
-        const double *re = &beads[((size_t)(grown - 1) * cpb + chb) * 3];
-        const double ex = re[0], ey = re[1], ez = re[2];
+        const int oe = at(grown - 1);
+        const double ex = X[oe], ey = Y[oe], ez = Z[oe];
         double r2 = ex * ex + ey * ey;
         r2 = r2 + ez * ez;
         if (a.log_w) a.log_w[c] = lw;
@@ -177,14 +286,16 @@ __global__ __launch_bounds__(256) void grow_real_tp(GrowArgs a)
 template <int G>
 static hipError_t launch_g(const GrowArgs &a, hipStream_t s)
 {
-    // 256-thread blocks when the bead store fits in 64 KiB, else one wave.
-    const size_t per_chain = (size_t)a.n_monomers * 3 * sizeof(double);
+    // 256-thread blocks when the bead planes fit in 64 KiB, else one wave.
+    auto planes = [&](int threads) {
+        return (size_t)3 * a.n_monomers * plane_row(threads / G, G) * sizeof(double);
+    };
     int threads = 256;
-    if ((size_t)(threads / G) * per_chain > 65536) threads = 64;
+    if (planes(threads) > 65536) threads = 64;
+    if (planes(threads) > 65536) return hipErrorInvalidValue;
     const int cpb = threads / G;
     const uint64_t blocks = (a.n_chains + cpb - 1) / cpb;
-    const size_t shmem = (size_t)cpb * per_chain;
-    hipLaunchKernelGGL((grow_real_tp<G>), dim3((uint32_t)blocks), dim3(threads), shmem, s, a);
+    hipLaunchKernelGGL((grow_real_tp<G>), dim3((uint32_t)blocks), dim3(threads), planes(threads), s, a);
     return hipGetLastError();
 }
 

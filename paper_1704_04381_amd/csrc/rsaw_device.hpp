@@ -64,10 +64,13 @@ __device__ __forceinline__ uint32_t half_word(const Philox4 &b, uint32_t h)
 // Lemire's method on 16-bit words, slow path: the primary word x of step
 // `step` is accepted when (x m) mod 2^16 >= 2^16 mod m, else the eight
 // halves of each redraw block (slot 0xFFFE, attempt 0, 1, ...) are tried in
-// order.  Returns (x m) / 2^16 of the accepted word, or sets *fail at the
-// attempt cap.  m >= 1.
+// order.  Returns (x m) / 2^16 of the accepted word, or kPickFailed at the
+// attempt cap.  m >= 1.  The failure travels in the return value so that no
+// flag of the caller has its address taken (which would put it in scratch).
+constexpr uint32_t kPickFailed = 0xFFFFFFFFu;
+
 __device__ __noinline__ uint32_t lemire_redraw16(uint64_t seed, uint64_t g, uint32_t step,
-                                                 uint32_t m, uint32_t x, bool *fail)
+                                                 uint32_t m, uint32_t x)
 {
     const uint32_t threshold = 65536u % m;
     uint32_t p = x * m;
@@ -79,8 +82,7 @@ __device__ __noinline__ uint32_t lemire_redraw16(uint64_t seed, uint64_t g, uint
             if ((p & 0xFFFFu) >= threshold) return p >> 16;
         }
     }
-    *fail = true;
-    return 0;
+    return kPickFailed;
 }
 
 // Wave-wide max of a 64-bit value (all 64 lanes must be active).
@@ -106,7 +108,6 @@ struct GrowArgs {
     double bond_length;
     double sigma2;
     double cull2; // (b + sigma)^2 (1 + 2^-30): beads at or beyond it cannot overlap
-    int32_t lds_row; // real space: row stride of the LDS bead planes, set by the launcher
     // per-chain outputs (device, any may be null)
     double *log_w;
     uint64_t *w_exact;

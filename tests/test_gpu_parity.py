@@ -134,7 +134,11 @@ def _real_case(N, k, M, seed, b=1.0, sigma=1.0, bins=0, offset=0):
 @pytest.mark.parametrize("N,k,M,seed", [(64, 8, 1_500, 1), (17, 8, 2_003, 2), (3, 8, 999, 3),
                                         (2, 8, 100, 4), (1, 8, 64, 5), (24, 1, 700, 6),
                                         (24, 5, 700, 7), (20, 16, 600, 8), (12, 33, 300, 9),
-                                        (10, 64, 200, 10)])
+                                        (10, 64, 200, 10),
+                                        # one-wave blocks (bead planes above 64 KiB at
+                                        # 256 threads) up to the largest N
+                                        (100, 8, 403, 11), (256, 8, 77, 12), (200, 16, 101, 13),
+                                        (150, 33, 65, 14), (256, 64, 21, 15)])
 def test_real_parity(N, k, M, seed):
     _, _, exact = _real_case(N, k, M, seed, bins=128)
     assert exact
