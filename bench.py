@@ -274,7 +274,10 @@ def main():
             "p50_ms": _percentile(r2["lat"], 0.5), "p99_ms": _percentile(r2["lat"], 0.99),
             "roofline": {"bound": "alu", "achieved": ach2, "peak": VALU_PEAK_TOPS,
                          "unit": "Tops/s", "frac": ach2 / VALU_PEAK_TOPS,
-                         "kernel_ms": r2["grow_ms"]},
+                         "traffic": (measured_traffic("grow_lattice_reg", "grow_lattice.hip", args.secondary)
+                                     if w2["geometry"] == "lattice" else
+                                     measured_traffic("grow_real_tp", "grow_real.hip", args.secondary)),
+                         "kernel_ms": r2["grow_ms"], "alg_ops_per_launch": ops2},
             "physics": {k: r2["summary"][k] for k in ("n_alive", "log_c_est", "r2_mean",
                                                       "r2_err", "rg2_mean", "rg2_err")},
         }
