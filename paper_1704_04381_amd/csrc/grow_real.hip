@@ -7,8 +7,8 @@
 //
 // Per step i:
 //   1. lane t obtains the Marsaglia direction of trial t (Philox slot t, the
-//      first accepted attempt; attempts 0 and 1 are always drawn) and forms
-//      the candidate c_t = tip + b e;
+//      first accepted attempt; rejected trials are retried by all lanes of
+//      the wave at once) and forms the candidate c_t = tip + b e;
 //   2. culling: beads i-2 and i-3 are always tested; the G lanes of the
 //      chain split beads 0 .. i-4 (lane t takes every G-th bead) and flag
 //      those whose squared tip distance is below (b + sigma)^2 (1 + 2^-30);
@@ -128,22 +128,67 @@ __global__ __launch_bounds__(256) void grow_real_tp(GrowArgs a)
     Philox4 sel{0, 0, 0, 0};
 
     for (int i = 1; i < N; ++i) {
-        // Attempts 0 and 1 are drawn by every lane at once: a wave then waits
-        // for a straggler only when one of its lanes fails both (probability
-        // (1 - pi/4)^2 per lane), instead of running about 3.6 rounds per
-        // step for the slowest of 64 geometric draws.
+        // 1. Marsaglia direction of trial t: the first accepted attempt.
+        // Round 1: every lane tries attempt 0 of its own trial.  Round 2: the
+        // 64 lanes of the wave serve the trials that failed, lane l taking
+        // the failed trial of rank q = l mod nF at attempt 1 + l / nF; each
+        // failed trial then takes its first accepting helper in lane order,
+        // which is its smallest accepted attempt.  Values move through the
+        // cross-lane permute network (no LDS storage).  A trial whose helpers
+        // all rejected continues alone after its last helped attempt.
         double v1 = 0.0, v2 = 0.0, s = 0.5;
-        double w1 = 0.0, w2 = 0.0, ws = 0.5;
-        const bool acc0 = marsaglia_try(draw(a.seed, g, (uint32_t)i, (uint32_t)t, 0), v1, v2, s);
-        const bool acc1 = marsaglia_try(draw(a.seed, g, (uint32_t)i, (uint32_t)t, 1), w1, w2, ws);
-        if (!acc0 && acc1) {
-            v1 = w1; v2 = w2; s = ws;
+        const bool need = alive && has_trial;
+        bool acc = marsaglia_try(draw(a.seed, g, (uint32_t)i, (uint32_t)t, 0), v1, v2, s);
+        uint32_t att = 1;
+        const uint64_t F = __ballot(need && !acc);
+        if (F != 0) {
+            const uint32_t nF = (uint32_t)__popcll(F);
+            const bool failing = need && !acc;
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(F >> 32),
+                                  __builtin_amdgcn_mbcnt_lo((uint32_t)F, 0u));
+            // lane q < nF learns the lane of the failed trial of rank q
+            const int owner_of_q = __builtin_amdgcn_ds_permute((int)((failing ? rank : 63u) * 4u), lane);
+            // l / nF and l mod nF (l < 64: the float quotient is never within
+            // rounding of an integer boundary)
+            const uint32_t jh = (uint32_t)(((float)lane + 0.5f) * __builtin_amdgcn_rcpf((float)nF));
+            const uint32_t q = (uint32_t)lane - jh * nF;
+            const int owner = __builtin_amdgcn_ds_bpermute((int)(q * 4u), owner_of_q);
+            const uint64_t og = a.chain_offset + (uint64_t)blockIdx.x * cpb +
+                                (uint64_t)(((threadIdx.x & ~63) + (owner & ~(G - 1))) / G);
+            double h1 = 0.0, h2 = 0.0, hs = 0.5;
+            const bool hok = marsaglia_try(draw(a.seed, og, (uint32_t)i, (uint32_t)(owner & (G - 1)), 1u + jh),
+                                           h1, h2, hs);
+            const uint64_t H = __ballot(hok);
+            // helpers of rank r are lanes r, r + nF, r + 2 nF, ...
+            uint64_t pattern = 0;
+            for (uint32_t l = 0; l < 64u; l += nF) pattern |= 1ull << l;
+            const uint64_t mine = failing ? (H & (pattern << rank)) : 0ull;
+            const int src = mine ? __builtin_ctzll(mine) : lane;
+            const auto pull = [&](double v) {
+                const int64_t bits = __double_as_longlong(v);
+                const int lo = __builtin_amdgcn_ds_bpermute(src * 4, (int)(uint32_t)bits);
+                const int hi = __builtin_amdgcn_ds_bpermute(src * 4, (int)(uint32_t)(bits >> 32));
+                return __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+            };
+            const double n1 = pull(h1), n2 = pull(h2), ns = pull(hs);
+            if (failing) {
+                if (mine) {
+                    v1 = n1; v2 = n2; s = ns;
+                    acc = true;
+                } else {
+                    att = 1u + (64u - rank + nF - 1u) / nF;
+                }
+            }
         }
-        bool done = !(alive && has_trial) || acc0 || acc1;
-        uint32_t att = 2;
+        // round 3 (rare): the remaining trials continue alone
+        bool done = !need || acc;
         while (!done) {
-            if (marsaglia_try(draw(a.seed, g, (uint32_t)i, (uint32_t)t, att), v1, v2, s)) done = true;
-            else if (++att == kMaxAttempt) { rng_fail = true; done = true; }
+            if (marsaglia_try(draw(a.seed, g, (uint32_t)i, (uint32_t)t, att), v1, v2, s)) {
+                done = true;
+            } else if (++att == kMaxAttempt) {
+                rng_fail = true;
+                done = true;
+            }
         }
         const double qf = 2.0 * sqrt(1.0 - s);
         const double ex = v1 * qf, ey = v2 * qf, ez = 1.0 - 2.0 * s;
