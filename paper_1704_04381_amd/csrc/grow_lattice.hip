@@ -26,7 +26,7 @@
 // Measured on MI355X (10^7 chains, N = 64): splitting the occupied mask over
 // two accumulators shortens the per-step dependency chain and gains ~10%;
 // capping the kernel at 4 waves per SIMD (spilling) loses ~10%.
-#include "rsaw_device.hpp"
+#include "lattice_common.hpp"
 
 #include <type_traits>
 
@@ -44,27 +44,6 @@ __device__ __forceinline__ void static_for(F &&f)
 }
 
 constexpr uint32_t kOrigin = 0x80808000u; // origin, Q = 0
-
-// LUT[mask * 8 + r]: the move to the r-th free candidate of the 7-bit mask,
-// packed as (coordinate delta in bytes 1..3) | (dQ mod 256 in byte 0).
-__device__ __forceinline__ uint32_t lattice_move(uint32_t idx)
-{
-    const uint32_t mask = idx >> 3, r = idx & 7u;
-    uint32_t seen = 0;
-    for (uint32_t c = 0; c < 7; ++c) {
-        if (c == 3 || !((mask >> c) & 1u)) continue;
-        if (seen == r) {
-            const int dq = (int)c - 3;
-            const int axis = dq < 0 ? -dq : dq; // 1 = x, 2 = y, 3 = z
-            const int32_t dcoord = (dq < 0 ? -1 : 1) * (int32_t)(1u << (8 * axis));
-            return ((uint32_t)dcoord & 0xFFFFFF00u) | ((uint32_t)dq & 0xFFu);
-        }
-        ++seen;
-    }
-    return 0;
-}
-
-constexpr int kLutSize = 120 * 8; // masks up to 0x77
 
 template <int NMAX, bool EXACT, typename CT>
 __global__ __launch_bounds__(256) void grow_lattice_reg(GrowArgs a)
@@ -200,9 +179,12 @@ static hipError_t launch(const GrowArgs &a, hipStream_t s)
 }
 
 // Dispatch on the N bucket, exact-weight flag and output coordinate type.
+hipError_t launch_grow_lattice_lds(const GrowArgs &a, bool i16, hipStream_t s);
+
 hipError_t launch_grow_lattice(const GrowArgs &a, bool exact, bool i16, hipStream_t s)
 {
     const int N = a.n_monomers;
+    if (!exact && N > 64) return launch_grow_lattice_lds(a, i16, s);
     if (exact) {
         // RSAW_EXACT_W is limited to N <= 28 by the caller
         if (N <= 16) return i16 ? launch<16, true, int16_t>(a, s) : launch<16, true, int32_t>(a, s);

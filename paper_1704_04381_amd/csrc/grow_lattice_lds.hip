@@ -1,0 +1,285 @@
+// Lattice chain growth for chains too long to keep in registers (N > 64):
+// the same growth rule as the register kernel (Sec. 3.3.2, Algorithm 1;
+// weight of Eq. 3) with the chain history in LDS and G lanes per chain.
+//
+// Layout.  Each chain owns S words of LDS: two parity planes (monomers of
+// even and odd index) of H words each, times one (byte format) or two (wide
+// format) words per monomer.  On the bipartite cubic lattice the monomers
+// that can neighbour the tip at step i are those of index i - 2, i - 4, ...,
+// i.e. the first floor(i / 2) entries of the plane of parity i, so the scan
+// reads one contiguous run.  Lane t of the chain's group reads 4 consecutive
+// words (one b128 load) per pass, the group 4 G words.  Entries not yet
+// placed hold 0, a sentinel that is never adjacent to any tip, so the scan
+// needs no bounds test and H is the half length rounded up to 4 G.
+//
+// Monomer words.
+//   byte format (N <= 128, coordinates within [-127, 127]): as in the
+//     register kernel, (Q mod 256, x + 128, y + 128, z + 128); pair test
+//     L = msad(r_j, tip & ~0xFF), bit = sat(2 - L), code = (r_j - tip + 3)
+//     mod 32 from the Q byte, 4 operations.
+//   wide format (N <= 16384): A = (x + 2^15) | (y + 2^15) << 16 and
+//     B = (64 + Q mod 32) | (z + 2^15) << 16; pair test
+//     L = sad_u16(A_j, A_t) + sad_u16(B_j & 0xFFFF0000, B_t & 0xFFFF0000),
+//     bit = sat(2 - L), code = (B_j - B_t + 3) mod 32, 6 operations.  A move
+//     adds per-field deltas that never carry across a field; one AND-OR
+//     brings B's low field back to 64 + (Q mod 32).
+//
+// Per step the G partial occupancy masks are OR-reduced across the group;
+// every lane of the group then performs the same pick (same Philox words),
+// and lane 0 appends the new monomer to its parity plane.
+#include "lattice_common.hpp"
+
+namespace rsaw {
+
+// Orders the LDS accesses of the lanes of one wave.
+__device__ __forceinline__ void lattice_wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr uint32_t kByteOrigin = 0x80808000u;            // origin, Q = 0
+constexpr uint32_t kWideOriginA = 0x80008000u;           // x = y = 0
+constexpr uint32_t kWideOriginB = 0x80000000u | 64u;     // z = 0, Q = 0
+
+template <bool WIDE>
+__device__ __forceinline__ uint32_t pair_bits(uint32_t wa, uint32_t wb, uint32_t ta, uint32_t tbh,
+                                              uint32_t tq)
+{
+    if constexpr (WIDE) {
+        uint32_t L = __builtin_amdgcn_sad_u16(wa, ta, 0u);
+        L = __builtin_amdgcn_sad_u16(wb & 0xFFFF0000u, tbh, L);
+        const uint32_t bit = __builtin_elementwise_sub_sat(2u, L);
+        return bit << ((wb - tq) & 31u);
+    } else {
+        const uint32_t L = __builtin_amdgcn_msad_u8(wa, ta, 0u);
+        const uint32_t bit = __builtin_elementwise_sub_sat(2u, L);
+        return bit << ((wa - tq) & 31u);
+    }
+}
+
+template <int G, bool WIDE, typename CT>
+__global__ __launch_bounds__(64) void grow_lattice_lds(GrowArgs a, int H, int S)
+{
+    constexpr int WPM = WIDE ? 2 : 1; // words per monomer
+    constexpr int CPB = 64 / G;       // chains per block (one wave)
+    extern __shared__ uint32_t lds_u[];
+    uint32_t *lut = lds_u;                       // byte-format move, or the A move
+    uint32_t *lutb = lds_u + kLutSize;           // B move (wide only)
+    uint32_t *chains = lds_u + WPM * kLutSize;   // CPB chains of S words
+
+    for (int idx = threadIdx.x; idx < kLutSize; idx += 64) {
+        const uint32_t mv = lattice_move((uint32_t)idx);
+        if constexpr (WIDE) {
+            const int dq = (int)(int8_t)(mv & 0xFFu);
+            const int axis = dq < 0 ? -dq : dq;
+            const int sg = dq < 0 ? -1 : 1;
+            lut[idx] = axis == 1 ? (uint32_t)sg : (axis == 2 ? (uint32_t)(sg * 65536) : 0u);
+            lutb[idx] = (uint32_t)((axis == 3 ? sg * 65536 : 0) + dq);
+        } else {
+            lut[idx] = mv;
+        }
+    }
+    for (int w = threadIdx.x; w < CPB * S; w += 64) chains[w] = 0u;
+    __syncthreads();
+
+    const int t = threadIdx.x & (G - 1);
+    const int chb = threadIdx.x / G;
+    const uint64_t c = (uint64_t)blockIdx.x * CPB + chb;
+    const bool valid = c < a.n_chains;
+    const uint64_t g = a.chain_offset + c;
+    const int N = a.n_monomers;
+    uint32_t *base = chains + chb * S;
+
+    uint32_t ta = WIDE ? kWideOriginA : kByteOrigin; // tip, A word (or the byte word)
+    uint32_t tb = WIDE ? kWideOriginB : 0u;          // tip, B word (wide only)
+    if (t == 0) {
+        base[0] = ta;
+        if constexpr (WIDE) base[H] = tb;
+    }
+    lattice_wave_sync();
+
+    bool alive = valid;
+    int grown = 1;
+    uint64_t cnt = 0; // 16-bit fields: steps with m = 2, 3, 4, 5 (step 1 has m = 6)
+    bool rng_fail = false;
+    Philox4 blk{0, 0, 0, 0};
+
+    for (int i = 1; i < N; ++i) {
+        // occupied-neighbour mask: the group scans the plane of parity i
+        const uint32_t *pa = base + (i & 1) * WPM * H;
+        const uint32_t *pb = pa + H;
+        const int nrel = i >> 1;
+        const int passes = (nrel + 4 * G - 1) / (4 * G);
+        const uint32_t tref = WIDE ? ta : (ta & 0xFFFFFF00u);
+        const uint32_t tbh = tb & 0xFFFF0000u;
+        const uint32_t tq = (WIDE ? tb : ta) - 3u;
+        uint32_t occ = 0, occ2 = 0;
+        for (int q = 0; q < passes; ++q) {
+            const int k = q * 4 * G + 4 * t;
+            const uint4 wa = *(const uint4 *)(pa + k);
+            uint4 wb = make_uint4(0u, 0u, 0u, 0u);
+            if constexpr (WIDE) wb = *(const uint4 *)(pb + k);
+            occ |= pair_bits<WIDE>(wa.x, wb.x, tref, tbh, tq);
+            occ2 |= pair_bits<WIDE>(wa.y, wb.y, tref, tbh, tq);
+            occ |= pair_bits<WIDE>(wa.z, wb.z, tref, tbh, tq);
+            occ2 |= pair_bits<WIDE>(wa.w, wb.w, tref, tbh, tq);
+        }
+        occ |= occ2;
+#pragma unroll
+        for (int off = 1; off < G; off <<= 1) occ |= (uint32_t)__shfl_xor((int)occ, off, 64);
+        const uint32_t freem = ~occ & 0x77u;
+        const uint32_t m = __builtin_popcount(freem);
+
+        // 16-bit selection word: half i mod 8 of one Philox block per 8 steps
+        if (i == 1 || (i & 7) == 0) blk = draw(a.seed, g, (uint32_t)(i >> 3), kSlotSelect, 0);
+        const uint32_t x = half_word(blk, (uint32_t)(i & 7));
+        const uint32_t p = x * m;
+        uint32_t r = p >> 16;
+        if (__builtin_expect(alive && (p & 0xFFFFu) < m, 0)) {
+            r = lemire_redraw16(a.seed, g, (uint32_t)i, m, x);
+            if (r == kPickFailed) {
+                rng_fail = true;
+                r = 0;
+            }
+        }
+
+        const bool step_ok = alive && m != 0;
+        const uint32_t li = (freem << 3) | (r & 7u);
+        uint32_t na, nb = 0u;
+        if constexpr (WIDE) {
+            na = ta + lut[li];
+            nb = ((tb + lutb[li]) & 0xFFFF001Fu) | 0x40u;
+        } else {
+            const uint32_t mv = lut[li];
+            na = ((ta & 0xFFFFFF00u) + (mv & 0xFFFFFF00u)) | ((ta + mv) & 0xFFu);
+        }
+        if (alive && m == 0) {
+            alive = false;
+            grown = i;
+        }
+        if (step_ok) {
+            ta = na;
+            tb = nb;
+            if (i >= 2 && m >= 2) cnt += 1ull << (16u * (m - 2u));
+            if (t == 0) {
+                uint32_t *wp = base + (i & 1) * WPM * H + (i >> 1);
+                wp[0] = na;
+                if constexpr (WIDE) wp[H] = nb;
+            }
+        }
+        lattice_wave_sync();
+    }
+    if (alive) grown = N;
+
+    // log W = sum over m = 1..6, ascending, of n_m log m; n_1 log 1 = 0 and
+    // m_1 = 6 always
+    double lw = 0.0;
+    if (N >= 2) {
+        lw = lw + (double)(uint32_t)(cnt & 0xFFFFu) * a.logm[2];
+        lw = lw + (double)(uint32_t)((cnt >> 16) & 0xFFFFu) * a.logm[3];
+        lw = lw + (double)(uint32_t)((cnt >> 32) & 0xFFFFu) * a.logm[4];
+        lw = lw + (double)(uint32_t)((cnt >> 48) & 0xFFFFu) * a.logm[5];
+        lw = lw + a.logm[6];
+    }
+
+    // observables over the placed monomers (integer sums: any order)
+    int32_t sx = 0, sy = 0, sz = 0;
+    int64_t s2 = 0;
+    for (int j = t; j < grown; j += G) {
+        const uint32_t *wp = base + (j & 1) * WPM * H + (j >> 1);
+        int32_t x, y, z;
+        if constexpr (WIDE) {
+            const uint32_t wa = wp[0], wb = wp[H];
+            x = (int32_t)(wa & 0xFFFFu) - 32768;
+            y = (int32_t)(wa >> 16) - 32768;
+            z = (int32_t)(wb >> 16) - 32768;
+        } else {
+            const uint32_t w = wp[0];
+            x = (int32_t)((w >> 8) & 0xFFu) - 128;
+            y = (int32_t)((w >> 16) & 0xFFu) - 128;
+            z = (int32_t)(w >> 24) - 128;
+        }
+        sx += x;
+        sy += y;
+        sz += z;
+        s2 += (int64_t)(x * x + y * y + z * z);
+    }
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) {
+        sx += __shfl_xor(sx, off, 64);
+        sy += __shfl_xor(sy, off, 64);
+        sz += __shfl_xor(sz, off, 64);
+        const int lo = __shfl_xor((int)(uint32_t)s2, off, 64);
+        const int hi = __shfl_xor((int)(uint32_t)((uint64_t)s2 >> 32), off, 64);
+        s2 += (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+    }
+    const int64_t gg = grown;
+    const int64_t nn = gg * s2 - ((int64_t)sx * sx + (int64_t)sy * sy + (int64_t)sz * sz);
+    int32_t ex, ey, ez;
+    if constexpr (WIDE) {
+        ex = (int32_t)(ta & 0xFFFFu) - 32768;
+        ey = (int32_t)(ta >> 16) - 32768;
+        ez = (int32_t)(tb >> 16) - 32768;
+    } else {
+        ex = (int32_t)((ta >> 8) & 0xFFu) - 128;
+        ey = (int32_t)((ta >> 16) & 0xFFu) - 128;
+        ez = (int32_t)(ta >> 24) - 128;
+    }
+    const double logw = alive ? lw : -__builtin_huge_val();
+
+    if (valid && t == 0) {
+        if (a.log_w) a.log_w[c] = logw;
+        if (a.r_end) {
+            CT *re = (CT *)a.r_end;
+            re[c] = (CT)ex;
+            re[a.n_chains + c] = (CT)ey;
+            re[2 * a.n_chains + c] = (CT)ez;
+        }
+        if (a.r2) a.r2[c] = (double)((int64_t)ex * ex + (int64_t)ey * ey + (int64_t)ez * ez);
+        if (a.n2rg2) a.n2rg2[c] = nn;
+        if (a.rg2) a.rg2[c] = (double)nn / ((double)gg * (double)gg);
+        if (a.n_grown) a.n_grown[c] = (uint16_t)grown;
+    }
+    if (rng_fail) atomicExch(a.status, 6);
+    const uint64_t bits = (alive && t == 0) ? (uint64_t)__double_as_longlong(lw) : 0ull;
+    const uint64_t wmax = wave_max_u64(bits);
+    if (threadIdx.x == 0 && wmax != 0) atomicMax(a.log_w_max_bits, (unsigned long long)wmax);
+}
+
+template <int G, bool WIDE, typename CT>
+static hipError_t launch_lds(const GrowArgs &a, hipStream_t s)
+{
+    constexpr int WPM = WIDE ? 2 : 1;
+    constexpr int CPB = 64 / G;
+    const int half = (a.n_monomers + 1) / 2;
+    const int H = (half + 4 * G - 1) / (4 * G) * (4 * G);
+    // chain stride: pad so that the chains of a wave start on different banks
+    const int S = 2 * WPM * H + (4 * G < 64 ? 4 * G : 0);
+    const size_t shmem = ((size_t)WPM * kLutSize + (size_t)CPB * S) * sizeof(uint32_t);
+    if (shmem > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void *)grow_lattice_lds<G, WIDE, CT>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+        if (e != hipSuccess) return e;
+    }
+    const uint64_t blocks = (a.n_chains + CPB - 1) / CPB;
+    hipLaunchKernelGGL((grow_lattice_lds<G, WIDE, CT>), dim3((uint32_t)blocks), dim3(64), shmem, s, a, H, S);
+    return hipGetLastError();
+}
+
+// Largest lattice chain of the LDS kernel (wide words: 128 KiB per chain).
+int lattice_lds_max_monomers() { return 16384; }
+
+// Launch for 64 < N <= 16384: G grows with N so that the scan of a step
+// stays a few passes per lane.
+hipError_t launch_grow_lattice_lds(const GrowArgs &a, bool i16, hipStream_t s)
+{
+    const int N = a.n_monomers;
+    if (N <= 128) return i16 ? launch_lds<4, false, int16_t>(a, s) : launch_lds<4, false, int32_t>(a, s);
+    if (N <= 512) return i16 ? launch_lds<8, true, int16_t>(a, s) : launch_lds<8, true, int32_t>(a, s);
+    if (N <= 2048) return i16 ? launch_lds<32, true, int16_t>(a, s) : launch_lds<32, true, int32_t>(a, s);
+    return i16 ? launch_lds<64, true, int16_t>(a, s) : launch_lds<64, true, int32_t>(a, s);
+}
+
+} // namespace rsaw

@@ -20,6 +20,7 @@ namespace rsaw {
 hipError_t launch_grow_lattice(const GrowArgs &a, bool exact, bool i16, hipStream_t s);
 hipError_t launch_grow_real(const GrowArgs &a, hipStream_t s);
 int real_max_monomers();
+int lattice_lds_max_monomers();
 } // namespace rsaw
 
 namespace {
@@ -151,7 +152,8 @@ rsaw_status validate(const rsaw_config *cfg)
             return fail(RSAW_E_INVALID, "lattice coord_type must be RSAW_I16 or RSAW_I32");
         if ((cfg->flags & RSAW_EXACT_W) && N > 28)
             return fail(RSAW_E_OVERFLOW, "RSAW_EXACT_W needs n_monomers <= 28");
-        if (N > 64) return fail(RSAW_E_UNSUPPORTED, "lattice kernel supports n_monomers <= 64");
+        if (N > rsaw::lattice_lds_max_monomers())
+            return fail(RSAW_E_UNSUPPORTED, "lattice kernels support n_monomers <= 16384");
     } else if (cfg->geometry == RSAW_REAL_HS) {
         if (cfg->k_trials < 1 || cfg->k_trials > 64)
             return fail(RSAW_E_INVALID, "real-space k_trials must be in 1..64");

@@ -40,7 +40,7 @@ BAD = [
     (dict(geometry="lattice", N=16, k=5), 1),
     (dict(geometry="lattice", N=16, k=6, coord="f64"), 1),
     (dict(geometry="lattice", N=29, k=6, exact_w=True), 3),
-    (dict(geometry="lattice", N=65, k=6), 2),
+    (dict(geometry="lattice", N=16385, k=6), 2),
     (dict(geometry="real", N=16, k=0), 1),
     (dict(geometry="real", N=16, k=65), 1),
     (dict(geometry="real", N=16, k=8, coord="i32"), 1),

@@ -103,6 +103,17 @@ def test_lattice_bit_exact(N, M, seed, coord):
     _lattice_case(N, M, seed, coord=coord, bins=256 if N > 1 else 0)
 
 
+@pytest.mark.parametrize("N,M,seed,coord", [
+    # LDS kernel: byte words with 4 lanes per chain (N <= 128), wide words with
+    # 8 (N <= 512), 32 (N <= 2048) and 64 lanes per chain, up to the largest N
+    (65, 3_001, 21, "i16"), (100, 1_500, 22, "i32"), (128, 2_000, 23, "i16"),
+    (129, 801, 24, "i32"), (300, 333, 25, "i16"), (512, 300, 26, "i32"),
+    (513, 200, 27, "i16"), (2_048, 60, 28, "i32"), (2_049, 40, 29, "i16"),
+    (5_000, 12, 30, "i32"), (16_384, 3, 31, "i16")])
+def test_lattice_long_chains_bit_exact(N, M, seed, coord):
+    _lattice_case(N, M, seed, coord=coord, bins=256)
+
+
 def test_lattice_dead_chains_bit_exact():
     # N = 64 chains get trapped often enough to exercise the dead-end path
     out, _ = _lattice_case(64, 40_000, 11, coord="i16", bins=256)
