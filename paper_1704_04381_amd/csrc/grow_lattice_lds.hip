@@ -24,7 +24,8 @@
 //     adds per-field deltas that never carry across a field; one AND-OR
 //     brings B's low field back to 64 + (Q mod 32).
 //
-// Per step the G partial occupancy masks are OR-reduced across the group;
+// Per step the G partial occupancy masks are OR-reduced across the group
+// (cross-lane DPP and permute operations, no LDS round trip);
 // every lane of the group then performs the same pick (same Philox words),
 // and lane 0 appends the new monomer to its parity plane.
 #include "lattice_common.hpp"
@@ -43,6 +44,27 @@ constexpr uint32_t kByteOrigin = 0x80808000u;            // origin, Q = 0
 constexpr uint32_t kWideOriginA = 0x80008000u;           // x = y = 0
 constexpr uint32_t kWideOriginB = 0x80000000u | 64u;     // z = 0, Q = 0
 
+// OR over the aligned group of G lanes, every lane receiving the result:
+// DPP butterflies within quads, half rows and rows of 16, then the gfx950
+// row-swap permutes for 32 and 64 lanes.  All lanes must be active.
+template <int G>
+__device__ __forceinline__ uint32_t group_or(uint32_t v)
+{
+    if constexpr (G >= 2) v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
+    if constexpr (G >= 4) v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
+    if constexpr (G >= 8) v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);
+    if constexpr (G >= 16) v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false);
+    if constexpr (G >= 32) {
+        const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        v = p[0] | p[1];
+    }
+    if constexpr (G >= 64) {
+        const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        v = p[0] | p[1];
+    }
+    return v;
+}
+
 template <bool WIDE>
 __device__ __forceinline__ uint32_t pair_bits(uint32_t wa, uint32_t wb, uint32_t ta, uint32_t tbh,
                                               uint32_t tq)
@@ -60,16 +82,16 @@ __device__ __forceinline__ uint32_t pair_bits(uint32_t wa, uint32_t wb, uint32_t
 }
 
 template <int G, bool WIDE, typename CT>
-__global__ __launch_bounds__(64) void grow_lattice_lds(GrowArgs a, int H, int S)
+__global__ __launch_bounds__(256) void grow_lattice_lds(GrowArgs a, int H, int S)
 {
     constexpr int WPM = WIDE ? 2 : 1; // words per monomer
-    constexpr int CPB = 64 / G;       // chains per block (one wave)
+    const int cpb = blockDim.x / G;   // chains per block
     extern __shared__ uint32_t lds_u[];
     uint32_t *lut = lds_u;                       // byte-format move, or the A move
     uint32_t *lutb = lds_u + kLutSize;           // B move (wide only)
-    uint32_t *chains = lds_u + WPM * kLutSize;   // CPB chains of S words
+    uint32_t *chains = lds_u + WPM * kLutSize;   // cpb chains of S words
 
-    for (int idx = threadIdx.x; idx < kLutSize; idx += 64) {
+    for (int idx = threadIdx.x; idx < kLutSize; idx += blockDim.x) {
         const uint32_t mv = lattice_move((uint32_t)idx);
         if constexpr (WIDE) {
             const int dq = (int)(int8_t)(mv & 0xFFu);
@@ -81,12 +103,12 @@ __global__ __launch_bounds__(64) void grow_lattice_lds(GrowArgs a, int H, int S)
             lut[idx] = mv;
         }
     }
-    for (int w = threadIdx.x; w < CPB * S; w += 64) chains[w] = 0u;
+    for (int w = threadIdx.x; w < cpb * S; w += blockDim.x) chains[w] = 0u;
     __syncthreads();
 
     const int t = threadIdx.x & (G - 1);
     const int chb = threadIdx.x / G;
-    const uint64_t c = (uint64_t)blockIdx.x * CPB + chb;
+    const uint64_t c = (uint64_t)blockIdx.x * cpb + chb;
     const bool valid = c < a.n_chains;
     const uint64_t g = a.chain_offset + c;
     const int N = a.n_monomers;
@@ -127,8 +149,7 @@ __global__ __launch_bounds__(64) void grow_lattice_lds(GrowArgs a, int H, int S)
             occ2 |= pair_bits<WIDE>(wa.w, wb.w, tref, tbh, tq);
         }
         occ |= occ2;
-#pragma unroll
-        for (int off = 1; off < G; off <<= 1) occ |= (uint32_t)__shfl_xor((int)occ, off, 64);
+        occ = group_or<G>(occ);
         const uint32_t freem = ~occ & 0x77u;
         const uint32_t m = __builtin_popcount(freem);
 
@@ -245,40 +266,49 @@ __global__ __launch_bounds__(64) void grow_lattice_lds(GrowArgs a, int H, int S)
     if (rng_fail) atomicExch(a.status, 6);
     const uint64_t bits = (alive && t == 0) ? (uint64_t)__double_as_longlong(lw) : 0ull;
     const uint64_t wmax = wave_max_u64(bits);
-    if (threadIdx.x == 0 && wmax != 0) atomicMax(a.log_w_max_bits, (unsigned long long)wmax);
+    if ((threadIdx.x & 63) == 0 && wmax != 0) atomicMax(a.log_w_max_bits, (unsigned long long)wmax);
 }
 
 template <int G, bool WIDE, typename CT>
 static hipError_t launch_lds(const GrowArgs &a, hipStream_t s)
 {
     constexpr int WPM = WIDE ? 2 : 1;
-    constexpr int CPB = 64 / G;
     const int half = (a.n_monomers + 1) / 2;
     const int H = (half + 4 * G - 1) / (4 * G) * (4 * G);
     // chain stride: pad so that the chains of a wave start on different banks
     const int S = 2 * WPM * H + (4 * G < 64 ? 4 * G : 0);
-    const size_t shmem = ((size_t)WPM * kLutSize + (size_t)CPB * S) * sizeof(uint32_t);
+    auto bytes = [&](int threads) {
+        return ((size_t)WPM * kLutSize + (size_t)(threads / G) * S) * sizeof(uint32_t);
+    };
+    // four waves per block share the move table when they fit in half the
+    // LDS of a CU; one wave otherwise
+    const int threads = bytes(256) <= 81920 ? 256 : 64;
+    const size_t shmem = bytes(threads);
+    if (shmem > 163840) return hipErrorInvalidValue;
     if (shmem > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)grow_lattice_lds<G, WIDE, CT>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
         if (e != hipSuccess) return e;
     }
-    const uint64_t blocks = (a.n_chains + CPB - 1) / CPB;
-    hipLaunchKernelGGL((grow_lattice_lds<G, WIDE, CT>), dim3((uint32_t)blocks), dim3(64), shmem, s, a, H, S);
+    const int cpb = threads / G;
+    const uint64_t blocks = (a.n_chains + cpb - 1) / cpb;
+    hipLaunchKernelGGL((grow_lattice_lds<G, WIDE, CT>), dim3((uint32_t)blocks), dim3(threads), shmem, s,
+                       a, H, S);
     return hipGetLastError();
 }
 
 // Largest lattice chain of the LDS kernel (wide words: 128 KiB per chain).
 int lattice_lds_max_monomers() { return 16384; }
 
-// Launch for 64 < N <= 16384: G grows with N so that the scan of a step
-// stays a few passes per lane.
+// Launch for 64 < N <= 16384.  G grows with N so that one wave's chains take
+// at most ~17 KiB of LDS (8 waves per CU) up to N = 2048.
 hipError_t launch_grow_lattice_lds(const GrowArgs &a, bool i16, hipStream_t s)
 {
     const int N = a.n_monomers;
     if (N <= 128) return i16 ? launch_lds<4, false, int16_t>(a, s) : launch_lds<4, false, int32_t>(a, s);
-    if (N <= 512) return i16 ? launch_lds<8, true, int16_t>(a, s) : launch_lds<8, true, int32_t>(a, s);
-    if (N <= 2048) return i16 ? launch_lds<32, true, int16_t>(a, s) : launch_lds<32, true, int32_t>(a, s);
+    if (N <= 256) return i16 ? launch_lds<8, true, int16_t>(a, s) : launch_lds<8, true, int32_t>(a, s);
+    if (N <= 512) return i16 ? launch_lds<16, true, int16_t>(a, s) : launch_lds<16, true, int32_t>(a, s);
+    if (N <= 1024) return i16 ? launch_lds<32, true, int16_t>(a, s) : launch_lds<32, true, int32_t>(a, s);
     return i16 ? launch_lds<64, true, int16_t>(a, s) : launch_lds<64, true, int32_t>(a, s);
 }
 
