@@ -25,16 +25,19 @@
 //   6. lane m - 1 of the group counts the steps with m free trials, and
 //      log W = sum_m n_m log m is formed once after the last step.
 //
-// Culling is exact, not an approximation.  A bead is dropped only when the
-// computed D^2 = ((dx dx + dy dy) + dz dz), dx = x_j - tip_x, is at least
-// T = (b + sigma)^2 (1 + 2^-30).  Each binary64 operation errs by at most
-// 2^-53 relative and all terms are non-negative, so the exact tip distance
-// is D >= (b + sigma)(1 + 2^-32).  The candidate lies within b (1 + 2^-49)
-// + 2^-44 |tip| of the tip (rounding of e, b e and tip + b e), so its exact
-// distance to the bead exceeds sigma + (b + sigma) 2^-32 - b 2^-49 - 2^-44 |tip|,
-// which for |tip| <= 255 b is at least sigma (1 + 2^-33); its computed d^2 is
-// then >= sigma^2 (1 + 2^-33)^2 (1 - 2^-50) > sigma^2: the full test would
-// also have found it free.
+// Culling is exact, not an approximation.  With u = 2^-53, a bead is
+// dropped only when its computed squared tip distance D~^2 (three
+// differences, squares and two additions of non-negative terms) is at least
+// T = (b + sigma)^2 (1 + e), e = 2^-30.  Then:
+//   - the exact tip distance is D >= sqrt(T) (1 + u)^-2.5;
+//   - the computed direction has |e| <= 1 + 5u, so the computed candidate
+//     lies within b (1 + 9u) + u |tip| of the tip;
+//   - the candidate's exact distance to the bead is d >= D - b (1 + 9u) - u |tip|,
+//     and its computed d~^2 >= d^2 (1 - u)^5, which is >= sigma^2 whenever
+//     d >= sigma (1 - u)^-2.5.
+// Putting these together, 0.49 e (b + sigma) >= 11.5 u (b + sigma) + u |tip|
+// suffices, and with |tip| <= (N - 1) b that holds for N <= 4 10^6: a culled
+// bead would also have passed the full test.
 #include "rsaw_device.hpp"
 
 namespace rsaw {
@@ -331,29 +334,40 @@ __global__ __launch_bounds__(256) void grow_real_tp(GrowArgs a)
 template <int G>
 static hipError_t launch_g(const GrowArgs &a, hipStream_t s)
 {
-    // 256-thread blocks when the bead planes fit in 64 KiB, else one wave.
+    // 256-thread blocks when the bead planes fit in half a CU's LDS, else
+    // one wave per block (up to the whole 160 KiB)
     auto planes = [&](int threads) {
         return (size_t)3 * a.n_monomers * plane_row(threads / G, G) * sizeof(double);
     };
     int threads = 256;
-    if (planes(threads) > 65536) threads = 64;
-    if (planes(threads) > 65536) return hipErrorInvalidValue;
+    if (planes(threads) > 81920) threads = 64;
+    const size_t shmem = planes(threads);
+    if (shmem + 65 * sizeof(double) > 163840) return hipErrorInvalidValue;
+    if (shmem > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void *)grow_real_tp<G>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+        if (e != hipSuccess) return e;
+    }
     const int cpb = threads / G;
     const uint64_t blocks = (a.n_chains + cpb - 1) / cpb;
-    hipLaunchKernelGGL((grow_real_tp<G>), dim3((uint32_t)blocks), dim3(threads), planes(threads), s, a);
+    hipLaunchKernelGGL((grow_real_tp<G>), dim3((uint32_t)blocks), dim3(threads), shmem, s, a);
     return hipGetLastError();
 }
 
-// Largest bead count supported by the LDS-resident kernel.
-int real_max_monomers() { return 256; }
+// Largest bead count of the LDS-resident kernel: one chain per wave, three
+// binary64 planes of N beads within a CU's 160 KiB.
+int real_max_monomers() { return 6144; }
 
+// Trial-parallel groups of G >= k lanes for short chains; one wave per chain
+// beyond N = 256, where the culling pass over all 64 lanes dominates and one
+// chain's planes already take a large share of the LDS.
 hipError_t launch_grow_real(const GrowArgs &a, hipStream_t s)
 {
     const int k = a.k_trials;
+    if (a.n_monomers > 256 || k > 32) return launch_g<64>(a, s);
     if (k <= 8) return launch_g<8>(a, s);
     if (k <= 16) return launch_g<16>(a, s);
-    if (k <= 32) return launch_g<32>(a, s);
-    return launch_g<64>(a, s);
+    return launch_g<32>(a, s);
 }
 
 } // namespace rsaw

@@ -164,7 +164,7 @@ rsaw_status validate(const rsaw_config *cfg)
             return fail(RSAW_E_INVALID, "bead_diameter must be finite and >= 0");
         if (cfg->flags & RSAW_EXACT_W) return fail(RSAW_E_INVALID, "RSAW_EXACT_W is lattice-only");
         if (N > rsaw::real_max_monomers())
-            return fail(RSAW_E_UNSUPPORTED, "real-space kernel supports n_monomers <= 256");
+            return fail(RSAW_E_UNSUPPORTED, "real-space kernel supports n_monomers <= 6144");
     } else {
         return fail(RSAW_E_INVALID, "unknown geometry");
     }

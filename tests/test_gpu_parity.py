@@ -155,6 +155,16 @@ def test_real_parity(N, k, M, seed):
     assert exact
 
 
+@pytest.mark.parametrize("N,k,M,seed,sigma", [
+    # one wave per chain: 256-thread blocks up to N = 682, one-wave blocks
+    # (LDS planes beyond 64 KiB) up to the largest N
+    (300, 8, 64, 41, 1.0), (700, 8, 24, 42, 1.0), (700, 16, 12, 43, 0.8),
+    (2_048, 8, 6, 44, 0.5), (6_144, 8, 3, 45, 0.5)])
+def test_real_long_chains(N, k, M, seed, sigma):
+    _, _, exact = _real_case(N, k, M, seed, sigma=sigma, bins=64)
+    assert exact
+
+
 def test_real_ideal_chain_and_bond_length():
     out, s, exact = _real_case(30, 8, 1_000, 12, b=1.5, sigma=0.0)
     assert exact
