@@ -358,16 +358,20 @@ static hipError_t launch_g(const GrowArgs &a, hipStream_t s)
 // binary64 planes of N beads within a CU's 160 KiB.
 int real_max_monomers() { return 6144; }
 
-// Trial-parallel groups of G >= k lanes for short chains; one wave per chain
-// beyond N = 256, where the culling pass over all 64 lanes dominates and one
-// chain's planes already take a large share of the LDS.
+// Lanes per chain: at least the next power of two >= k (one trial per
+// lane), and enough that the chains whose planes fit in a CU's LDS still
+// fill about 8 waves (G >= 0.075 N); the extra lanes share the culling pass.
 hipError_t launch_grow_real(const GrowArgs &a, hipStream_t s)
 {
     const int k = a.k_trials;
-    if (a.n_monomers > 256 || k > 32) return launch_g<64>(a, s);
-    if (k <= 8) return launch_g<8>(a, s);
-    if (k <= 16) return launch_g<16>(a, s);
-    return launch_g<32>(a, s);
+    const int N = a.n_monomers;
+    int need = k;
+    const int occ = (3 * N + 39) / 40; // ceil(0.075 N)
+    if (occ > need) need = occ;
+    if (need <= 8) return launch_g<8>(a, s);
+    if (need <= 16) return launch_g<16>(a, s);
+    if (need <= 32) return launch_g<32>(a, s);
+    return launch_g<64>(a, s);
 }
 
 } // namespace rsaw
