@@ -166,6 +166,38 @@ rsaw_status rsaw_gen_chains_sync(const rsaw_config *cfg, const rsaw_chain_out *o
                                  rsaw_summary *h_summary, double *d_hist_w,
                                  uint64_t *d_hist_n, void *stream);
 
+/*
+ * rsaw_gen_batch — grow and reduce n ensembles at once (the same method as
+ * rsaw_gen_chains, Sec. 3.3.2-3.3.3, Eqs. 2, 3 and 6, for each ensemble).
+ *
+ *   cfgs         host array of n configurations, each validated as for
+ *                rsaw_gen_chains before anything is enqueued; any geometry,
+ *                N, k and size may be mixed.
+ *   outs         host array of n rsaw_chain_out (device arrays; NULL
+ *                members are not written), or NULL for none.
+ *   d_summaries  device array of n rsaw_summary, or NULL to skip every
+ *                reduction.
+ *   d_hist_w,    host arrays of n device pointers (each as the d_hist_w /
+ *   d_hist_n     d_hist_n of rsaw_gen_chains, may be NULL), or NULL.
+ *   stream       hipStream_t or NULL.
+ *
+ * Every ensemble's per-chain outputs and summary are bit-identical to those
+ * of a separate rsaw_gen_chains call with the same configuration.  The
+ * ensembles share launches: one growth launch per kernel variant (geometry,
+ * size class and block shape), whose blocks map to (ensemble, chunk) through
+ * a prefix table, and three reduction launches for all of them, instead of
+ * four launches per ensemble.  The descriptor tables travel in one copy from
+ * a pinned host buffer of the library, reused per (device, stream): a call
+ * waits for the previous call's table copy on the same stream (not for its
+ * kernels).  Asynchronous otherwise.
+ * Errors: as rsaw_gen_chains, with the index of the first invalid ensemble
+ * in rsaw_last_error(); RSAW_E_INVALID for n < 0 or cfgs NULL with n > 0.
+ * n = 0 does nothing.
+ */
+rsaw_status rsaw_gen_batch(const rsaw_config *cfgs, const rsaw_chain_out *outs, int32_t n,
+                           rsaw_summary *d_summaries, double *const *d_hist_w,
+                           uint64_t *const *d_hist_n, void *stream);
+
 /* Static description of a status code. */
 const char *rsaw_status_string(rsaw_status s);
 

@@ -56,7 +56,7 @@ class rsaw_summary(C.Structure):
 SUMMARY_BYTES = C.sizeof(rsaw_summary)
 
 # Every symbol include/rsaw.h declares.
-EXPORTS = ["rsaw_gen_chains", "rsaw_gen_chains_sync", "rsaw_status_string",
+EXPORTS = ["rsaw_gen_chains", "rsaw_gen_chains_sync", "rsaw_gen_batch", "rsaw_status_string",
            "rsaw_last_error", "rsaw_version", "rsaw_kernel_timing", "rsaw_kernel_time",
            "rsaw_shutdown"]
 
@@ -87,6 +87,9 @@ def load(path: str = LIB_PATH):
         lib.rsaw_gen_chains_sync.argtypes = [C.POINTER(rsaw_config), C.POINTER(rsaw_chain_out),
                                              C.POINTER(rsaw_summary), vp, vp, vp]
         lib.rsaw_gen_chains_sync.restype = C.c_int
+        lib.rsaw_gen_batch.argtypes = [C.POINTER(rsaw_config), C.POINTER(rsaw_chain_out), C.c_int32,
+                                       vp, C.POINTER(vp), C.POINTER(vp), vp]
+        lib.rsaw_gen_batch.restype = C.c_int
         lib.rsaw_status_string.argtypes = [C.c_int]
         lib.rsaw_status_string.restype = C.c_char_p
         lib.rsaw_last_error.argtypes = []
@@ -145,25 +148,12 @@ def gen_chains_raw(cfg: rsaw_config, out: rsaw_chain_out | None, d_summary: int,
                                stream or None))
 
 
-def gen_chains(geometry, N, k, n_chains, seed, *, coord=None, chain_offset=0,
-               bond_length=1.0, bead_diameter=1.0, hist_bins=0, exact_w=False,
-               per_chain=True, device=None, stream=None, sync=True):
-    """Grow ``n_chains`` chains on the GPU and reduce them.
-
-    Returns ``(out, summary)``: ``out`` is a dict of device tensors (log_w,
-    r_end [3, M], r2, rg2, n_grown, and n2rg2 / w_exact on the lattice), empty
-    when ``per_chain`` is false; ``summary`` is a dict (host) when ``sync`` is
-    true, else the raw device uint8 tensor (parse with ``parse_summary``).
-    """
+def _alloc_outputs(cfg: rsaw_config, dev, per_chain: bool, hist_bins: int):
+    """Device tensors for one ensemble's per-chain outputs and histogram, and
+    the rsaw_chain_out that points at them."""
     import torch
 
-    if not torch.cuda.is_available():
-        raise RsawError(5, "no GPU: librsaw runs on MI355X only (no CPU fallback)")
-    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
-    cfg = make_config(geometry, N, k, n_chains, seed, coord=coord, chain_offset=chain_offset,
-                      bond_length=bond_length, bead_diameter=bead_diameter,
-                      hist_bins=hist_bins, exact_w=exact_w)
-    M = int(n_chains)
+    M = int(cfg.n_chains)
     lattice = cfg.geometry == RSAW_LATTICE_SC
     out = {}
     o = rsaw_chain_out()
@@ -179,26 +169,105 @@ def gen_chains(geometry, N, k, n_chains, seed, *, coord=None, chain_offset=0,
         if lattice:
             out["n2rg2"] = torch.empty(M, dtype=torch.int64, device=dev)
             o.n2rg2 = out["n2rg2"].data_ptr()
-            if exact_w:
+            if cfg.flags & RSAW_EXACT_W:
                 out["w_exact"] = torch.empty(M, dtype=torch.uint64, device=dev)
                 o.w_exact = out["w_exact"].data_ptr()
+    if hist_bins:
+        out["hist_w"] = torch.empty(hist_bins, dtype=torch.float64, device=dev)
+        out["hist_n"] = torch.empty(hist_bins, dtype=torch.uint64, device=dev)
+    return out, o
+
+
+def _device(device):
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RsawError(5, "no GPU: librsaw runs on MI355X only (no CPU fallback)")
+    return torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+
+
+def gen_chains(geometry, N, k, n_chains, seed, *, coord=None, chain_offset=0,
+               bond_length=1.0, bead_diameter=1.0, hist_bins=0, exact_w=False,
+               per_chain=True, device=None, stream=None, sync=True):
+    """Grow ``n_chains`` chains on the GPU and reduce them.
+
+    Returns ``(out, summary)``: ``out`` is a dict of device tensors (log_w,
+    r_end [3, M], r2, rg2, n_grown, and n2rg2 / w_exact on the lattice), empty
+    when ``per_chain`` is false; ``summary`` is a dict (host) when ``sync`` is
+    true, else the raw device uint8 tensor (parse with ``parse_summary``).
+    """
+    import torch
+
+    dev = _device(device)
+    cfg = make_config(geometry, N, k, n_chains, seed, coord=coord, chain_offset=chain_offset,
+                      bond_length=bond_length, bead_diameter=bead_diameter,
+                      hist_bins=hist_bins, exact_w=exact_w)
+    out, o = _alloc_outputs(cfg, dev, per_chain, hist_bins)
     summ = torch.empty(SUMMARY_BYTES, dtype=torch.uint8, device=dev)
-    hw = torch.empty(max(hist_bins, 0), dtype=torch.float64, device=dev) if hist_bins else None
-    hn = torch.empty(max(hist_bins, 0), dtype=torch.uint64, device=dev) if hist_bins else None
     if stream is None:
         stream = torch.cuda.current_stream(dev).cuda_stream
     with torch.cuda.device(dev):
-        gen_chains_raw(cfg, o, summ.data_ptr(), hw.data_ptr() if hw is not None else 0,
-                       hn.data_ptr() if hn is not None else 0, stream)
-    if hist_bins:
-        out["hist_w"] = hw
-        out["hist_n"] = hn
+        gen_chains_raw(cfg, o, summ.data_ptr(), out["hist_w"].data_ptr() if hist_bins else 0,
+                       out["hist_n"].data_ptr() if hist_bins else 0, stream)
     if not sync:
         return out, summ
     s = parse_summary(summ)
     if s["status"] != 0:
         raise RsawError(s["status"], "device reported a rejection-cap hit")
     return out, s
+
+
+def gen_batch_raw(cfgs, outs, d_summaries: int, hist_w=None, hist_n=None, stream: int = 0):
+    """Direct call of rsaw_gen_batch: lists of configs and chain-out structs,
+    a device address of len(cfgs) summaries (0 = none), and optional lists of
+    per-ensemble histogram device addresses (0 = NULL)."""
+    lib = load()
+    n = len(cfgs)
+    carr = (rsaw_config * max(n, 1))(*cfgs)
+    oarr = (rsaw_chain_out * max(n, 1))(*outs) if outs is not None else None
+    hw = (C.c_void_p * max(n, 1))(*[p or None for p in hist_w]) if hist_w is not None else None
+    hn = (C.c_void_p * max(n, 1))(*[p or None for p in hist_n]) if hist_n is not None else None
+    _check(lib.rsaw_gen_batch(carr, oarr, n, d_summaries or None, hw, hn, stream or None))
+
+
+def gen_batch(specs, *, per_chain=True, device=None, stream=None, sync=True):
+    """Grow and reduce several ensembles with one rsaw_gen_batch call.
+
+    ``specs`` is a list of dicts with the arguments of ``gen_chains``
+    (geometry, N, k, n_chains, seed and the optional keywords).  Returns a
+    list of ``(out, summary)`` pairs as ``gen_chains`` does; with ``sync``
+    false the summaries are the raw device tensor of all of them.
+    """
+    import torch
+
+    dev = _device(device)
+    cfgs, outs, allocs = [], [], []
+    for sp in specs:
+        sp = dict(sp)
+        bins = int(sp.get("hist_bins", 0))
+        cfg = make_config(sp.pop("geometry"), sp.pop("N"), sp.pop("k"), sp.pop("n_chains"),
+                          sp.pop("seed"), **sp)
+        out, o = _alloc_outputs(cfg, dev, per_chain, bins)
+        cfgs.append(cfg)
+        outs.append(o)
+        allocs.append(out)
+    n = len(cfgs)
+    summ = torch.empty(max(n, 1) * SUMMARY_BYTES, dtype=torch.uint8, device=dev)
+    hist_w = [a["hist_w"].data_ptr() if "hist_w" in a else 0 for a in allocs]
+    hist_n = [a["hist_n"].data_ptr() if "hist_n" in a else 0 for a in allocs]
+    if stream is None:
+        stream = torch.cuda.current_stream(dev).cuda_stream
+    with torch.cuda.device(dev):
+        gen_batch_raw(cfgs, outs, summ.data_ptr(), hist_w, hist_n, stream)
+    if not sync:
+        return allocs, summ
+    res = []
+    for i, out in enumerate(allocs):
+        s = parse_summary(summ[i * SUMMARY_BYTES:(i + 1) * SUMMARY_BYTES])
+        if s["status"] != 0:
+            raise RsawError(s["status"], f"ensemble {i}: device reported a rejection-cap hit")
+        res.append((out, s))
+    return res
 
 
 def version() -> int:

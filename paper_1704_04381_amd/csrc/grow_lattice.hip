@@ -46,7 +46,7 @@ __device__ __forceinline__ void static_for(F &&f)
 constexpr uint32_t kOrigin = 0x80808000u; // origin, Q = 0
 
 template <int NMAX, bool EXACT, typename CT>
-__global__ __launch_bounds__(256) void grow_lattice_reg(GrowArgs a)
+__device__ __forceinline__ void grow_lattice_reg_body(const GrowArgs &a, uint64_t bid)
 {
     __shared__ uint32_t lut[kLutSize];
     __shared__ double logm[8];
@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void grow_lattice_reg(GrowArgs a)
     if (threadIdx.x < 8) logm[threadIdx.x] = a.logm[threadIdx.x];
     __syncthreads();
 
-    const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t c = bid * blockDim.x + threadIdx.x;
     const bool valid = c < a.n_chains;
     const uint64_t g = a.chain_offset + c;
     const int N = a.n_monomers;
@@ -171,6 +171,20 @@ __global__ __launch_bounds__(256) void grow_lattice_reg(GrowArgs a)
 }
 
 template <int NMAX, bool EXACT, typename CT>
+__global__ __launch_bounds__(256) void grow_lattice_reg(GrowArgs a)
+{
+    grow_lattice_reg_body<NMAX, EXACT, CT>(a, blockIdx.x);
+}
+
+// Batched launch: block b serves the ensemble whose block range holds b.
+template <int NMAX, bool EXACT, typename CT>
+__global__ __launch_bounds__(256) void grow_lattice_reg_batch(const GrowEntry *tab, const uint64_t *block0, int n)
+{
+    const int e = find_segment(block0, n, blockIdx.x);
+    grow_lattice_reg_body<NMAX, EXACT, CT>(tab[e].a, blockIdx.x - block0[e]);
+}
+
+template <int NMAX, bool EXACT, typename CT>
 static hipError_t launch(const GrowArgs &a, hipStream_t s)
 {
     const uint64_t blocks = (a.n_chains + 255) / 256;
@@ -193,6 +207,48 @@ hipError_t launch_grow_lattice(const GrowArgs &a, bool exact, bool i16, hipStrea
     if (N <= 16) return i16 ? launch<16, false, int16_t>(a, s) : launch<16, false, int32_t>(a, s);
     if (N <= 32) return i16 ? launch<32, false, int16_t>(a, s) : launch<32, false, int32_t>(a, s);
     return i16 ? launch<64, false, int16_t>(a, s) : launch<64, false, int32_t>(a, s);
+}
+
+// Variant of the register kernel for one ensemble (N <= 64, or exact weights).
+void lattice_reg_variant(const GrowArgs &a, bool exact, bool i16, GrowVariant *v)
+{
+    const int N = a.n_monomers;
+    v->family = 0;
+    v->p0 = exact ? (N <= 16 ? 16 : 32) : (N <= 16 ? 16 : (N <= 32 ? 32 : 64));
+    v->p1 = exact ? 1 : 0;
+    v->p2 = i16 ? 1 : 0;
+    v->threads = 256;
+    v->cpb = 256;
+    v->shmem = 0;
+    v->H = 0;
+    v->S = 0;
+}
+
+template <int NMAX, bool EXACT, typename CT>
+static hipError_t launch_batch(const GrowEntry *tab, const uint64_t *block0, int n, uint64_t blocks,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL((grow_lattice_reg_batch<NMAX, EXACT, CT>), dim3((uint32_t)blocks), dim3(256), 0, s,
+                       tab, block0, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_lattice_reg_batch(const GrowVariant &v, const GrowEntry *tab, const uint64_t *block0,
+                                    int n, uint64_t blocks, hipStream_t s)
+{
+    const bool i16 = v.p2 != 0;
+    if (v.p1) {
+        if (v.p0 == 16) return i16 ? launch_batch<16, true, int16_t>(tab, block0, n, blocks, s)
+                                   : launch_batch<16, true, int32_t>(tab, block0, n, blocks, s);
+        return i16 ? launch_batch<32, true, int16_t>(tab, block0, n, blocks, s)
+                   : launch_batch<32, true, int32_t>(tab, block0, n, blocks, s);
+    }
+    if (v.p0 == 16) return i16 ? launch_batch<16, false, int16_t>(tab, block0, n, blocks, s)
+                               : launch_batch<16, false, int32_t>(tab, block0, n, blocks, s);
+    if (v.p0 == 32) return i16 ? launch_batch<32, false, int16_t>(tab, block0, n, blocks, s)
+                               : launch_batch<32, false, int32_t>(tab, block0, n, blocks, s);
+    return i16 ? launch_batch<64, false, int16_t>(tab, block0, n, blocks, s)
+               : launch_batch<64, false, int32_t>(tab, block0, n, blocks, s);
 }
 
 } // namespace rsaw

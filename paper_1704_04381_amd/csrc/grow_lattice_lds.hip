@@ -82,7 +82,7 @@ __device__ __forceinline__ uint32_t pair_bits(uint32_t wa, uint32_t wb, uint32_t
 }
 
 template <int G, bool WIDE, typename CT>
-__global__ __launch_bounds__(256) void grow_lattice_lds(GrowArgs a, int H, int S)
+__device__ __forceinline__ void grow_lattice_lds_body(const GrowArgs &a, uint64_t bid, int H, int S)
 {
     constexpr int WPM = WIDE ? 2 : 1; // words per monomer
     const int cpb = blockDim.x / G;   // chains per block
@@ -108,7 +108,7 @@ __global__ __launch_bounds__(256) void grow_lattice_lds(GrowArgs a, int H, int S
 
     const int t = threadIdx.x & (G - 1);
     const int chb = threadIdx.x / G;
-    const uint64_t c = (uint64_t)blockIdx.x * cpb + chb;
+    const uint64_t c = bid * cpb + chb;
     const bool valid = c < a.n_chains;
     const uint64_t g = a.chain_offset + c;
     const int N = a.n_monomers;
@@ -270,46 +270,106 @@ __global__ __launch_bounds__(256) void grow_lattice_lds(GrowArgs a, int H, int S
 }
 
 template <int G, bool WIDE, typename CT>
-static hipError_t launch_lds(const GrowArgs &a, hipStream_t s)
+__global__ __launch_bounds__(256) void grow_lattice_lds(GrowArgs a, int H, int S)
 {
-    constexpr int WPM = WIDE ? 2 : 1;
-    const int half = (a.n_monomers + 1) / 2;
+    grow_lattice_lds_body<G, WIDE, CT>(a, blockIdx.x, H, S);
+}
+
+// Batched launch: block b serves the ensemble whose block range holds b.
+template <int G, bool WIDE, typename CT>
+__global__ __launch_bounds__(256) void grow_lattice_lds_batch(const GrowEntry *tab, const uint64_t *block0,
+                                                              int n)
+{
+    const int e = find_segment(block0, n, blockIdx.x);
+    grow_lattice_lds_body<G, WIDE, CT>(tab[e].a, blockIdx.x - block0[e], tab[e].H, tab[e].S);
+}
+
+// Largest lattice chain of the LDS kernel (wide words: 128 KiB per chain).
+int lattice_lds_max_monomers() { return 16384; }
+
+// Variant for 64 < N <= 16384.  G grows with N so that one wave's chains take
+// at most ~17 KiB of LDS (8 waves per CU) up to N = 2048; four waves per
+// block share the move table when the block fits in half a CU's LDS.
+hipError_t lattice_lds_variant(const GrowArgs &a, bool i16, GrowVariant *v)
+{
+    const int N = a.n_monomers;
+    int G, wide;
+    if (N <= 128) { G = 4; wide = 0; }
+    else if (N <= 256) { G = 8; wide = 1; }
+    else if (N <= 512) { G = 16; wide = 1; }
+    else if (N <= 1024) { G = 32; wide = 1; }
+    else { G = 64; wide = 1; }
+    const int WPM = wide ? 2 : 1;
+    const int half = (N + 1) / 2;
     const int H = (half + 4 * G - 1) / (4 * G) * (4 * G);
     // chain stride: pad so that the chains of a wave start on different banks
     const int S = 2 * WPM * H + (4 * G < 64 ? 4 * G : 0);
     auto bytes = [&](int threads) {
         return ((size_t)WPM * kLutSize + (size_t)(threads / G) * S) * sizeof(uint32_t);
     };
-    // four waves per block share the move table when they fit in half the
-    // LDS of a CU; one wave otherwise
     const int threads = bytes(256) <= 81920 ? 256 : 64;
-    const size_t shmem = bytes(threads);
-    if (shmem > 163840) return hipErrorInvalidValue;
+    if (bytes(threads) > 163840) return hipErrorInvalidValue;
+    v->family = 1;
+    v->p0 = G;
+    v->p1 = wide;
+    v->p2 = i16 ? 1 : 0;
+    v->threads = threads;
+    v->cpb = threads / G;
+    v->shmem = bytes(threads);
+    v->H = H;
+    v->S = S;
+    return hipSuccess;
+}
+
+template <int G, bool WIDE, typename CT>
+static hipError_t launch_lds(const GrowArgs &a, const GrowVariant &v, const GrowEntry *tab,
+                             const uint64_t *block0, int n, uint64_t blocks, size_t shmem, hipStream_t s)
+{
+    const void *fn = tab ? (const void *)grow_lattice_lds_batch<G, WIDE, CT>
+                         : (const void *)grow_lattice_lds<G, WIDE, CT>;
     if (shmem > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void *)grow_lattice_lds<G, WIDE, CT>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
         if (e != hipSuccess) return e;
     }
-    const int cpb = threads / G;
-    const uint64_t blocks = (a.n_chains + cpb - 1) / cpb;
-    hipLaunchKernelGGL((grow_lattice_lds<G, WIDE, CT>), dim3((uint32_t)blocks), dim3(threads), shmem, s,
-                       a, H, S);
+    if (tab)
+        hipLaunchKernelGGL((grow_lattice_lds_batch<G, WIDE, CT>), dim3((uint32_t)blocks), dim3(v.threads),
+                           shmem, s, tab, block0, n);
+    else
+        hipLaunchKernelGGL((grow_lattice_lds<G, WIDE, CT>), dim3((uint32_t)blocks), dim3(v.threads), shmem, s,
+                           a, v.H, v.S);
     return hipGetLastError();
 }
 
-// Largest lattice chain of the LDS kernel (wide words: 128 KiB per chain).
-int lattice_lds_max_monomers() { return 16384; }
+static hipError_t dispatch_lds(const GrowArgs &a, const GrowVariant &v, const GrowEntry *tab,
+                               const uint64_t *block0, int n, uint64_t blocks, size_t shmem, hipStream_t s)
+{
+    const bool i16 = v.p2 != 0;
+#define RSAW_LDS(G, W)                                                                                \
+    return i16 ? launch_lds<G, W, int16_t>(a, v, tab, block0, n, blocks, shmem, s)                    \
+               : launch_lds<G, W, int32_t>(a, v, tab, block0, n, blocks, shmem, s)
+    switch (v.p0) {
+    case 4: RSAW_LDS(4, false);
+    case 8: RSAW_LDS(8, true);
+    case 16: RSAW_LDS(16, true);
+    case 32: RSAW_LDS(32, true);
+    default: RSAW_LDS(64, true);
+    }
+#undef RSAW_LDS
+}
 
-// Launch for 64 < N <= 16384.  G grows with N so that one wave's chains take
-// at most ~17 KiB of LDS (8 waves per CU) up to N = 2048.
 hipError_t launch_grow_lattice_lds(const GrowArgs &a, bool i16, hipStream_t s)
 {
-    const int N = a.n_monomers;
-    if (N <= 128) return i16 ? launch_lds<4, false, int16_t>(a, s) : launch_lds<4, false, int32_t>(a, s);
-    if (N <= 256) return i16 ? launch_lds<8, true, int16_t>(a, s) : launch_lds<8, true, int32_t>(a, s);
-    if (N <= 512) return i16 ? launch_lds<16, true, int16_t>(a, s) : launch_lds<16, true, int32_t>(a, s);
-    if (N <= 1024) return i16 ? launch_lds<32, true, int16_t>(a, s) : launch_lds<32, true, int32_t>(a, s);
-    return i16 ? launch_lds<64, true, int16_t>(a, s) : launch_lds<64, true, int32_t>(a, s);
+    GrowVariant v;
+    hipError_t e = lattice_lds_variant(a, i16, &v);
+    if (e != hipSuccess) return e;
+    const uint64_t blocks = (a.n_chains + v.cpb - 1) / v.cpb;
+    return dispatch_lds(a, v, nullptr, nullptr, 0, blocks, v.shmem, s);
+}
+
+hipError_t launch_lattice_lds_batch(const GrowVariant &v, const GrowEntry *tab, const uint64_t *block0,
+                                    int n, uint64_t blocks, size_t shmem, hipStream_t s)
+{
+    return dispatch_lds(GrowArgs{}, v, tab, block0, n, blocks, shmem, s);
 }
 
 } // namespace rsaw

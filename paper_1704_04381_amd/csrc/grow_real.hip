@@ -88,7 +88,7 @@ __device__ __forceinline__ void wave_sync()
 __host__ __device__ inline int plane_row(int cpb, int G) { return G == 64 ? (cpb | 1) : cpb; }
 
 template <int G>
-__global__ __launch_bounds__(256) void grow_real_tp(GrowArgs a)
+__device__ __forceinline__ void grow_real_body(const GrowArgs &a, uint64_t bid)
 {
     extern __shared__ double lds[]; // X, Y, Z planes of [N][row], swizzled
     __shared__ double logm[65];
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void grow_real_tp(GrowArgs a)
     // element of bead j of this chain in a plane
     const auto at = [&](int j) { return j * row + (chb ^ ((j * swz_mul) & swz_mask)); };
     const uint64_t gmask_bits = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
-    const uint64_t c = (uint64_t)blockIdx.x * cpb + chb;
+    const uint64_t c = bid * cpb + chb;
     const bool valid = c < a.n_chains;
     const uint64_t g = a.chain_offset + c;
     const int k = a.k_trials;
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(256) void grow_real_tp(GrowArgs a)
             const uint32_t jh = (uint32_t)(((float)lane + 0.5f) * __builtin_amdgcn_rcpf((float)nF));
             const uint32_t q = (uint32_t)lane - jh * nF;
             const int owner = __builtin_amdgcn_ds_bpermute((int)(q * 4u), owner_of_q);
-            const uint64_t og = a.chain_offset + (uint64_t)blockIdx.x * cpb +
+            const uint64_t og = a.chain_offset + bid * cpb +
                                 (uint64_t)(((threadIdx.x & ~63) + (owner & ~(G - 1))) / G);
             double h1 = 0.0, h2 = 0.0, hs = 0.5;
             const bool hok = marsaglia_try(draw(a.seed, og, (uint32_t)i, (uint32_t)(owner & (G - 1)), 1u + jh),
@@ -332,26 +332,17 @@ __global__ __launch_bounds__(256) void grow_real_tp(GrowArgs a)
 }
 
 template <int G>
-static hipError_t launch_g(const GrowArgs &a, hipStream_t s)
+__global__ __launch_bounds__(256) void grow_real_tp(GrowArgs a)
 {
-    // 256-thread blocks when the bead planes fit in half a CU's LDS, else
-    // one wave per block (up to the whole 160 KiB)
-    auto planes = [&](int threads) {
-        return (size_t)3 * a.n_monomers * plane_row(threads / G, G) * sizeof(double);
-    };
-    int threads = 256;
-    if (planes(threads) > 81920) threads = 64;
-    const size_t shmem = planes(threads);
-    if (shmem + 65 * sizeof(double) > 163840) return hipErrorInvalidValue;
-    if (shmem > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void *)grow_real_tp<G>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-        if (e != hipSuccess) return e;
-    }
-    const int cpb = threads / G;
-    const uint64_t blocks = (a.n_chains + cpb - 1) / cpb;
-    hipLaunchKernelGGL((grow_real_tp<G>), dim3((uint32_t)blocks), dim3(threads), shmem, s, a);
-    return hipGetLastError();
+    grow_real_body<G>(a, blockIdx.x);
+}
+
+// Batched launch: block b serves the ensemble whose block range holds b.
+template <int G>
+__global__ __launch_bounds__(256) void grow_real_tp_batch(const GrowEntry *tab, const uint64_t *block0, int n)
+{
+    const int e = find_segment(block0, n, blockIdx.x);
+    grow_real_body<G>(tab[e].a, blockIdx.x - block0[e]);
 }
 
 // Largest bead count of the LDS-resident kernel: one chain per wave, three
@@ -361,17 +352,74 @@ int real_max_monomers() { return 6144; }
 // Lanes per chain: at least the next power of two >= k (one trial per
 // lane), and enough that the chains whose planes fit in a CU's LDS still
 // fill about 8 waves (G >= 0.075 N); the extra lanes share the culling pass.
-hipError_t launch_grow_real(const GrowArgs &a, hipStream_t s)
+// 256-thread blocks when the bead planes fit in half a CU's LDS, else one
+// wave per block (up to the whole 160 KiB).
+hipError_t real_variant(const GrowArgs &a, GrowVariant *v)
 {
-    const int k = a.k_trials;
     const int N = a.n_monomers;
-    int need = k;
+    int need = a.k_trials;
     const int occ = (3 * N + 39) / 40; // ceil(0.075 N)
     if (occ > need) need = occ;
-    if (need <= 8) return launch_g<8>(a, s);
-    if (need <= 16) return launch_g<16>(a, s);
-    if (need <= 32) return launch_g<32>(a, s);
-    return launch_g<64>(a, s);
+    const int G = need <= 8 ? 8 : (need <= 16 ? 16 : (need <= 32 ? 32 : 64));
+    auto planes = [&](int threads) {
+        return (size_t)3 * N * plane_row(threads / G, G) * sizeof(double);
+    };
+    int threads = 256;
+    if (planes(threads) > 81920) threads = 64;
+    if (planes(threads) + 65 * sizeof(double) > 163840) return hipErrorInvalidValue;
+    v->family = 2;
+    v->p0 = G;
+    v->p1 = 0;
+    v->p2 = 0;
+    v->threads = threads;
+    v->cpb = threads / G;
+    v->shmem = planes(threads);
+    v->H = 0;
+    v->S = 0;
+    return hipSuccess;
+}
+
+template <int G>
+static hipError_t launch_g(const GrowArgs &a, const GrowVariant &v, const GrowEntry *tab,
+                           const uint64_t *block0, int n, uint64_t blocks, size_t shmem, hipStream_t s)
+{
+    const void *fn = tab ? (const void *)grow_real_tp_batch<G> : (const void *)grow_real_tp<G>;
+    if (shmem > 65536) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+        if (e != hipSuccess) return e;
+    }
+    if (tab)
+        hipLaunchKernelGGL((grow_real_tp_batch<G>), dim3((uint32_t)blocks), dim3(v.threads), shmem, s, tab,
+                           block0, n);
+    else
+        hipLaunchKernelGGL((grow_real_tp<G>), dim3((uint32_t)blocks), dim3(v.threads), shmem, s, a);
+    return hipGetLastError();
+}
+
+static hipError_t dispatch_real(const GrowArgs &a, const GrowVariant &v, const GrowEntry *tab,
+                                const uint64_t *block0, int n, uint64_t blocks, size_t shmem, hipStream_t s)
+{
+    switch (v.p0) {
+    case 8: return launch_g<8>(a, v, tab, block0, n, blocks, shmem, s);
+    case 16: return launch_g<16>(a, v, tab, block0, n, blocks, shmem, s);
+    case 32: return launch_g<32>(a, v, tab, block0, n, blocks, shmem, s);
+    default: return launch_g<64>(a, v, tab, block0, n, blocks, shmem, s);
+    }
+}
+
+hipError_t launch_grow_real(const GrowArgs &a, hipStream_t s)
+{
+    GrowVariant v;
+    hipError_t e = real_variant(a, &v);
+    if (e != hipSuccess) return e;
+    const uint64_t blocks = (a.n_chains + v.cpb - 1) / v.cpb;
+    return dispatch_real(a, v, nullptr, nullptr, 0, blocks, v.shmem, s);
+}
+
+hipError_t launch_real_batch(const GrowVariant &v, const GrowEntry *tab, const uint64_t *block0, int n,
+                             uint64_t blocks, size_t shmem, hipStream_t s)
+{
+    return dispatch_real(GrowArgs{}, v, tab, block0, n, blocks, shmem, s);
 }
 
 } // namespace rsaw

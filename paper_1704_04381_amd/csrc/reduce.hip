@@ -65,7 +65,7 @@ __device__ __forceinline__ void split_limbs(double w, uint64_t &l0, uint64_t &l1
     l2 = (uint64_t)f2;
 }
 
-__global__ __launch_bounds__(kRT) void reduce_partials(ReduceArgs a)
+__device__ __forceinline__ void reduce_partials_body(const ReduceArgs &a, uint64_t bid)
 {
     extern __shared__ unsigned char smem[];
     ThreadSums *ts = (ThreadSums *)smem;                                   // [kRT]
@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kRT) void reduce_partials(ReduceArgs a)
 
     const double L = __longlong_as_double((long long)*a.lmax_bits);
     const double nsq1 = (double)(a.n_monomers - 1) * (double)(a.n_monomers - 1) + 1.0;
-    const uint64_t begin = (uint64_t)blockIdx.x * a.chunk;
+    const uint64_t begin = bid * a.chunk;
     uint64_t end = begin + a.chunk;
     if (end > a.n_chains) end = a.n_chains;
 
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(kRT) void reduce_partials(ReduceArgs a)
         __syncthreads();
     }
     if (tid == 0) {
-        BlockPartial &bp = a.partials[blockIdx.x];
+        BlockPartial &bp = a.partials[bid];
         for (int q = 0; q < kNumSums; ++q) bp.s[q] = ts[0].s[q];
         bp.alive = ts[0].alive;
         bp.steps = ts[0].steps;
@@ -142,9 +142,13 @@ __global__ __launch_bounds__(kRT) void reduce_partials(ReduceArgs a)
     }
 }
 
-__global__ __launch_bounds__(kRT) void reduce_final(ReduceArgs a, uint32_t n_blocks,
-                                                     rsaw_summary *out, double *hist_w,
-                                                     uint64_t *hist_n)
+__global__ __launch_bounds__(kRT) void reduce_partials(ReduceArgs a)
+{
+    reduce_partials_body(a, blockIdx.x);
+}
+
+__device__ __forceinline__ void reduce_final_body(const ReduceArgs &a, uint32_t n_blocks, rsaw_summary *out,
+                                                  double *hist_w, uint64_t *hist_n)
 {
     __shared__ ThreadSums ts[kRT];
     const int tid = threadIdx.x;
@@ -211,6 +215,35 @@ __global__ __launch_bounds__(kRT) void reduce_final(ReduceArgs a, uint32_t n_blo
     }
 }
 
+__global__ __launch_bounds__(kRT) void reduce_final(ReduceArgs a, uint32_t n_blocks, rsaw_summary *out,
+                                                     double *hist_w, uint64_t *hist_n)
+{
+    reduce_final_body(a, n_blocks, out, hist_w, hist_n);
+}
+
+// Batched forms: one entry per ensemble.
+__global__ void reduce_init_batch(const ReduceEntry *tab, int n)
+{
+    const ReduceEntry &e = tab[blockIdx.x];
+    if (threadIdx.x == 0) {
+        *e.lmax = 0ull;
+        *e.status = 0;
+    }
+    for (int q = threadIdx.x; q < 4 * e.r.bins; q += blockDim.x) e.r.hist_acc[q] = 0ull;
+}
+
+__global__ __launch_bounds__(kRT) void reduce_partials_batch(const ReduceEntry *tab, const uint64_t *block0, int n)
+{
+    const int e = find_segment(block0, n, blockIdx.x);
+    reduce_partials_body(tab[e].r, blockIdx.x - block0[e]);
+}
+
+__global__ __launch_bounds__(kRT) void reduce_final_batch(const ReduceEntry *tab, int n)
+{
+    const ReduceEntry &e = tab[blockIdx.x];
+    reduce_final_body(e.r, e.n_blocks, e.out, e.hist_w, e.hist_n);
+}
+
 size_t reduce_partials_shmem(int bins)
 {
     return sizeof(ThreadSums) * kRT + (size_t)4 * bins * sizeof(unsigned long long);
@@ -232,6 +265,24 @@ hipError_t launch_reduce_init(unsigned long long *lmax_bits, int32_t *status,
                               unsigned long long *hist_acc, int n_acc, hipStream_t s)
 {
     hipLaunchKernelGGL(reduce_init, dim3(4), dim3(256), 0, s, lmax_bits, status, hist_acc, n_acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_batch(const ReduceEntry *tab, const uint64_t *block0, int n, uint64_t total_blocks,
+                               int max_bins, hipStream_t s, bool init_only)
+{
+    if (n <= 0) return hipSuccess;
+    if (init_only) {
+        hipLaunchKernelGGL(reduce_init_batch, dim3((uint32_t)n), dim3(256), 0, s, tab, n);
+        return hipGetLastError();
+    }
+    if (total_blocks > 0) {
+        hipLaunchKernelGGL(reduce_partials_batch, dim3((uint32_t)total_blocks), dim3(kRT),
+                           reduce_partials_shmem(max_bins), s, tab, block0, n);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(reduce_final_batch, dim3((uint32_t)n), dim3(kRT), 0, s, tab, n);
     return hipGetLastError();
 }
 

@@ -1,10 +1,13 @@
 // C ABI of librsaw (declared in include/rsaw.h): argument validation,
 // per-(device, stream) workspace, and the launch sequence
-//   reduce_init -> grow_{lattice,real} -> reduce_partials -> reduce_final.
+//   reduce_init -> grow_{lattice,real} -> reduce_partials -> reduce_final,
+// one ensemble per call or a batch of ensembles sharing the launches.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
+#include <tuple>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -21,6 +24,15 @@ hipError_t launch_grow_lattice(const GrowArgs &a, bool exact, bool i16, hipStrea
 hipError_t launch_grow_real(const GrowArgs &a, hipStream_t s);
 int real_max_monomers();
 int lattice_lds_max_monomers();
+void lattice_reg_variant(const GrowArgs &a, bool exact, bool i16, GrowVariant *v);
+hipError_t lattice_lds_variant(const GrowArgs &a, bool i16, GrowVariant *v);
+hipError_t real_variant(const GrowArgs &a, GrowVariant *v);
+hipError_t launch_lattice_reg_batch(const GrowVariant &v, const GrowEntry *tab, const uint64_t *block0,
+                                    int n, uint64_t blocks, hipStream_t s);
+hipError_t launch_lattice_lds_batch(const GrowVariant &v, const GrowEntry *tab, const uint64_t *block0,
+                                    int n, uint64_t blocks, size_t shmem, hipStream_t s);
+hipError_t launch_real_batch(const GrowVariant &v, const GrowEntry *tab, const uint64_t *block0, int n,
+                             uint64_t blocks, size_t shmem, hipStream_t s);
 } // namespace rsaw
 
 namespace {
@@ -43,6 +55,9 @@ rsaw_status hip_fail(hipError_t e, const char *what)
 struct Workspace {
     void *base = nullptr;
     size_t bytes = 0;
+    void *stage = nullptr;      // pinned host staging of batch descriptor tables
+    size_t stage_bytes = 0;
+    hipEvent_t stage_done = nullptr; // recorded after the last copy out of `stage`
 };
 
 std::mutex g_ws_lock;
@@ -70,6 +85,39 @@ rsaw_status workspace(int dev, hipStream_t s, size_t need, void **out)
         w.bytes = sz;
     }
     *out = w.base;
+    return RSAW_OK;
+}
+
+// Pinned host buffer of at least `need` bytes for the batch tables of
+// (dev, s), free for writing: waits for the previous copy out of it.
+rsaw_status staging(int dev, hipStream_t s, size_t need, void **out, hipEvent_t *done)
+{
+    std::lock_guard<std::mutex> lk(g_ws_lock);
+    Workspace &w = g_ws[{dev, (void *)s}];
+    if (w.stage_done) {
+        hipError_t e = hipEventSynchronize(w.stage_done);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    } else {
+        hipError_t e = hipEventCreateWithFlags(&w.stage_done, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    }
+    if (w.stage_bytes < need) {
+        if (w.stage) {
+            hipError_t e = hipHostFree(w.stage);
+            if (e != hipSuccess) return hip_fail(e, "hipHostFree");
+            w.stage = nullptr;
+            w.stage_bytes = 0;
+        }
+        size_t sz = need < ((size_t)1 << 16) ? ((size_t)1 << 16) : need;
+        hipError_t e = hipHostMalloc(&w.stage, sz, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            w.stage = nullptr;
+            return fail(RSAW_E_NOMEM, std::string("staging hipHostMalloc: ") + hipGetErrorString(e));
+        }
+        w.stage_bytes = sz;
+    }
+    *out = w.stage;
+    *done = w.stage_done;
     return RSAW_OK;
 }
 
@@ -171,9 +219,126 @@ rsaw_status validate(const rsaw_config *cfg)
     return RSAW_OK;
 }
 
-// Shared body of the entry points.  With force_reduce the summary goes to the
-// workspace when the caller gives no device summary; *used_summary receives
-// the device address the summary was written to (or NULL).
+// Per-ensemble layout of the workspace: reduction cells, block partials,
+// histogram accumulators and the per-chain arrays the reduction needs when
+// the caller does not supply them.
+struct EnsLayout {
+    bool lattice, exact, reduce;
+    int bins;
+    uint32_t n_blocks; // reduce blocks
+    uint64_t chunk;    // chains per reduce block
+    size_t off_lmax, off_status, off_summary, off_part, off_hacc;
+    size_t off_lw, off_r2, off_rg2, off_ng, off_wx, off_nn;
+    bool need_lw, need_r2, need_rg2, need_ng, need_wx, need_nn;
+};
+
+// Appends the ensemble's regions at *off (bytes, 256-aligned).
+void layout_ensemble(const rsaw_config *cfg, const rsaw_chain_out &o, bool reduce, size_t *off,
+                     EnsLayout *L)
+{
+    const uint64_t M = cfg->n_chains;
+    L->lattice = cfg->geometry == RSAW_LATTICE_SC;
+    L->exact = L->lattice && (cfg->flags & RSAW_EXACT_W);
+    L->reduce = reduce;
+    L->bins = reduce ? cfg->hist_bins : 0;
+    // reduce blocks: at most 1024, each a contiguous run of whole 256-chain tiles
+    L->n_blocks = 0;
+    L->chunk = 256;
+    if (M > 0) {
+        const uint64_t tiles = (M + 255) / 256;
+        const uint64_t nb = tiles < 1024 ? tiles : 1024;
+        L->chunk = ((tiles + nb - 1) / nb) * 256;
+        L->n_blocks = (uint32_t)((M + L->chunk - 1) / L->chunk);
+    }
+    size_t x = *off;
+    L->off_lmax = x; x = align256(x + sizeof(unsigned long long));
+    L->off_status = x; x = align256(x + sizeof(int32_t));
+    L->off_summary = x; x = align256(x + sizeof(rsaw_summary));
+    L->off_part = x; x = align256(x + (size_t)L->n_blocks * sizeof(rsaw::BlockPartial));
+    L->off_hacc = x; x = align256(x + (size_t)4 * L->bins * sizeof(unsigned long long));
+    L->need_lw = reduce && !o.log_w;
+    L->need_r2 = reduce && !o.r2;
+    L->need_rg2 = reduce && !o.rg2;
+    L->need_ng = reduce && !o.n_grown;
+    L->need_wx = reduce && L->exact && !o.w_exact;
+    L->need_nn = reduce && L->exact && !o.n2rg2;
+    L->off_lw = x; if (L->need_lw) x = align256(x + M * sizeof(double));
+    L->off_r2 = x; if (L->need_r2) x = align256(x + M * sizeof(double));
+    L->off_rg2 = x; if (L->need_rg2) x = align256(x + M * sizeof(double));
+    L->off_ng = x; if (L->need_ng) x = align256(x + M * sizeof(uint16_t));
+    L->off_wx = x; if (L->need_wx) x = align256(x + M * sizeof(uint64_t));
+    L->off_nn = x; if (L->need_nn) x = align256(x + M * sizeof(int64_t));
+    *off = x;
+}
+
+// The per-chain arrays the kernels write: the caller's, completed with
+// workspace arrays where the reduction needs them.
+rsaw_chain_out bind_outputs(const rsaw_chain_out &in, const EnsLayout &L, char *ws)
+{
+    rsaw_chain_out o = in;
+    if (L.need_lw) o.log_w = (double *)(ws + L.off_lw);
+    if (L.need_r2) o.r2 = (double *)(ws + L.off_r2);
+    if (L.need_rg2) o.rg2 = (double *)(ws + L.off_rg2);
+    if (L.need_ng) o.n_grown = (uint16_t *)(ws + L.off_ng);
+    if (L.need_wx) o.w_exact = (uint64_t *)(ws + L.off_wx);
+    if (L.need_nn) o.n2rg2 = (int64_t *)(ws + L.off_nn);
+    if (!L.lattice) o.n2rg2 = nullptr;
+    if (!L.exact) o.w_exact = nullptr;
+    return o;
+}
+
+rsaw::GrowArgs grow_args(const rsaw_config *cfg, const rsaw_chain_out &o, const EnsLayout &L, char *ws)
+{
+    rsaw::GrowArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.seed = cfg->seed;
+    a.chain_offset = cfg->chain_offset;
+    a.n_chains = cfg->n_chains;
+    a.n_monomers = cfg->n_monomers;
+    a.k_trials = cfg->k_trials;
+    a.bond_length = cfg->bond_length;
+    a.sigma2 = cfg->bead_diameter * cfg->bead_diameter;
+    const double bs = cfg->bond_length + cfg->bead_diameter;
+    a.cull2 = bs * bs * (1.0 + 0x1p-30);
+    a.log_w = o.log_w;
+    a.w_exact = o.w_exact;
+    a.r_end = o.r_end;
+    a.r2 = o.r2;
+    a.rg2 = o.rg2;
+    a.n2rg2 = o.n2rg2;
+    a.n_grown = o.n_grown;
+    a.log_w_max_bits = (unsigned long long *)(ws + L.off_lmax);
+    a.status = (int32_t *)(ws + L.off_status);
+    std::memcpy(a.logm, logm_table(), sizeof(a.logm));
+    return a;
+}
+
+rsaw::ReduceArgs reduce_args(const rsaw_config *cfg, const rsaw_chain_out &o, const EnsLayout &L, char *ws)
+{
+    rsaw::ReduceArgs r;
+    std::memset(&r, 0, sizeof(r));
+    r.n_chains = cfg->n_chains;
+    r.chunk = L.chunk;
+    r.n_monomers = cfg->n_monomers;
+    r.bins = L.bins;
+    r.exact = L.exact ? 1 : 0;
+    r.log_w = o.log_w;
+    r.r2 = o.r2;
+    r.rg2 = o.rg2;
+    r.n_grown = o.n_grown;
+    r.w_exact = o.w_exact;
+    r.n2rg2 = o.n2rg2;
+    r.lmax_bits = (unsigned long long *)(ws + L.off_lmax);
+    r.status = (int32_t *)(ws + L.off_status);
+    r.partials = (rsaw::BlockPartial *)(ws + L.off_part);
+    r.hist_acc = (unsigned long long *)(ws + L.off_hacc);
+    return r;
+}
+
+// Shared body of the single-ensemble entry points.  With force_reduce the
+// summary goes to the workspace when the caller gives no device summary;
+// *used_summary receives the device address the summary was written to (or
+// NULL).
 rsaw_status gen_impl(const rsaw_config *cfg, const rsaw_chain_out *out, rsaw_summary *d_summary,
                      double *d_hist_w, uint64_t *d_hist_n, void *stream, bool force_reduce,
                      rsaw_summary **used_summary)
@@ -187,91 +352,30 @@ rsaw_status gen_impl(const rsaw_config *cfg, const rsaw_chain_out *out, rsaw_sum
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
 
-    const uint64_t M = cfg->n_chains;
-    const bool lattice = cfg->geometry == RSAW_LATTICE_SC;
-    const bool exact = lattice && (cfg->flags & RSAW_EXACT_W);
     const bool reduce = force_reduce || d_summary != nullptr || d_hist_w != nullptr || d_hist_n != nullptr;
-    const int bins = reduce ? cfg->hist_bins : 0;
-    rsaw_chain_out o{};
-    if (out) o = *out;
-
-    // reduce blocks: at most 1024, each a contiguous run of whole 256-chain tiles
-    uint32_t n_blocks = 0;
-    uint64_t chunk = 256;
-    if (M > 0) {
-        const uint64_t tiles = (M + 255) / 256;
-        const uint64_t nb = tiles < 1024 ? tiles : 1024;
-        chunk = ((tiles + nb - 1) / nb) * 256;
-        n_blocks = (uint32_t)((M + chunk - 1) / chunk);
-    }
-
-    // workspace layout
+    rsaw_chain_out in{};
+    if (out) in = *out;
+    EnsLayout L;
     size_t off = 0;
-    const size_t off_lmax = off; off = align256(off + sizeof(unsigned long long));
-    const size_t off_status = off; off = align256(off + sizeof(int32_t));
-    const size_t off_summary = off; off = align256(off + sizeof(rsaw_summary));
-    const size_t off_part = off; off = align256(off + (size_t)n_blocks * sizeof(rsaw::BlockPartial));
-    const size_t off_hacc = off; off = align256(off + (size_t)4 * bins * sizeof(unsigned long long));
-    const bool need_lw = reduce && !o.log_w, need_r2 = reduce && !o.r2, need_rg2 = reduce && !o.rg2,
-               need_ng = reduce && !o.n_grown, need_wx = reduce && exact && !o.w_exact,
-               need_nn = reduce && exact && lattice && !o.n2rg2;
-    const size_t off_lw = off; if (need_lw) off = align256(off + M * sizeof(double));
-    const size_t off_r2 = off; if (need_r2) off = align256(off + M * sizeof(double));
-    const size_t off_rg2 = off; if (need_rg2) off = align256(off + M * sizeof(double));
-    const size_t off_ng = off; if (need_ng) off = align256(off + M * sizeof(uint16_t));
-    const size_t off_wx = off; if (need_wx) off = align256(off + M * sizeof(uint64_t));
-    const size_t off_nn = off; if (need_nn) off = align256(off + M * sizeof(int64_t));
-
+    layout_ensemble(cfg, in, reduce, &off, &L);
     void *wsv = nullptr;
     st = workspace(dev, s, off, &wsv);
     if (st != RSAW_OK) return st;
     char *ws = (char *)wsv;
-    if (need_lw) o.log_w = (double *)(ws + off_lw);
-    if (need_r2) o.r2 = (double *)(ws + off_r2);
-    if (need_rg2) o.rg2 = (double *)(ws + off_rg2);
-    if (need_ng) o.n_grown = (uint16_t *)(ws + off_ng);
-    if (need_wx) o.w_exact = (uint64_t *)(ws + off_wx);
-    if (need_nn) o.n2rg2 = (int64_t *)(ws + off_nn);
-    if (!lattice) o.n2rg2 = nullptr;
-    if (!exact) o.w_exact = nullptr;
+    const rsaw_chain_out o = bind_outputs(in, L, ws);
 
-    unsigned long long *lmax = (unsigned long long *)(ws + off_lmax);
-    int32_t *status = (int32_t *)(ws + off_status);
-
-    unsigned long long *hacc = (unsigned long long *)(ws + off_hacc);
-    e = rsaw::launch_reduce_init(lmax, status, hacc, 4 * bins, s);
+    e = rsaw::launch_reduce_init((unsigned long long *)(ws + L.off_lmax), (int32_t *)(ws + L.off_status),
+                                 (unsigned long long *)(ws + L.off_hacc), 4 * L.bins, s);
     if (e != hipSuccess) return hip_fail(e, "reduce_init launch");
 
-    if (M > 0) {
-        rsaw::GrowArgs a;
-        std::memset(&a, 0, sizeof(a));
-        a.seed = cfg->seed;
-        a.chain_offset = cfg->chain_offset;
-        a.n_chains = M;
-        a.n_monomers = cfg->n_monomers;
-        a.k_trials = cfg->k_trials;
-        a.bond_length = cfg->bond_length;
-        a.sigma2 = cfg->bead_diameter * cfg->bead_diameter;
-        {
-            const double bs = cfg->bond_length + cfg->bead_diameter;
-            a.cull2 = bs * bs * (1.0 + 0x1p-30);
-        }
-        a.log_w = o.log_w;
-        a.w_exact = o.w_exact;
-        a.r_end = o.r_end;
-        a.r2 = o.r2;
-        a.rg2 = o.rg2;
-        a.n2rg2 = o.n2rg2;
-        a.n_grown = o.n_grown;
-        a.log_w_max_bits = lmax;
-        a.status = status;
-        std::memcpy(a.logm, logm_table(), sizeof(a.logm));
+    if (cfg->n_chains > 0) {
+        const rsaw::GrowArgs a = grow_args(cfg, o, L, ws);
         EventPair tp;
         bool timed = false;
         st = timing_start(s, &tp, &timed);
         if (st != RSAW_OK) return st;
-        e = lattice ? rsaw::launch_grow_lattice(a, exact, cfg->coord_type == RSAW_I16, s)
-                    : rsaw::launch_grow_real(a, s);
+        e = L.lattice ? rsaw::launch_grow_lattice(a, L.exact, cfg->coord_type == RSAW_I16, s)
+                      : rsaw::launch_grow_real(a, s);
         if (timed) {
             st = timing_stop(s, tp);
             if (st != RSAW_OK) return st;
@@ -280,27 +384,166 @@ rsaw_status gen_impl(const rsaw_config *cfg, const rsaw_chain_out *out, rsaw_sum
     }
 
     if (reduce) {
-        rsaw::ReduceArgs r;
-        std::memset(&r, 0, sizeof(r));
-        r.n_chains = M;
-        r.chunk = chunk;
-        r.n_monomers = cfg->n_monomers;
-        r.bins = bins;
-        r.exact = exact ? 1 : 0;
-        r.log_w = o.log_w;
-        r.r2 = o.r2;
-        r.rg2 = o.rg2;
-        r.n_grown = o.n_grown;
-        r.w_exact = o.w_exact;
-        r.n2rg2 = o.n2rg2;
-        r.lmax_bits = lmax;
-        r.status = status;
-        r.partials = (rsaw::BlockPartial *)(ws + off_part);
-        r.hist_acc = hacc;
-        rsaw_summary *dsum = d_summary ? d_summary : (rsaw_summary *)(ws + off_summary);
-        e = rsaw::launch_reduce(r, n_blocks, dsum, d_hist_w, d_hist_n, s);
+        const rsaw::ReduceArgs r = reduce_args(cfg, o, L, ws);
+        rsaw_summary *dsum = d_summary ? d_summary : (rsaw_summary *)(ws + L.off_summary);
+        e = rsaw::launch_reduce(r, L.n_blocks, dsum, d_hist_w, d_hist_n, s);
         if (e != hipSuccess) return hip_fail(e, "reduce kernel launch");
         if (used_summary) *used_summary = dsum;
+    }
+    return RSAW_OK;
+}
+
+// Batched body: every ensemble's growth shares one launch per kernel
+// variant, and the reductions three launches in all.
+rsaw_status batch_impl(const rsaw_config *cfgs, const rsaw_chain_out *outs, int32_t n,
+                       rsaw_summary *d_summaries, double *const *d_hist_w, uint64_t *const *d_hist_n,
+                       void *stream)
+{
+    g_last_error.clear();
+    if (n < 0) return fail(RSAW_E_INVALID, "n must be >= 0");
+    if (n == 0) return RSAW_OK;
+    if (!cfgs) return fail(RSAW_E_INVALID, "cfgs is NULL");
+    for (int32_t i = 0; i < n; ++i) {
+        rsaw_status st = validate(&cfgs[i]);
+        if (st != RSAW_OK) return fail(st, "ensemble " + std::to_string(i) + ": " + g_last_error);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    const bool reduce = d_summaries != nullptr;
+
+    // layouts and kernel variants
+    std::vector<EnsLayout> L(n);
+    std::vector<rsaw_chain_out> in(n);
+    std::vector<rsaw::GrowVariant> var(n);
+    size_t off = 0;
+    int max_bins = 0;
+    uint64_t red_blocks = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        in[i] = outs ? outs[i] : rsaw_chain_out{};
+        layout_ensemble(&cfgs[i], in[i], reduce, &off, &L[i]);
+        max_bins = std::max(max_bins, L[i].bins);
+        red_blocks += L[i].n_blocks;
+        rsaw::GrowArgs probe;
+        std::memset(&probe, 0, sizeof(probe));
+        probe.n_monomers = cfgs[i].n_monomers;
+        probe.k_trials = cfgs[i].k_trials;
+        const bool i16 = cfgs[i].coord_type == RSAW_I16;
+        if (!L[i].lattice) {
+            e = rsaw::real_variant(probe, &var[i]);
+        } else if (L[i].exact || cfgs[i].n_monomers <= 64) {
+            rsaw::lattice_reg_variant(probe, L[i].exact, i16, &var[i]);
+            e = hipSuccess;
+        } else {
+            e = rsaw::lattice_lds_variant(probe, i16, &var[i]);
+        }
+        if (e != hipSuccess) return fail(RSAW_E_UNSUPPORTED, "ensemble " + std::to_string(i) + ": no kernel variant");
+    }
+    // ensembles with chains, grouped by variant (stable: index order within a group)
+    std::vector<int32_t> order;
+    for (int32_t i = 0; i < n; ++i)
+        if (cfgs[i].n_chains > 0) order.push_back(i);
+    auto key = [&](int32_t i) {
+        const rsaw::GrowVariant &v = var[i];
+        return std::make_tuple(v.family, v.p0, v.p1, v.p2, v.threads);
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return key(x) < key(y); });
+    const int32_t ng = (int32_t)order.size();
+
+    // device tables after the ensembles' regions
+    const size_t off_gtab = align256(off);
+    const size_t off_gb0 = align256(off_gtab + (size_t)ng * sizeof(rsaw::GrowEntry));
+    const size_t off_rtab = align256(off_gb0 + (size_t)(ng + 1) * sizeof(uint64_t));
+    const size_t off_rb0 = align256(off_rtab + (size_t)n * sizeof(rsaw::ReduceEntry));
+    const size_t off_end = align256(off_rb0 + (size_t)(n + 1) * sizeof(uint64_t));
+    const size_t tab_bytes = off_end - off_gtab;
+    void *wsv = nullptr;
+    rsaw_status st = workspace(dev, s, off_end, &wsv);
+    if (st != RSAW_OK) return st;
+    char *ws = (char *)wsv;
+    void *stv = nullptr;
+    hipEvent_t stage_done = nullptr;
+    st = staging(dev, s, tab_bytes, &stv, &stage_done);
+    if (st != RSAW_OK) return st;
+    char *stage = (char *)stv;
+    rsaw::GrowEntry *gtab = (rsaw::GrowEntry *)(stage + (off_gtab - off_gtab));
+    uint64_t *gb0 = (uint64_t *)(stage + (off_gb0 - off_gtab));
+    rsaw::ReduceEntry *rtab = (rsaw::ReduceEntry *)(stage + (off_rtab - off_gtab));
+    uint64_t *rb0 = (uint64_t *)(stage + (off_rb0 - off_gtab));
+
+    std::vector<rsaw_chain_out> o(n);
+    for (int32_t i = 0; i < n; ++i) o[i] = bind_outputs(in[i], L[i], ws);
+    // growth groups: [first, last) in `order`, blocks and largest LDS
+    struct Group { int32_t first, last; uint64_t blocks; size_t shmem; };
+    std::vector<Group> groups;
+    uint64_t b = 0;
+    for (int32_t q = 0; q < ng; ++q) {
+        const int32_t i = order[q];
+        if (q == 0 || key(i) != key(order[q - 1])) {
+            groups.push_back(Group{q, q, 0, 0});
+            b = 0;
+        }
+        Group &G = groups.back();
+        gtab[q].a = grow_args(&cfgs[i], o[i], L[i], ws);
+        gtab[q].H = var[i].H;
+        gtab[q].S = var[i].S;
+        gb0[q] = b;
+        b += (cfgs[i].n_chains + var[i].cpb - 1) / var[i].cpb;
+        G.last = q + 1;
+        G.blocks = b;
+        G.shmem = std::max(G.shmem, var[i].shmem);
+    }
+    gb0[ng] = 0;
+    uint64_t rb = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        rsaw::ReduceEntry &r = rtab[i];
+        std::memset(&r, 0, sizeof(r));
+        r.r = reduce_args(&cfgs[i], o[i], L[i], ws);
+        r.n_blocks = L[i].n_blocks;
+        r.lmax = (unsigned long long *)(ws + L[i].off_lmax);
+        r.status = (int32_t *)(ws + L[i].off_status);
+        r.out = reduce ? d_summaries + i : nullptr;
+        r.hist_w = (reduce && d_hist_w) ? d_hist_w[i] : nullptr;
+        r.hist_n = (reduce && d_hist_n) ? d_hist_n[i] : nullptr;
+        rb0[i] = rb;
+        rb += L[i].n_blocks;
+    }
+    rb0[n] = rb;
+
+    e = hipMemcpyAsync(ws + off_gtab, stage, tab_bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "batch table copy");
+    e = hipEventRecord(stage_done, s);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    const rsaw::GrowEntry *d_gtab = (const rsaw::GrowEntry *)(ws + off_gtab);
+    const uint64_t *d_gb0 = (const uint64_t *)(ws + off_gb0);
+    const rsaw::ReduceEntry *d_rtab = (const rsaw::ReduceEntry *)(ws + off_rtab);
+    const uint64_t *d_rb0 = (const uint64_t *)(ws + off_rb0);
+
+    e = rsaw::launch_reduce_batch(d_rtab, d_rb0, n, 0, 0, s, true);
+    if (e != hipSuccess) return hip_fail(e, "batched reduce_init launch");
+    for (const Group &G : groups) {
+        const rsaw::GrowVariant &v = var[order[G.first]];
+        const int32_t cnt = G.last - G.first;
+        EventPair tp;
+        bool timed = false;
+        st = timing_start(s, &tp, &timed);
+        if (st != RSAW_OK) return st;
+        if (v.family == 0)
+            e = rsaw::launch_lattice_reg_batch(v, d_gtab + G.first, d_gb0 + G.first, cnt, G.blocks, s);
+        else if (v.family == 1)
+            e = rsaw::launch_lattice_lds_batch(v, d_gtab + G.first, d_gb0 + G.first, cnt, G.blocks, G.shmem, s);
+        else
+            e = rsaw::launch_real_batch(v, d_gtab + G.first, d_gb0 + G.first, cnt, G.blocks, G.shmem, s);
+        if (timed) {
+            st = timing_stop(s, tp);
+            if (st != RSAW_OK) return st;
+        }
+        if (e != hipSuccess) return hip_fail(e, "batched grow kernel launch");
+    }
+    if (reduce) {
+        e = rsaw::launch_reduce_batch(d_rtab, d_rb0, n, rb, max_bins, s, false);
+        if (e != hipSuccess) return hip_fail(e, "batched reduce kernel launch");
     }
     return RSAW_OK;
 }
@@ -332,6 +575,13 @@ rsaw_status rsaw_gen_chains_sync(const rsaw_config *cfg, const rsaw_chain_out *o
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     if (h_summary->status != RSAW_OK) return fail((rsaw_status)h_summary->status, "rejection cap reached");
     return RSAW_OK;
+}
+
+rsaw_status rsaw_gen_batch(const rsaw_config *cfgs, const rsaw_chain_out *outs, int32_t n,
+                           rsaw_summary *d_summaries, double *const *d_hist_w,
+                           uint64_t *const *d_hist_n, void *stream)
+{
+    return batch_impl(cfgs, outs, n, d_summaries, d_hist_w, d_hist_n, stream);
 }
 
 const char *rsaw_status_string(rsaw_status s)
@@ -397,14 +647,14 @@ void rsaw_shutdown(void)
     }
     std::lock_guard<std::mutex> lk(g_ws_lock);
     for (auto &kv : g_ws) {
-        if (kv.second.base) {
-            int cur = 0;
-            (void)hipGetDevice(&cur);
-            (void)hipSetDevice(kv.first.first);
-            (void)hipDeviceSynchronize();
-            (void)hipFree(kv.second.base);
-            (void)hipSetDevice(cur);
-        }
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(kv.first.first);
+        (void)hipDeviceSynchronize();
+        if (kv.second.base) (void)hipFree(kv.second.base);
+        if (kv.second.stage) (void)hipHostFree(kv.second.stage);
+        if (kv.second.stage_done) (void)hipEventDestroy(kv.second.stage_done);
+        (void)hipSetDevice(cur);
     }
     g_ws.clear();
 }

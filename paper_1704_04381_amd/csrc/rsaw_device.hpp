@@ -122,4 +122,35 @@ struct GrowArgs {
     double logm[65];                    // ln(m) correctly rounded, m = 0..64
 };
 
+// One ensemble of a batched launch: its arguments and, for the LDS lattice
+// kernel, its plane length H and chain stride S (words).
+struct GrowEntry {
+    GrowArgs a;
+    int32_t H, S;
+};
+
+// Segment of block `bid` in a batched launch: the last e with block0[e] <= bid
+// (block0 ascending, block0[0] = 0, n >= 1).
+__device__ __forceinline__ int find_segment(const uint64_t *block0, int n, uint64_t bid)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (block0[mid] <= bid) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Launch shape of one growth kernel variant; ensembles with equal kernel,
+// template parameters and block size share one batched launch.
+struct GrowVariant {
+    int family;         // 0 lattice (registers), 1 lattice (LDS), 2 hard spheres
+    int p0, p1, p2;     // template parameters of the family
+    int threads;        // threads per block
+    int cpb;            // chains per block
+    size_t shmem;       // dynamic LDS bytes per block
+    int32_t H, S;       // LDS lattice plane length and chain stride
+};
+
 } // namespace rsaw

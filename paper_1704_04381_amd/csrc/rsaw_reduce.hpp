@@ -35,6 +35,23 @@ struct ReduceArgs {
     unsigned long long *hist_acc; // [4][bins]: limbs 0, 1, 2 of sum w, and counts
 };
 
+// One ensemble of a batched reduction.
+struct ReduceEntry {
+    ReduceArgs r;
+    uint32_t n_blocks;           // reduce blocks of this ensemble
+    unsigned long long *lmax;    // the cells that r reads, writable for the init
+    int32_t *status;
+    rsaw_summary *out;
+    double *hist_w;
+    uint64_t *hist_n;
+};
+
+// Batched reduction: with init_only, zero every ensemble's accumulators
+// (one block each); otherwise the partials over the concatenated block
+// ranges (block0 ascending) and one final block per ensemble.
+hipError_t launch_reduce_batch(const ReduceEntry *tab, const uint64_t *block0, int n, uint64_t total_blocks,
+                               int max_bins, hipStream_t s, bool init_only);
+
 hipError_t launch_reduce_init(unsigned long long *lmax_bits, int32_t *status,
                               unsigned long long *hist_acc, int n_acc, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs &a, uint32_t n_blocks, rsaw_summary *out,

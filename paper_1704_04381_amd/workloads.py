@@ -26,3 +26,32 @@ WORKLOADS = {
 def steps_per_chain(w) -> int:
     """Nominal monomer-steps per chain (N - 1 growth steps)."""
     return w["N"] - 1
+
+
+def mixed_ensembles(n=256, meta_seed=42, m_lo=3.0, m_span=3.0):
+    """Descriptors of a mixed batch of ensembles (the batched-launch workload).
+
+    Ensemble e draws three uniforms (u_N, u_k, u_M) from NumPy's
+    Philox4x32-10 generator keyed by ``meta_seed`` (a published counter-based
+    generator, so the list does not depend on the language that reads it):
+    N = 8 + floor(121 u_N); even e are lattice ensembles (k = 6, int32 ends),
+    odd e hard-sphere ensembles with k = 8 (u_k < 1/2) or 16 (b = sigma = 1);
+    M = floor(10^(m_lo + m_span u_M)) chains; seed = meta_seed * 2^20 + e.
+    Returns a list of dicts accepted by ``gen_chains`` / ``gen_batch``.
+    """
+    import numpy as np
+
+    g = np.random.Generator(np.random.Philox(key=meta_seed))
+    u = g.random((n, 3))
+    out = []
+    for e in range(n):
+        N = 8 + int(121 * u[e, 0])
+        M = int(10.0 ** (m_lo + m_span * u[e, 2]))
+        seed = meta_seed * (1 << 20) + e
+        if e % 2 == 0:
+            out.append(dict(geometry="lattice", N=N, k=6, n_chains=M, seed=seed, coord="i32"))
+        else:
+            k = 8 if u[e, 1] < 0.5 else 16
+            out.append(dict(geometry="real", N=N, k=k, n_chains=M, seed=seed, coord="f64",
+                            bond_length=1.0, bead_diameter=1.0))
+    return out

@@ -79,6 +79,18 @@ def test_null_arguments():
     assert lib.rsaw_status_string(99).decode() == "unknown status"
 
 
+def test_batch_argument_errors():
+    lib = _lib()
+    assert lib.rsaw_gen_batch(None, None, 0, None, None, None, None) == 0
+    assert lib.rsaw_gen_batch(None, None, -1, None, None, None, None) == 1
+    assert lib.rsaw_gen_batch(None, None, 3, None, None, None, None) == 1
+    good = rs.make_config("lattice", 16, 6, 10, 1)
+    bad = rs.make_config("real", 16, 65, 10, 1)
+    arr = (rs.rsaw_config * 3)(good, bad, good)
+    assert lib.rsaw_gen_batch(arr, None, 3, None, None, None, None) == 1
+    assert "ensemble 1" in lib.rsaw_last_error().decode()
+
+
 def test_kernel_timing_switch_without_launches():
     lib = _lib()
     assert lib.rsaw_kernel_timing(1) == 0
