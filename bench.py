@@ -5,7 +5,9 @@ A step is one pass of the whole path over one ensemble: grow every chain
 (weighted averages, c_n estimate, R^2 histogram).  The headline workload is
 the simple cubic lattice at N = 64 monomers, 10^7 chains, int16 coordinates,
 FP64 log-weights and a 256-bin histogram; the hard-sphere N = 64, k = 8,
-10^6-chain workload is reported beside it under "secondary".
+10^6-chain workload is reported beside it under "secondary", and a mixed
+batch of 256 ensembles (one batched call against per-ensemble calls) under
+"batch".
 
 Prints one JSON line.  value = monomer-steps/s = M (N - 1) K / T with the
 inputs (seed, configuration) resident before the timed region.
@@ -153,6 +155,73 @@ def run_gpu(w, steps, warmup, torch, rs):
     return dict(wall=wall, lat=lat, summary=summary, grow_ms=k_ms / k_n)
 
 
+def run_batch(torch, rs, reps, m_lo=3.0, m_span=3.0):
+    """Mixed workload of 256 ensembles of 10^m_lo .. 10^(m_lo + m_span)
+    chains: one rsaw_gen_batch call against 256 rsaw_gen_chains calls on the
+    same stream (per-chain outputs and summaries in both), events around the
+    whole and around each plain call."""
+    from paper_1704_04381_amd.workloads import mixed_ensembles
+
+    dev = torch.device("cuda", 0)
+    specs = mixed_ensembles(m_lo=m_lo, m_span=m_span)
+    cfgs, outs, keep = [], [], []
+    for sp in specs:
+        sp = dict(sp)
+        cfg = rs.make_config(sp.pop("geometry"), sp.pop("N"), sp.pop("k"), sp.pop("n_chains"),
+                             sp.pop("seed"), **sp)
+        out, o = rs._alloc_outputs(cfg, dev, True, 0)
+        cfgs.append(cfg)
+        outs.append(o)
+        keep.append(out)
+    n = len(cfgs)
+    summ = torch.empty(n * rs.SUMMARY_BYTES, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    sh = stream.cuda_stream
+    steps = sum(c.n_chains * (c.n_monomers - 1) for c in cfgs)
+
+    def batched():
+        rs.gen_batch_raw(cfgs, outs, summ.data_ptr(), None, None, sh)
+
+    def plain(evs=None):
+        for i, (c, o) in enumerate(zip(cfgs, outs)):
+            if evs is not None:
+                evs[i][0].record(stream)
+            rs.gen_chains_raw(c, o, summ.data_ptr() + i * rs.SUMMARY_BYTES, 0, 0, sh)
+            if evs is not None:
+                evs[i][1].record(stream)
+
+    batched()
+    plain()
+    torch.cuda.synchronize()
+    t_b, t_p, per = [], [], []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        batched()
+        b.record(stream)
+        torch.cuda.synchronize()
+        t_b.append(a.elapsed_time(b))
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+        a2, b2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a2.record(stream)
+        plain(evs)
+        b2.record(stream)
+        torch.cuda.synchronize()
+        t_p.append(a2.elapsed_time(b2))
+        per.extend(x.elapsed_time(y) for x, y in evs)
+    tb, tp = _percentile(t_b, 0.5), _percentile(t_p, 0.5)
+    return {
+        "workload": f"mixed_256 (N = 8..128, lattice k = 6 / hard spheres k = 8, 16, "
+                    f"10^{m_lo:g}..10^{m_lo + m_span:g} chains each)",
+        "ensembles": n, "chains": sum(c.n_chains for c in cfgs), "monomer_steps": steps,
+        "batched_ms": tb, "batched_value": steps / (tb / 1e3),
+        "plain_ms": tp, "plain_value": steps / (tp / 1e3),
+        "unit": "monomer-steps/s", "speedup": tp / tb, "reps": reps,
+        "plain_ensemble_p50_ms": _percentile(per, 0.5), "plain_ensemble_p99_ms": _percentile(per, 0.99),
+        "batched_ensemble_latency_ms": tb,
+    }
+
+
 def cpu_baseline(w, sample_chains, threads):
     """The oracle, untuned, on the host cores: a bounded sample of the same
     workload (its first `sample_chains` chains), split over threads."""
@@ -193,6 +262,8 @@ def main():
     ap.add_argument("--workload", default="lattice_n64")
     ap.add_argument("--secondary", default="real_n64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the mixed 256-ensemble batched-launch measurement")
     ap.add_argument("--cpu-sample", type=int, default=0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (3 times), to scale "
@@ -281,6 +352,9 @@ def main():
             "physics": {k: r2["summary"][k] for k in ("n_alive", "log_c_est", "r2_mean",
                                                       "r2_err", "rg2_mean", "rg2_err")},
         }
+    if not args.no_batch:
+        line["batch"] = {"full": run_batch(torch, rs, 3),
+                         "small": run_batch(torch, rs, 5, m_lo=2.0, m_span=2.0)}
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         sample = args.cpu_sample or (1_000_000 if w["geometry"] == "lattice" else 300_000)
