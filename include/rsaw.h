@@ -198,6 +198,66 @@ rsaw_status rsaw_gen_batch(const rsaw_config *cfgs, const rsaw_chain_out *outs, 
                            rsaw_summary *d_summaries, double *const *d_hist_w,
                            uint64_t *const *d_hist_n, void *stream);
 
+/*
+ * Serving loop.  A server owns S HIP streams on one device and a scheduler
+ * thread.  Each request is one ensemble (an rsaw_config).  The scheduler
+ * forms batches from the head of the arrival queue while the requests'
+ * device bytes (26 B per chain plus 160 KiB each) fit in bytes_per_stream
+ * and the batch holds at most max_batch requests.  It launches each batch
+ * with rsaw_gen_batch on a free stream, so a new batch starts while others
+ * run.  A completion thread per stream retires the batch's tickets.  Each
+ * result is bit-identical to a stand-alone rsaw_gen_chains call with the
+ * same configuration, whatever the mix it was served in.
+ */
+typedef struct rsaw_server rsaw_server;
+
+typedef struct {
+    uint64_t bytes_per_stream; /* admission budget of one batch (default 2 GiB) */
+    int32_t max_batch;         /* requests per batch, 1..4096 (default 256)     */
+    int32_t streams;           /* concurrent batches, 1..16 (default 2)         */
+} rsaw_server_params;
+
+/*
+ * rsaw_server_create — start a server on `device` (params NULL = defaults).
+ * *out receives the handle.  RSAW_E_INVALID for out-of-range parameters,
+ * RSAW_E_DEVICE for a bad device, RSAW_E_NOMEM if its buffers cannot be
+ * allocated.
+ */
+rsaw_status rsaw_server_create(const rsaw_server_params *params, int32_t device, rsaw_server **out);
+
+/*
+ * rsaw_server_submit — queue one request; *ticket identifies it.  The
+ * configuration is checked as by rsaw_gen_chains (same statuses).  A
+ * request whose bytes exceed bytes_per_stream is refused with
+ * RSAW_E_NOMEM.  Thread-safe.
+ */
+rsaw_status rsaw_server_submit(rsaw_server *s, const rsaw_config *cfg, uint64_t *ticket);
+
+/*
+ * rsaw_server_poll — *done = 1 if the request has finished.  Then its
+ * summary is written to *h_summary (host, may be NULL) and times_us
+ * receives the queueing and completion latencies from submission in
+ * microseconds ({started - submitted, finished - submitted}, host array of
+ * 2, may be NULL), and the ticket is released.  Returns the request's
+ * status once it has finished, RSAW_OK while it runs, RSAW_E_INVALID for an
+ * unknown ticket.
+ */
+rsaw_status rsaw_server_poll(rsaw_server *s, uint64_t ticket, int32_t *done, rsaw_summary *h_summary,
+                             double *times_us);
+
+/*
+ * rsaw_server_wait — block until the request finishes, then as
+ * rsaw_server_poll.  Each ticket is taken (polled to completion or waited
+ * for) once, by one thread.
+ */
+rsaw_status rsaw_server_wait(rsaw_server *s, uint64_t ticket, rsaw_summary *h_summary, double *times_us);
+
+/*
+ * rsaw_server_destroy — finish the batches in flight, fail requests that
+ * never started (RSAW_E_DEVICE), stop the threads and free the server.
+ */
+void rsaw_server_destroy(rsaw_server *s);
+
 /* Static description of a status code. */
 const char *rsaw_status_string(rsaw_status s);
 

@@ -55,8 +55,14 @@ class rsaw_summary(C.Structure):
 
 SUMMARY_BYTES = C.sizeof(rsaw_summary)
 
+
+class rsaw_server_params(C.Structure):
+    _fields_ = [("bytes_per_stream", C.c_uint64), ("max_batch", C.c_int32), ("streams", C.c_int32)]
+
 # Every symbol include/rsaw.h declares.
-EXPORTS = ["rsaw_gen_chains", "rsaw_gen_chains_sync", "rsaw_gen_batch", "rsaw_status_string",
+EXPORTS = ["rsaw_gen_chains", "rsaw_gen_chains_sync", "rsaw_gen_batch", "rsaw_server_create",
+           "rsaw_server_submit", "rsaw_server_poll", "rsaw_server_wait", "rsaw_server_destroy",
+           "rsaw_status_string",
            "rsaw_last_error", "rsaw_version", "rsaw_kernel_timing", "rsaw_kernel_time",
            "rsaw_shutdown"]
 
@@ -90,6 +96,17 @@ def load(path: str = LIB_PATH):
         lib.rsaw_gen_batch.argtypes = [C.POINTER(rsaw_config), C.POINTER(rsaw_chain_out), C.c_int32,
                                        vp, C.POINTER(vp), C.POINTER(vp), vp]
         lib.rsaw_gen_batch.restype = C.c_int
+        lib.rsaw_server_create.argtypes = [C.POINTER(rsaw_server_params), C.c_int32, C.POINTER(vp)]
+        lib.rsaw_server_create.restype = C.c_int
+        lib.rsaw_server_submit.argtypes = [vp, C.POINTER(rsaw_config), C.POINTER(C.c_uint64)]
+        lib.rsaw_server_submit.restype = C.c_int
+        lib.rsaw_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(C.c_int32), C.POINTER(rsaw_summary),
+                                         C.POINTER(C.c_double)]
+        lib.rsaw_server_poll.restype = C.c_int
+        lib.rsaw_server_wait.argtypes = [vp, C.c_uint64, C.POINTER(rsaw_summary), C.POINTER(C.c_double)]
+        lib.rsaw_server_wait.restype = C.c_int
+        lib.rsaw_server_destroy.argtypes = [vp]
+        lib.rsaw_server_destroy.restype = None
         lib.rsaw_status_string.argtypes = [C.c_int]
         lib.rsaw_status_string.restype = C.c_char_p
         lib.rsaw_last_error.argtypes = []
@@ -268,6 +285,60 @@ def gen_batch(specs, *, per_chain=True, device=None, stream=None, sync=True):
             raise RsawError(s["status"], f"ensemble {i}: device reported a rejection-cap hit")
         res.append((out, s))
     return res
+
+
+class Server:
+    """Serving loop of librsaw (rsaw_server_*): submit ensembles, take their
+    summaries.  Each result equals a stand-alone gen_chains call."""
+
+    def __init__(self, bytes_per_stream=2 << 30, max_batch=256, streams=2, device=0):
+        lib = load()
+        self._lib = lib
+        p = rsaw_server_params(int(bytes_per_stream), int(max_batch), int(streams))
+        h = C.c_void_p()
+        _check(lib.rsaw_server_create(C.byref(p), int(device), C.byref(h)))
+        self._h = h
+
+    def submit(self, geometry, N, k, n_chains, seed, **kw) -> int:
+        cfg = make_config(geometry, N, k, n_chains, seed, **kw)
+        t = C.c_uint64()
+        _check(self._lib.rsaw_server_submit(self._h, C.byref(cfg), C.byref(t)))
+        return t.value
+
+    def _result(self, st, summ, times):
+        if st != 0:
+            raise RsawError(st, self._lib.rsaw_last_error().decode())
+        d = summary_to_dict(summ)
+        d["queue_us"], d["latency_us"] = times[0], times[1]
+        return d
+
+    def poll(self, ticket):
+        """Summary dict (with queue_us and latency_us) or None while running."""
+        done = C.c_int32()
+        summ = rsaw_summary()
+        times = (C.c_double * 2)()
+        st = self._lib.rsaw_server_poll(self._h, ticket, C.byref(done), C.byref(summ), times)
+        if not done.value:
+            _check(st)
+            return None
+        return self._result(st, summ, times)
+
+    def wait(self, ticket):
+        summ = rsaw_summary()
+        times = (C.c_double * 2)()
+        st = self._lib.rsaw_server_wait(self._h, ticket, C.byref(summ), times)
+        return self._result(st, summ, times)
+
+    def close(self):
+        if self._h:
+            self._lib.rsaw_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def version() -> int:

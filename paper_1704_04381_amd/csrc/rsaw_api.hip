@@ -550,6 +550,15 @@ rsaw_status batch_impl(const rsaw_config *cfgs, const rsaw_chain_out *outs, int3
 
 } // namespace
 
+namespace rsaw {
+// The argument checks of rsaw_gen_chains, for the serving loop's submit.
+rsaw_status check_config(const rsaw_config *cfg)
+{
+    g_last_error.clear();
+    return validate(cfg);
+}
+} // namespace rsaw
+
 extern "C" {
 
 rsaw_status rsaw_gen_chains(const rsaw_config *cfg, const rsaw_chain_out *out,

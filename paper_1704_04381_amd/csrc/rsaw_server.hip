@@ -1,0 +1,323 @@
+// Serving loop of librsaw (declared in include/rsaw.h): requests (one
+// ensemble each) are queued by rsaw_server_submit, a scheduler thread forms
+// batches from the queue head and launches each with rsaw_gen_batch on one
+// of S streams, and a completion thread per stream waits for the batch's
+// event, copies the summaries out and retires the tickets.
+//
+// Admission: a batch takes requests in arrival order while the device bytes
+// they need (the per-chain arrays of the reduction, 26 B per chain, plus a
+// fixed share) stay within the per-stream budget and the batch holds at most
+// max_batch requests.  A new batch starts on any free stream while others
+// run, so short requests arriving during a long batch do not wait for it.
+// Every result is that of a stand-alone rsaw_gen_chains call (batched
+// growth and reduction are bit-identical to single calls).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "rsaw.h"
+
+namespace rsaw {
+rsaw_status check_config(const rsaw_config *cfg); // the checks of rsaw_gen_chains
+} // namespace rsaw
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Ticket {
+    rsaw_config cfg;
+    Clock::time_point submitted, started, done_at;
+    bool done = false;
+    rsaw_status status = RSAW_OK;
+    rsaw_summary summary;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    rsaw_summary *d_summ = nullptr; // max_batch summaries (device)
+    rsaw_summary *h_summ = nullptr; // pinned copy
+    std::vector<uint64_t> tickets;  // the batch assigned to the slot (empty: free)
+    bool launched = false;          // its launch and completion event are enqueued
+    std::thread waiter;
+    std::condition_variable cv;     // a batch was launched on this slot
+};
+
+// Device bytes a request holds while in flight (the reduction's per-chain
+// arrays in the library workspace, and its cells and partials).
+size_t request_bytes(const rsaw_config &c)
+{
+    return (size_t)c.n_chains * (3 * sizeof(double) + sizeof(uint16_t)) + (size_t)160 * 1024;
+}
+
+} // namespace
+
+struct rsaw_server {
+    rsaw_server_params p;
+    int device = 0;
+    std::mutex mu;
+    std::condition_variable cv_sched; // new request or a slot became free
+    std::condition_variable cv_done;  // a ticket completed
+    std::deque<uint64_t> queue;
+    std::unordered_map<uint64_t, Ticket> tickets;
+    uint64_t next_ticket = 1;
+    bool stopping = false;
+    std::vector<Slot> slots;
+    std::thread scheduler;
+    std::string error;
+
+    void fail_batch(Slot &sl, rsaw_status st)
+    {
+        for (uint64_t t : sl.tickets) {
+            Ticket &tk = tickets[t];
+            tk.status = st;
+            tk.done = true;
+            tk.done_at = Clock::now();
+        }
+        sl.tickets.clear();
+    }
+
+    void schedule_loop()
+    {
+        hipSetDevice(device);
+        std::unique_lock<std::mutex> lk(mu);
+        while (true) {
+            cv_sched.wait(lk, [&] {
+                if (stopping) return true;
+                if (queue.empty()) return false;
+                for (Slot &sl : slots)
+                    if (sl.tickets.empty()) return true;
+                return false;
+            });
+            if (stopping && queue.empty()) break;
+            if (stopping) {
+                // drain: fail what never started
+                for (uint64_t t : queue) {
+                    Ticket &tk = tickets[t];
+                    tk.status = RSAW_E_DEVICE;
+                    tk.done = true;
+                    tk.done_at = Clock::now();
+                }
+                queue.clear();
+                cv_done.notify_all();
+                break;
+            }
+            Slot *free_slot = nullptr;
+            for (Slot &sl : slots)
+                if (sl.tickets.empty()) {
+                    free_slot = &sl;
+                    break;
+                }
+            if (!free_slot) continue;
+            // admission from the queue head
+            std::vector<uint64_t> batch;
+            size_t bytes = 0;
+            while (!queue.empty() && (int)batch.size() < p.max_batch) {
+                const Ticket &tk = tickets[queue.front()];
+                const size_t need = request_bytes(tk.cfg);
+                if (!batch.empty() && bytes + need > p.bytes_per_stream) break;
+                bytes += need;
+                batch.push_back(queue.front());
+                queue.pop_front();
+            }
+            std::vector<rsaw_config> cfgs;
+            const Clock::time_point now = Clock::now();
+            for (uint64_t t : batch) {
+                Ticket &tk = tickets[t];
+                tk.started = now;
+                cfgs.push_back(tk.cfg);
+            }
+            free_slot->tickets = batch;
+            lk.unlock();
+            // the launch itself runs outside the lock; only this thread launches
+            rsaw_status st = rsaw_gen_batch(cfgs.data(), nullptr, (int32_t)cfgs.size(), free_slot->d_summ,
+                                            nullptr, nullptr, free_slot->stream);
+            hipError_t e = hipSuccess;
+            if (st == RSAW_OK)
+                e = hipMemcpyAsync(free_slot->h_summ, free_slot->d_summ, cfgs.size() * sizeof(rsaw_summary),
+                                   hipMemcpyDeviceToHost, free_slot->stream);
+            if (st == RSAW_OK && e == hipSuccess) e = hipEventRecord(free_slot->done, free_slot->stream);
+            lk.lock();
+            if (st != RSAW_OK || e != hipSuccess) {
+                error = st != RSAW_OK ? rsaw_last_error() : hipGetErrorString(e);
+                fail_batch(*free_slot, st != RSAW_OK ? st : RSAW_E_DEVICE);
+                cv_done.notify_all();
+                continue;
+            }
+            free_slot->launched = true;
+            free_slot->cv.notify_one();
+        }
+    }
+
+    void wait_loop(Slot *sl)
+    {
+        hipSetDevice(device);
+        std::unique_lock<std::mutex> lk(mu);
+        while (true) {
+            sl->cv.wait(lk, [&] { return sl->launched || (stopping && sl->tickets.empty()); });
+            if (!sl->launched) break;
+            lk.unlock();
+            hipError_t e = hipEventSynchronize(sl->done);
+            const Clock::time_point now = Clock::now();
+            lk.lock();
+            for (size_t i = 0; i < sl->tickets.size(); ++i) {
+                Ticket &tk = tickets[sl->tickets[i]];
+                tk.done_at = now;
+                tk.done = true;
+                if (e != hipSuccess) {
+                    tk.status = RSAW_E_DEVICE;
+                } else {
+                    tk.summary = sl->h_summ[i];
+                    tk.status = (rsaw_status)tk.summary.status;
+                }
+            }
+            sl->tickets.clear();
+            sl->launched = false;
+            cv_done.notify_all();
+            cv_sched.notify_one();
+        }
+    }
+};
+
+extern "C" {
+
+rsaw_status rsaw_server_create(const rsaw_server_params *params, int32_t device, rsaw_server **out)
+{
+    if (!out) return RSAW_E_INVALID;
+    *out = nullptr;
+    rsaw_server_params p{};
+    p.bytes_per_stream = (size_t)2 << 30;
+    p.max_batch = 256;
+    p.streams = 2;
+    if (params) p = *params;
+    if (p.streams < 1 || p.streams > 16 || p.max_batch < 1 || p.max_batch > 4096 || p.bytes_per_stream == 0)
+        return RSAW_E_INVALID;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return RSAW_E_DEVICE;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    if (hipSetDevice(device) != hipSuccess) return RSAW_E_DEVICE;
+    rsaw_server *s = new rsaw_server();
+    s->p = p;
+    s->device = device;
+    s->slots = std::vector<Slot>(p.streams);
+    bool ok = true;
+    for (Slot &sl : s->slots) {
+        ok = ok && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess;
+        ok = ok && hipMalloc(&sl.d_summ, (size_t)p.max_batch * sizeof(rsaw_summary)) == hipSuccess;
+        ok = ok && hipHostMalloc(&sl.h_summ, (size_t)p.max_batch * sizeof(rsaw_summary), hipHostMallocDefault) ==
+                       hipSuccess;
+        if (!ok) break;
+    }
+    (void)hipSetDevice(prev);
+    if (!ok) {
+        for (Slot &sl : s->slots) {
+            if (sl.d_summ) (void)hipFree(sl.d_summ);
+            if (sl.h_summ) (void)hipHostFree(sl.h_summ);
+            if (sl.done) (void)hipEventDestroy(sl.done);
+            if (sl.stream) (void)hipStreamDestroy(sl.stream);
+        }
+        delete s;
+        return RSAW_E_NOMEM;
+    }
+    for (Slot &sl : s->slots) sl.waiter = std::thread(&rsaw_server::wait_loop, s, &sl);
+    s->scheduler = std::thread(&rsaw_server::schedule_loop, s);
+    *out = s;
+    return RSAW_OK;
+}
+
+rsaw_status rsaw_server_submit(rsaw_server *s, const rsaw_config *cfg, uint64_t *ticket)
+{
+    if (!s || !cfg || !ticket) return RSAW_E_INVALID;
+    rsaw_status st = rsaw::check_config(cfg);
+    if (st != RSAW_OK) return st;
+    if (request_bytes(*cfg) > s->p.bytes_per_stream) return RSAW_E_NOMEM;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stopping) return RSAW_E_INVALID;
+    const uint64_t t = s->next_ticket++;
+    Ticket &tk = s->tickets[t];
+    tk.cfg = *cfg;
+    tk.submitted = Clock::now();
+    std::memset(&tk.summary, 0, sizeof(tk.summary));
+    s->queue.push_back(t);
+    *ticket = t;
+    s->cv_sched.notify_one();
+    return RSAW_OK;
+}
+
+static rsaw_status take(rsaw_server *s, uint64_t ticket, rsaw_summary *h_summary, double *times_us)
+{
+    Ticket &tk = s->tickets[ticket];
+    if (h_summary) *h_summary = tk.summary;
+    if (times_us) {
+        times_us[0] = std::chrono::duration<double, std::micro>(tk.started - tk.submitted).count();
+        times_us[1] = std::chrono::duration<double, std::micro>(tk.done_at - tk.submitted).count();
+    }
+    const rsaw_status st = tk.status;
+    s->tickets.erase(ticket);
+    return st;
+}
+
+rsaw_status rsaw_server_poll(rsaw_server *s, uint64_t ticket, int32_t *done, rsaw_summary *h_summary,
+                             double *times_us)
+{
+    if (!s || !done) return RSAW_E_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->tickets.find(ticket);
+    if (it == s->tickets.end()) return RSAW_E_INVALID;
+    *done = it->second.done ? 1 : 0;
+    if (!it->second.done) return RSAW_OK;
+    return take(s, ticket, h_summary, times_us);
+}
+
+rsaw_status rsaw_server_wait(rsaw_server *s, uint64_t ticket, rsaw_summary *h_summary, double *times_us)
+{
+    if (!s) return RSAW_E_INVALID;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->tickets.find(ticket);
+    if (it == s->tickets.end()) return RSAW_E_INVALID;
+    s->cv_done.wait(lk, [&] { return s->tickets[ticket].done; });
+    return take(s, ticket, h_summary, times_us);
+}
+
+void rsaw_server_destroy(rsaw_server *s)
+{
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stopping = true;
+    }
+    s->cv_sched.notify_all();
+    if (s->scheduler.joinable()) s->scheduler.join();
+    for (Slot &sl : s->slots) {
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+        }
+        sl.cv.notify_all();
+        if (sl.waiter.joinable()) sl.waiter.join();
+    }
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(s->device);
+    for (Slot &sl : s->slots) {
+        (void)hipStreamSynchronize(sl.stream);
+        (void)hipFree(sl.d_summ);
+        (void)hipHostFree(sl.h_summ);
+        (void)hipEventDestroy(sl.done);
+        (void)hipStreamDestroy(sl.stream);
+    }
+    (void)hipSetDevice(prev);
+    delete s;
+}
+
+} // extern "C"

@@ -91,6 +91,19 @@ def test_batch_argument_errors():
     assert "ensemble 1" in lib.rsaw_last_error().decode()
 
 
+def test_server_argument_errors():
+    lib = _lib()
+    h = C.c_void_p()
+    bad = rs.rsaw_server_params(1 << 20, 0, 1)
+    assert lib.rsaw_server_create(C.byref(bad), 0, C.byref(h)) == 1
+    bad = rs.rsaw_server_params(1 << 20, 8, 17)
+    assert lib.rsaw_server_create(C.byref(bad), 0, C.byref(h)) == 1
+    assert lib.rsaw_server_create(None, 0, None) == 1
+    assert lib.rsaw_server_submit(None, None, None) == 1
+    assert lib.rsaw_server_wait(None, 1, None, None) == 1
+    lib.rsaw_server_destroy(None)
+
+
 def test_kernel_timing_switch_without_launches():
     lib = _lib()
     assert lib.rsaw_kernel_timing(1) == 0

@@ -1,0 +1,94 @@
+"""Serving loop (rsaw_server_*): results served in any mix equal stand-alone
+rsaw_gen_chains calls; tickets, polling, concurrency and shutdown."""
+from __future__ import annotations
+
+import math
+import threading
+
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1704_04381_amd as rs
+from paper_1704_04381_amd.workloads import mixed_ensembles
+
+pytestmark = pytest.mark.gpu
+
+_TIMING_KEYS = ("queue_us", "latency_us")
+
+
+def _equal(served, alone):
+    for key, v in alone.items():
+        w = served[key]
+        if isinstance(v, float) and math.isnan(v):
+            assert math.isnan(w), key
+        else:
+            assert w == v, (key, w, v)
+
+
+def _alone(sp):
+    sp = dict(sp)
+    _, s = rs.gen_chains(sp.pop("geometry"), sp.pop("N"), sp.pop("k"), sp.pop("n_chains"), sp.pop("seed"),
+                         per_chain=False, **sp)
+    return s
+
+
+def test_served_results_equal_single_calls():
+    specs = mixed_ensembles(n=60, meta_seed=5, m_lo=2.0, m_span=2.5)
+    print("[gpu] server: 60 mixed requests", flush=True)
+    with rs.Server(max_batch=16, streams=3) as srv:
+        tickets = [srv.submit(**sp) for sp in specs]
+        served = [srv.wait(t) for t in tickets]
+    for sp, s in zip(specs, served):
+        assert s["latency_us"] >= s["queue_us"] >= 0.0
+        _equal(s, _alone(sp))
+
+
+def test_same_request_in_different_mixes():
+    probe = dict(geometry="lattice", N=48, k=6, n_chains=5_000, seed=777, coord="i32", hist_bins=0)
+    with rs.Server(max_batch=8, streams=2) as srv:
+        a = srv.submit(**probe)
+        others = [srv.submit(**sp) for sp in mixed_ensembles(n=30, meta_seed=9, m_lo=2.0, m_span=2.0)]
+        b = srv.submit(**probe)
+        ra, rb = srv.wait(a), srv.wait(b)
+        for t in others:
+            srv.wait(t)
+    for key in ra:
+        if key not in _TIMING_KEYS:
+            assert ra[key] == rb[key] or (isinstance(ra[key], float) and math.isnan(ra[key])), key
+
+
+def test_polling_and_concurrent_submitters():
+    specs = mixed_ensembles(n=80, meta_seed=6, m_lo=2.0, m_span=1.5)
+    got = {}
+    with rs.Server(max_batch=32, streams=2) as srv:
+        def worker(part):
+            for i in part:
+                got[i] = srv.submit(**specs[i])
+
+        th = [threading.Thread(target=worker, args=(range(j, 80, 2),)) for j in range(2)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        pending = dict(got)
+        results = {}
+        while pending:
+            for i, t in list(pending.items()):
+                r = srv.poll(t)
+                if r is not None:
+                    results[i] = r
+                    del pending[i]
+    for i in (0, 17, 42, 79):
+        _equal(results[i], _alone(specs[i]))
+
+
+def test_invalid_requests_and_shutdown_with_pending_work():
+    srv = rs.Server(max_batch=4, streams=1, bytes_per_stream=64 << 20)
+    with pytest.raises(rs.RsawError):
+        srv.submit("real", 16, 65, 10, 1)
+    with pytest.raises(rs.RsawError):
+        srv.submit("lattice", 16, 6, 10_000_000, 1)  # beyond the admission budget
+    for sp in mixed_ensembles(n=20, meta_seed=8, m_lo=3.0, m_span=1.0):
+        srv.submit(**sp)
+    srv.close()  # finishes or fails whatever is queued, then stops
