@@ -222,6 +222,52 @@ def run_batch(torch, rs, reps, m_lo=3.0, m_span=3.0):
     }
 
 
+def run_serving(rs, rate, n, warmup, streams=2, max_batch=64, m_lo=4.0, m_span=3.0):
+    """Open-loop serving run: requests submitted at their Poisson arrival
+    times by one thread, completions taken by another; latency =
+    completion - submission (host clock), measured after `warmup` requests."""
+    import threading
+
+    from paper_1704_04381_amd.workloads import serving_requests
+
+    reqs = serving_requests(n=n, rate=rate, m_lo=m_lo, m_span=m_span)
+    srv = rs.Server(max_batch=max_batch, streams=streams)
+    tickets = [None] * n
+    ready = [threading.Event() for _ in range(n)]
+    t0 = time.perf_counter()
+
+    def submitter():
+        for i, (at, sp) in enumerate(reqs):
+            d = t0 + at - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            tickets[i] = srv.submit(**sp)
+            ready[i].set()
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    lat, done_t = [], []
+    for i in range(n):
+        ready[i].wait()
+        r = srv.wait(tickets[i])
+        if i >= warmup:
+            lat.append(r["latency_us"] / 1e3)
+        done_t.append(time.perf_counter())
+    th.join()
+    srv.close()
+    work = [sp["n_chains"] * (sp["N"] - 1) for _, sp in reqs]
+    t_first = t0 + reqs[warmup][0]
+    span = max(done_t[warmup:]) - t_first
+    measured = sum(work[warmup:])
+    offered = sum(work) / reqs[-1][0]
+    achieved = measured / span
+    return {
+        "rate_per_s": rate, "requests": n, "warmup": warmup, "streams": streams, "max_batch": max_batch,
+        "latency_p50_ms": _percentile(lat, 0.5), "latency_p99_ms": _percentile(lat, 0.99),
+        "throughput_steps_per_s": achieved, "offered_steps_per_s": offered, "span_s": span,
+    }
+
+
 def cpu_baseline(w, sample_chains, threads):
     """The oracle, untuned, on the host cores: a bounded sample of the same
     workload (its first `sample_chains` chains), split over threads."""
@@ -262,6 +308,8 @@ def main():
     ap.add_argument("--workload", default="lattice_n64")
     ap.add_argument("--secondary", default="real_n64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve", action="store_true",
+                    help="only run the serving benchmark (open-loop Poisson requests; about 2 minutes)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the mixed 256-ensemble batched-launch measurement")
     ap.add_argument("--cpu-sample", type=int, default=0)
@@ -283,6 +331,26 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs an MI355X GPU", file=sys.stderr)
         sys.exit(2)
+    if args.serve:
+        rs.load()
+        out = {"metric": "serving: Poisson requests (N = 16..256, lattice / hard spheres, 10^4..10^7 "
+                         "chains each), latency p50/p99 and throughput", "unit": "ms / monomer-steps/s",
+               "runs": []}
+        for rate, n, warm in ((200.0, 2100, 100), (20.0, 300, 30), (5.0, 150, 15)):
+            print(f"[serve] rate {rate}/s, {n} requests", file=sys.stderr, flush=True)
+            out["runs"].append(run_serving(rs, rate, n, warm))
+        # the 200/s run is overloaded: its throughput is the capacity, and
+        # rho = offered work / capacity for every run
+        from paper_1704_04381_amd.workloads import serving_requests
+
+        cap = out["runs"][0]["throughput_steps_per_s"]
+        for r in out["runs"]:
+            r["rho"] = r["offered_steps_per_s"] / cap
+        mean_work = sum(sp["n_chains"] * (sp["N"] - 1) for _, sp in serving_requests()) / 2100
+        out["capacity_steps_per_s"] = cap
+        out["max_sustainable_rate_per_s"] = cap / mean_work
+        print(json.dumps(out), flush=True)
+        return
     if args.copy_calibration:
         n = args.copy_calibration * (1 << 20)
         src = torch.ones(n, dtype=torch.uint8, device="cuda")

@@ -55,3 +55,36 @@ def mixed_ensembles(n=256, meta_seed=42, m_lo=3.0, m_span=3.0):
             out.append(dict(geometry="real", N=N, k=k, n_chains=M, seed=seed, coord="f64",
                             bond_length=1.0, bead_diameter=1.0))
     return out
+
+
+def serving_requests(n=2100, rate=200.0, meta_seed=7, m_lo=4.0, m_span=3.0):
+    """Request stream of the serving workload: Poisson arrivals at ``rate``
+    per second (exponential gaps) and per-request descriptors, all from
+    NumPy's Philox4x32-10 keyed by ``meta_seed``.
+
+    Request r draws (u_gap, u_N, u_geo, u_M): gap = -ln(1 - u_gap) / rate;
+    N = (16, 32, 64, 128, 256)[floor(5 u_N)]; lattice (k = 6) when
+    u_geo < 1/2, else hard spheres (k = 8, b = sigma = 1); M =
+    floor(10^(m_lo + m_span u_M)) chains; seed = meta_seed * 2^20 + r.
+    Returns a list of (arrival_seconds, spec) with spec as for ``gen_chains``.
+    """
+    import math
+
+    import numpy as np
+
+    g = np.random.Generator(np.random.Philox(key=meta_seed))
+    u = g.random((n, 4))
+    t = 0.0
+    out = []
+    for r in range(n):
+        t += -math.log(1.0 - u[r, 0]) / rate
+        N = (16, 32, 64, 128, 256)[min(int(5 * u[r, 1]), 4)]
+        M = int(10.0 ** (m_lo + m_span * u[r, 3]))
+        seed = meta_seed * (1 << 20) + r
+        if u[r, 2] < 0.5:
+            spec = dict(geometry="lattice", N=N, k=6, n_chains=M, seed=seed, coord="i32")
+        else:
+            spec = dict(geometry="real", N=N, k=8, n_chains=M, seed=seed, coord="f64",
+                        bond_length=1.0, bead_diameter=1.0)
+        out.append((t, spec))
+    return out
