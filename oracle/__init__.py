@@ -57,17 +57,17 @@ def _load():
         u64, i32, dbl, vp = C.c_uint64, C.c_int32, C.c_double, C.c_void_p
         lib.oro_philox4x32_10.argtypes = [vp, u64, vp]
         lib.oro_philox4x32_10.restype = None
-        lib.oro_lattice_chain.argtypes = [u64, u64, i32] + [vp] * 10
+        lib.oro_lattice_chain.argtypes = [u64, u64, i32] + [vp] * 10 + [i32, vp]
         lib.oro_lattice_chain.restype = C.c_int
-        lib.oro_real_chain.argtypes = [u64, u64, i32, i32, dbl, dbl] + [vp] * 7
+        lib.oro_real_chain.argtypes = [u64, u64, i32, i32, dbl, dbl] + [vp] * 7 + [i32, vp]
         lib.oro_real_chain.restype = C.c_int
         lib.oro_unit_vector.argtypes = [u64, u64, C.c_uint32, C.c_uint32, vp, vp]
         lib.oro_unit_vector.restype = C.c_int
         lib.oro_overlaps.argtypes = [vp, vp, dbl]
         lib.oro_overlaps.restype = C.c_int
-        lib.oro_gen_lattice.argtypes = [u64, u64, u64, i32] + [vp] * 8
+        lib.oro_gen_lattice.argtypes = [u64, u64, u64, i32] + [vp] * 8 + [i32]
         lib.oro_gen_lattice.restype = C.c_int
-        lib.oro_gen_real.argtypes = [u64, u64, u64, i32, i32, dbl, dbl] + [vp] * 5
+        lib.oro_gen_real.argtypes = [u64, u64, u64, i32, i32, dbl, dbl] + [vp] * 5 + [i32]
         lib.oro_gen_real.restype = C.c_int
         lib.oro_reduce.argtypes = [u64, i32, vp, vp, vp, vp, i32, vp, vp, vp]
         lib.oro_reduce.restype = None
@@ -135,38 +135,47 @@ def overlaps(c, r, sigma2):
     return bool(lib.oro_overlaps(_p(c), _p(r), sigma2))
 
 
-def lattice_chain(seed, chain, N):
-    """One lattice chain with its coordinates and the m_i sequence."""
+RESTART = 2  # flag: a dead end restarts the chain with the next round of random numbers
+
+
+def lattice_chain(seed, chain, N, restart=False):
+    """One lattice chain with its coordinates and the m_i sequence (of the
+    final growth attempt); ``rounds`` counts the attempts."""
     lib = _load()
     xyz = np.zeros((N, 3), dtype=np.int32)
     mseq = np.zeros(N, dtype=np.int32)
     lw = np.zeros(1); we = np.zeros(1, np.uint64); ok = np.zeros(1, np.int32)
     g = np.zeros(1, np.int32); e = np.zeros(3, np.int32)
     r2 = np.zeros(1, np.int64); nn = np.zeros(1, np.int64); rg = np.zeros(1)
+    rounds = np.zeros(1, np.int32)
     _check(lib.oro_lattice_chain(seed, chain, N, _p(xyz), _p(mseq), _p(lw), _p(we),
-                                 _p(ok), _p(g), _p(e), _p(r2), _p(nn), _p(rg)),
+                                 _p(ok), _p(g), _p(e), _p(r2), _p(nn), _p(rg),
+                                 RESTART if restart else 0, _p(rounds)),
            "lattice_chain")
     n = int(g[0])
     return dict(xyz=xyz[:n], m=mseq, log_w=float(lw[0]), w_exact=int(we[0]),
                 w_exact_ok=bool(ok[0]), n_grown=n, end=e, r2=int(r2[0]),
-                n2rg2=int(nn[0]), rg2=float(rg[0]))
+                n2rg2=int(nn[0]), rg2=float(rg[0]), rounds=int(rounds[0]))
 
 
-def real_chain(seed, chain, N, k, b=1.0, sigma=1.0):
-    """One hard-sphere chain with its coordinates and the m_i sequence."""
+def real_chain(seed, chain, N, k, b=1.0, sigma=1.0, restart=False):
+    """One hard-sphere chain with its coordinates and the m_i sequence (of the
+    final growth attempt); ``rounds`` counts the attempts."""
     lib = _load()
     xyz = np.zeros((N, 3))
     mseq = np.zeros(N, dtype=np.int32)
     lw = np.zeros(1); g = np.zeros(1, np.int32); e = np.zeros(3)
     r2 = np.zeros(1); rg = np.zeros(1)
+    rounds = np.zeros(1, np.int32)
     _check(lib.oro_real_chain(seed, chain, N, k, b, sigma, _p(xyz), _p(mseq), _p(lw),
-                              _p(g), _p(e), _p(r2), _p(rg)), "real_chain")
+                              _p(g), _p(e), _p(r2), _p(rg), RESTART if restart else 0,
+                              _p(rounds)), "real_chain")
     n = int(g[0])
     return dict(xyz=xyz[:n], m=mseq, log_w=float(lw[0]), n_grown=n, end=e,
-                r2=float(r2[0]), rg2=float(rg[0]))
+                r2=float(r2[0]), rg2=float(rg[0]), rounds=int(rounds[0]))
 
 
-def gen_lattice(seed, N, n_chains, chain_offset=0):
+def gen_lattice(seed, N, n_chains, chain_offset=0, restart=False):
     """Per-chain lattice outputs for chains chain_offset .. +n_chains-1."""
     lib = _load()
     n = int(n_chains)
@@ -177,11 +186,12 @@ def gen_lattice(seed, N, n_chains, chain_offset=0):
     _check(lib.oro_gen_lattice(seed, chain_offset, n, N, _p(out["log_w"]),
                                _p(out["w_exact"]), _p(out["w_exact_ok"]),
                                _p(out["r_end"]), _p(out["r2"]), _p(out["n2rg2"]),
-                               _p(out["rg2"]), _p(out["n_grown"])), "gen_lattice")
+                               _p(out["rg2"]), _p(out["n_grown"]), RESTART if restart else 0),
+           "gen_lattice")
     return out
 
 
-def gen_real(seed, N, k, n_chains, b=1.0, sigma=1.0, chain_offset=0):
+def gen_real(seed, N, k, n_chains, b=1.0, sigma=1.0, chain_offset=0, restart=False):
     """Per-chain hard-sphere outputs for chains chain_offset .. +n_chains-1."""
     lib = _load()
     n = int(n_chains)
@@ -189,7 +199,7 @@ def gen_real(seed, N, k, n_chains, b=1.0, sigma=1.0, chain_offset=0):
                rg2=np.zeros(n), n_grown=np.zeros(n, np.int32))
     _check(lib.oro_gen_real(seed, chain_offset, n, N, k, b, sigma, _p(out["log_w"]),
                             _p(out["r_end"]), _p(out["r2"]), _p(out["rg2"]),
-                            _p(out["n_grown"])), "gen_real")
+                            _p(out["n_grown"]), RESTART if restart else 0), "gen_real")
     return out
 
 

@@ -84,6 +84,8 @@ static void draw_block(uint64_t seed, uint64_t chain, uint32_t c2,
 #define SLOT_SELECT 0xFFFFu   /* primary selection half-words, one block per 8 steps */
 #define SLOT_REDRAW 0xFFFEu   /* Lemire redraw half-words for step i                */
 #define MAX_ATTEMPT 65536u
+#define ORO_RESTART 2        /* flag: a dead end restarts the chain (Sec. 3.3.2)  */
+#define MAX_ROUNDS 65536u    /* growth attempts of a chain with ORO_RESTART       */
 
 /* 16-bit half h (0..7) of a Philox block: word h / 2, low half for even h. */
 static uint32_t half_word(const uint32_t blk[4], uint32_t h)
@@ -108,13 +110,15 @@ int oro_lemire16(uint32_t x, uint32_t m, uint32_t *index)
     return 1;
 }
 
-/* The pick of step i; *redraws counts the rejected half-words. */
+/* The pick of step i; *redraws counts the rejected half-words.  `step` is
+ * the step word i | (r << 16) of growth attempt r (restarts): the primary
+ * block has c2 = (i >> 3) | (r << 16), the redraw blocks c2 = step. */
 int oro_pick(uint64_t seed, uint64_t chain, uint32_t step, uint32_t m,
              uint32_t *index, uint32_t *redraws)
 {
     uint32_t blk[4];
     uint32_t rejected = 0;
-    draw_block(seed, chain, step >> 3, SLOT_SELECT, 0, blk);
+    draw_block(seed, chain, ((step & 0xFFFFu) >> 3) | (step & 0xFFFF0000u), SLOT_SELECT, 0, blk);
     if (oro_lemire16(half_word(blk, step & 7u), m, index)) {
         if (redraws) *redraws = 0;
         return ORO_OK;
@@ -179,18 +183,29 @@ static const int32_t LATTICE_DIR[6][3] = {
 int oro_lattice_chain(uint64_t seed, uint64_t chain, int32_t N,
                       int32_t *xyz, int32_t *m_seq, double *log_w,
                       uint64_t *w_exact, int32_t *w_exact_ok, int32_t *n_grown,
-                      int32_t end[3], int64_t *r2, int64_t *n2rg2, double *rg2)
+                      int32_t end[3], int64_t *r2, int64_t *n2rg2, double *rg2,
+                      int32_t flags, int32_t *rounds)
 {
     if (N < 1) return ORO_E_INVALID;
     int32_t *pos = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)N);
     if (!pos) return ORO_E_NOMEM;
-    pos[0] = 0; pos[1] = 0; pos[2] = 0;
-    int64_t n_of_m[7] = {0, 0, 0, 0, 0, 0, 0}; /* steps with m_i = m */
-    uint64_t w = 1;
-    int w_ok = 1;
-    int32_t g = 1;
-    int dead = 0;
+    int64_t n_of_m[7];
+    uint64_t w;
+    int w_ok;
+    int32_t g;
+    int dead;
     int status = ORO_OK;
+    const uint32_t max_rounds = (flags & ORO_RESTART) ? MAX_ROUNDS : 1u;
+    uint32_t round = 0;
+    /* A dead end discards the attempt and, with ORO_RESTART, the chain grows
+     * again from the origin with the next round of random numbers. */
+    for (;;) {
+    pos[0] = 0; pos[1] = 0; pos[2] = 0;
+    for (int q = 0; q < 7; ++q) n_of_m[q] = 0; /* steps with m_i = m */
+    w = 1;
+    w_ok = 1;
+    g = 1;
+    dead = 0;
     if (m_seq) m_seq[0] = 0;
 
     for (int32_t i = 1; i < N; ++i) {
@@ -214,7 +229,7 @@ int oro_lattice_chain(uint64_t seed, uint64_t chain, int32_t N,
             break;
         }
         uint32_t pick;
-        status = pick_uniform(seed, chain, (uint32_t)i, m, &pick);
+        status = pick_uniform(seed, chain, (uint32_t)i | (round << 16), m, &pick);
         if (status != ORO_OK) break;
         int chosen = -1;
         uint32_t seen = 0;
@@ -232,10 +247,14 @@ int oro_lattice_chain(uint64_t seed, uint64_t chain, int32_t N,
         if (w_ok && w > UINT64_MAX / m) w_ok = 0;
         if (w_ok) w = w * m;
     }
+    if (status != ORO_OK || !dead || round + 1 >= max_rounds) break;
+    ++round;
+    }
     if (status != ORO_OK) {
         free(pos);
         return status;
     }
+    if (rounds) *rounds = (int32_t)round + 1;
 
     double lw = log_weight(n_of_m, 6);
 
@@ -314,7 +333,7 @@ int oro_overlaps(const double c[3], const double r[3], double sigma2)
 int oro_real_chain(uint64_t seed, uint64_t chain, int32_t N, int32_t k,
                    double b, double sigma, double *xyz, int32_t *m_seq,
                    double *log_w, int32_t *n_grown, double end[3], double *r2,
-                   double *rg2)
+                   double *rg2, int32_t flags, int32_t *rounds)
 {
     if (N < 1 || k < 1 || k > 64 || !(b > 0.0) || !(sigma >= 0.0)) return ORO_E_INVALID;
     double *pos = (double *)malloc(sizeof(double) * 3 * (size_t)N);
@@ -322,20 +341,27 @@ int oro_real_chain(uint64_t seed, uint64_t chain, int32_t N, int32_t k,
     double cand[64][3];
     int free_[64];
     double sigma2 = sigma * sigma;
-    pos[0] = 0.0; pos[1] = 0.0; pos[2] = 0.0;
     int64_t n_of_m[65];
-    for (int q = 0; q <= 64; ++q) n_of_m[q] = 0;
-    int32_t g = 1;
-    int dead = 0;
+    int32_t g;
+    int dead;
     int status = ORO_OK;
+    const uint32_t max_rounds = (flags & ORO_RESTART) ? MAX_ROUNDS : 1u;
+    uint32_t round = 0;
+    /* Restart rule as for the lattice. */
+    for (;;) {
+    pos[0] = 0.0; pos[1] = 0.0; pos[2] = 0.0;
+    for (int q = 0; q <= 64; ++q) n_of_m[q] = 0;
+    g = 1;
+    dead = 0;
     if (m_seq) m_seq[0] = 0;
 
     for (int32_t i = 1; i < N && status == ORO_OK; ++i) {
         const double *tip = &pos[3 * (i - 1)];
+        const uint32_t sw = (uint32_t)i | (round << 16); /* step word */
         uint32_t m = 0;
         for (int32_t t = 0; t < k; ++t) {
             double e[3];
-            status = oro_unit_vector(seed, chain, (uint32_t)i, (uint32_t)t, e, NULL);
+            status = oro_unit_vector(seed, chain, sw, (uint32_t)t, e, NULL);
             if (status != ORO_OK) break;
             cand[t][0] = tip[0] + b * e[0];
             cand[t][1] = tip[1] + b * e[1];
@@ -353,7 +379,7 @@ int oro_real_chain(uint64_t seed, uint64_t chain, int32_t N, int32_t k,
             break;
         }
         uint32_t pick;
-        status = pick_uniform(seed, chain, (uint32_t)i, m, &pick);
+        status = pick_uniform(seed, chain, sw, m, &pick);
         if (status != ORO_OK) break;
         int chosen = -1;
         uint32_t seen = 0;
@@ -369,10 +395,14 @@ int oro_real_chain(uint64_t seed, uint64_t chain, int32_t N, int32_t k,
         g = i + 1;
         n_of_m[m] += 1;
     }
+    if (status != ORO_OK || !dead || round + 1 >= max_rounds) break;
+    ++round;
+    }
     if (status != ORO_OK) {
         free(pos);
         return status;
     }
+    if (rounds) *rounds = (int32_t)round + 1;
     double lw = log_weight(n_of_m, k);
 
     double sx = 0.0, sy = 0.0, sz = 0.0;
@@ -413,7 +443,7 @@ int oro_real_chain(uint64_t seed, uint64_t chain, int32_t N, int32_t k,
 int oro_gen_lattice(uint64_t seed, uint64_t chain_offset, uint64_t n, int32_t N,
                     double *log_w, uint64_t *w_exact, int32_t *w_exact_ok,
                     int32_t *r_end, int64_t *r2, int64_t *n2rg2, double *rg2,
-                    int32_t *n_grown)
+                    int32_t *n_grown, int32_t flags)
 {
     for (uint64_t c = 0; c < n; ++c) {
         double lw, rg;
@@ -421,7 +451,7 @@ int oro_gen_lattice(uint64_t seed, uint64_t chain_offset, uint64_t n, int32_t N,
         int32_t ok, g, e[3];
         int64_t rr, nn;
         int s = oro_lattice_chain(seed, chain_offset + c, N, NULL, NULL, &lw, &we, &ok,
-                                  &g, e, &rr, &nn, &rg);
+                                  &g, e, &rr, &nn, &rg, flags, NULL);
         if (s != ORO_OK) return s;
         if (log_w) log_w[c] = lw;
         if (w_exact) w_exact[c] = we;
@@ -437,13 +467,13 @@ int oro_gen_lattice(uint64_t seed, uint64_t chain_offset, uint64_t n, int32_t N,
 
 int oro_gen_real(uint64_t seed, uint64_t chain_offset, uint64_t n, int32_t N, int32_t k,
                  double b, double sigma, double *log_w, double *r_end, double *r2,
-                 double *rg2, int32_t *n_grown)
+                 double *rg2, int32_t *n_grown, int32_t flags)
 {
     for (uint64_t c = 0; c < n; ++c) {
         double lw, e[3], rr, rg;
         int32_t g;
         int s = oro_real_chain(seed, chain_offset + c, N, k, b, sigma, NULL, NULL, &lw, &g,
-                               e, &rr, &rg);
+                               e, &rr, &rg, flags, NULL);
         if (s != ORO_OK) return s;
         if (log_w) log_w[c] = lw;
         if (r_end) { r_end[c] = e[0]; r_end[n + c] = e[1]; r_end[2 * n + c] = e[2]; }
