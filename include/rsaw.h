@@ -64,6 +64,16 @@ typedef enum {
 
 /* flags */
 #define RSAW_EXACT_W 1u /* lattice: also keep W exactly as uint64 (needs N <= 28) */
+/*
+ * RSAW_RESTART: a dead end discards the chain and grows it again from the
+ * origin (the rule of Sec. 3.3.2 and 3.3.3), up to 65536 attempts; attempt
+ * r draws its random numbers with r in the high 16 bits of the step word of
+ * the Philox counter (attempt 0 is the stream used without the flag).  The
+ * outputs are those of the first complete attempt (a chain that fails every
+ * attempt is dead, as without the flag).  The mean weight then estimates
+ * c_n / P(complete) rather than c_n.
+ */
+#define RSAW_RESTART 2u
 
 typedef struct {
     int32_t geometry;      /* RSAW_LATTICE_SC or RSAW_REAL_HS                        */
@@ -76,7 +86,7 @@ typedef struct {
     double bond_length;    /* b > 0 (real space; the lattice constant is 1)          */
     double bead_diameter;  /* sigma >= 0 (real space; 0 = ideal chain)               */
     int32_t hist_bins;     /* B >= 0 bins of the R^2 histogram over [0, (N-1)^2]     */
-    uint32_t flags;        /* RSAW_EXACT_W                                           */
+    uint32_t flags;        /* RSAW_EXACT_W | RSAW_RESTART                            */
 } rsaw_config;
 
 /*

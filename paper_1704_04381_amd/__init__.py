@@ -22,6 +22,7 @@ RSAW_LATTICE_SC = 0
 RSAW_REAL_HS = 1
 RSAW_I16, RSAW_I32, RSAW_F64 = 0, 1, 2
 RSAW_EXACT_W = 1
+RSAW_RESTART = 2
 
 STATUS = {0: "RSAW_OK", 1: "RSAW_E_INVALID", 2: "RSAW_E_UNSUPPORTED", 3: "RSAW_E_OVERFLOW",
           4: "RSAW_E_NOMEM", 5: "RSAW_E_DEVICE", 6: "RSAW_E_RNG"}
@@ -129,7 +130,7 @@ def _check(status):
 
 
 def make_config(geometry, N, k, n_chains, seed, *, coord=None, chain_offset=0,
-                bond_length=1.0, bead_diameter=1.0, hist_bins=0, exact_w=False):
+                bond_length=1.0, bead_diameter=1.0, hist_bins=0, exact_w=False, restart=False):
     geo = {"lattice": RSAW_LATTICE_SC, "real": RSAW_REAL_HS}[geometry] \
         if isinstance(geometry, str) else int(geometry)
     if coord is None:
@@ -137,7 +138,7 @@ def make_config(geometry, N, k, n_chains, seed, *, coord=None, chain_offset=0,
     ct = {"i16": RSAW_I16, "i32": RSAW_I32, "f64": RSAW_F64}[coord]
     return rsaw_config(geo, int(N), int(k), ct, int(n_chains), int(seed), int(chain_offset),
                        float(bond_length), float(bead_diameter), int(hist_bins),
-                       RSAW_EXACT_W if exact_w else 0)
+                       (RSAW_EXACT_W if exact_w else 0) | (RSAW_RESTART if restart else 0))
 
 
 def summary_to_dict(s: rsaw_summary) -> dict:
@@ -204,7 +205,7 @@ def _device(device):
 
 
 def gen_chains(geometry, N, k, n_chains, seed, *, coord=None, chain_offset=0,
-               bond_length=1.0, bead_diameter=1.0, hist_bins=0, exact_w=False,
+               bond_length=1.0, bead_diameter=1.0, hist_bins=0, exact_w=False, restart=False,
                per_chain=True, device=None, stream=None, sync=True):
     """Grow ``n_chains`` chains on the GPU and reduce them.
 
@@ -218,7 +219,7 @@ def gen_chains(geometry, N, k, n_chains, seed, *, coord=None, chain_offset=0,
     dev = _device(device)
     cfg = make_config(geometry, N, k, n_chains, seed, coord=coord, chain_offset=chain_offset,
                       bond_length=bond_length, bead_diameter=bead_diameter,
-                      hist_bins=hist_bins, exact_w=exact_w)
+                      hist_bins=hist_bins, exact_w=exact_w, restart=restart)
     out, o = _alloc_outputs(cfg, dev, per_chain, hist_bins)
     summ = torch.empty(SUMMARY_BYTES, dtype=torch.uint8, device=dev)
     if stream is None:

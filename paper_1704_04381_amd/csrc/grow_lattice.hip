@@ -62,110 +62,139 @@ __device__ __forceinline__ void grow_lattice_reg_body(const GrowArgs &a, uint64_
     uint32_t pos[NMAX];
     static_for<0, NMAX>([&](auto J) { pos[J.value] = kOrigin; });
     uint32_t tip = kOrigin;
-    bool alive = valid;
+    bool alive = false;
     int grown = 1;
     uint32_t cntp = 0;
     uint64_t wx = 1;
     bool rng_fail = false;
     Philox4 blk{0, 0, 0, 0};
+    // outputs of the attempt that ends the chain: the first complete one, or
+    // the last allowed one (one attempt without restarts)
+    double res_lw = -__builtin_huge_val();
+    uint64_t res_wx = 0;
+    int64_t res_nn = 0;
+    int32_t res_ex = 0, res_ey = 0, res_ez = 0;
+    int res_grown = 1;
+    bool res_alive = false;
+    bool pending = valid;
 
-    static_for<1, NMAX>([&](auto I) {
-        constexpr int i = I.value;
-        if (i >= N) return;
-        // occupied-neighbour mask from the same-parity monomers, accumulated
-        // in two independent registers to halve the dependency chain
-        const uint32_t tref = tip & 0xFFFFFF00u;
-        const uint32_t tq = tip - 3u;
-        uint32_t occ = 0, occ2 = 0;
-        static_for<0, i / 2>([&](auto Q) {
-            constexpr int j = i - 2 - 2 * Q.value;
-            const uint32_t L = __builtin_amdgcn_msad_u8(pos[j], tref, 0u);
-            const uint32_t bit = __builtin_elementwise_sub_sat(2u, L);
-            if constexpr (Q.value & 1) occ2 = (bit << ((pos[j] - tq) & 31u)) | occ2;
-            else occ = (bit << ((pos[j] - tq) & 31u)) | occ;
-        });
-        occ |= occ2;
-        const uint32_t freem = ~occ & 0x77u;
-        const uint32_t m = __builtin_popcount(freem);
+    for (uint32_t rd = 0; rd < a.max_rounds; ++rd) {
+        if (rd > 0) {
+            static_for<0, NMAX>([&](auto J) { pos[J.value] = pending ? kOrigin : pos[J.value]; });
+            tip = pending ? kOrigin : tip;
+            cntp = pending ? 0u : cntp;
+            wx = pending ? 1ull : wx;
+        }
+        alive = pending;
+        grown = 1;
+        const uint32_t hi = rd << 16; // attempt in the high half of the step word
 
-        // 16-bit selection word: half i mod 8 of one Philox block per 8 steps
-        if constexpr (i == 1 || (i & 7) == 0) blk = draw(a.seed, g, (uint32_t)(i >> 3), kSlotSelect, 0);
-        constexpr int h = i & 7;
-        const uint32_t wd = (h >> 1) == 0 ? blk.x0 : ((h >> 1) == 1 ? blk.x1 : ((h >> 1) == 2 ? blk.x2 : blk.x3));
-        const uint32_t x = (h & 1) ? (wd >> 16) : (wd & 0xFFFFu);
-        const uint32_t p = x * m;
-        uint32_t r = p >> 16;
-        if (__builtin_expect(alive && (p & 0xFFFFu) < m, 0)) {
-            r = lemire_redraw16(a.seed, g, (uint32_t)i, m, x);
-            if (r == kPickFailed) {
-                rng_fail = true;
-                r = 0;
+        static_for<1, NMAX>([&](auto I) {
+            constexpr int i = I.value;
+            if (i >= N) return;
+            // occupied-neighbour mask from the same-parity monomers, accumulated
+            // in two independent registers to halve the dependency chain
+            const uint32_t tref = tip & 0xFFFFFF00u;
+            const uint32_t tq = tip - 3u;
+            uint32_t occ = 0, occ2 = 0;
+            static_for<0, i / 2>([&](auto Q) {
+                constexpr int j = i - 2 - 2 * Q.value;
+                const uint32_t L = __builtin_amdgcn_msad_u8(pos[j], tref, 0u);
+                const uint32_t bit = __builtin_elementwise_sub_sat(2u, L);
+                if constexpr (Q.value & 1) occ2 = (bit << ((pos[j] - tq) & 31u)) | occ2;
+                else occ = (bit << ((pos[j] - tq) & 31u)) | occ;
+            });
+            occ |= occ2;
+            const uint32_t freem = ~occ & 0x77u;
+            const uint32_t m = __builtin_popcount(freem);
+
+            // 16-bit selection word: half i mod 8 of one Philox block per 8 steps
+            if constexpr (i == 1 || (i & 7) == 0)
+                blk = draw(a.seed, g, (uint32_t)(i >> 3) | hi, kSlotSelect, 0);
+            constexpr int h = i & 7;
+            const uint32_t wd = (h >> 1) == 0 ? blk.x0 : ((h >> 1) == 1 ? blk.x1 : ((h >> 1) == 2 ? blk.x2 : blk.x3));
+            const uint32_t x = (h & 1) ? (wd >> 16) : (wd & 0xFFFFu);
+            const uint32_t p = x * m;
+            uint32_t r = p >> 16;
+            if (__builtin_expect(alive && (p & 0xFFFFu) < m, 0)) {
+                r = lemire_redraw16(a.seed, g, (uint32_t)i | hi, m, x);
+                if (r == kPickFailed) {
+                    rng_fail = true;
+                    r = 0;
+                }
             }
-        }
 
-        const bool step_ok = alive && m != 0;
-        const uint32_t mv = lut[(freem << 3) | (r & 7u)];
-        const uint32_t nxt = ((tip & 0xFFFFFF00u) + (mv & 0xFFFFFF00u)) | ((tip + mv) & 0xFFu);
-        if (alive && m == 0) {
-            alive = false;
-            grown = i;
+            const bool step_ok = alive && m != 0;
+            const uint32_t mv = lut[(freem << 3) | (r & 7u)];
+            const uint32_t nxt = ((tip & 0xFFFFFF00u) + (mv & 0xFFFFFF00u)) | ((tip + mv) & 0xFFu);
+            if (alive && m == 0) {
+                alive = false;
+                grown = i;
+            }
+            tip = step_ok ? nxt : tip;
+            pos[i] = tip;
+            if (step_ok) {
+                // n_m field at bit 6 (m - 2) mod 32: m = 2..5 at 0, 6, 12, 18, m = 1
+                // at 26 (unused); step 1 always has m = 6 and is not counted
+                if constexpr (i >= 2) cntp += 1u << ((6u * m + 20u) & 31u);
+                if (EXACT) wx = wx * (uint64_t)m;
+            }
+        });
+        if (alive) grown = N;
+        const bool ends = pending && (alive || rd + 1 >= a.max_rounds);
+        if (ends) {
+            // log W = sum over m = 1..6, ascending, of n_m log m (one rounding
+            // each); n_1 log 1 = 0 and m_1 = 6 always
+            double lw = 0.0;
+            if (N >= 2) {
+                lw = lw + (double)(cntp & 63u) * logm[2];
+                lw = lw + (double)((cntp >> 6) & 63u) * logm[3];
+                lw = lw + (double)((cntp >> 12) & 63u) * logm[4];
+                lw = lw + (double)((cntp >> 18) & 63u) * logm[5];
+                lw = lw + logm[6];
+            }
+            // observables over the g placed monomers, from the biased coordinate bytes
+            uint32_t sx = 0, sy = 0, sz = 0, s2 = 0;
+            static_for<0, NMAX>([&](auto J) {
+                constexpr int j = J.value;
+                const uint32_t w = j < grown ? (pos[j] & 0xFFFFFF00u) : 0u;
+                sx = __builtin_amdgcn_udot4(w, 0x00000100u, sx, false);
+                sy = __builtin_amdgcn_udot4(w, 0x00010000u, sy, false);
+                sz = __builtin_amdgcn_udot4(w, 0x01000000u, sz, false);
+                s2 = __builtin_amdgcn_udot4(w, w, s2, false);
+            });
+            const int64_t gg = grown;
+            const int64_t Sx = (int64_t)sx - 128 * gg, Sy = (int64_t)sy - 128 * gg, Sz = (int64_t)sz - 128 * gg;
+            const int64_t S2 = (int64_t)s2 - 256 * ((int64_t)sx + (int64_t)sy + (int64_t)sz) + 3 * 16384 * gg;
+            res_nn = gg * S2 - (Sx * Sx + Sy * Sy + Sz * Sz);
+            res_ex = (int32_t)((tip >> 8) & 0xFFu) - 128;
+            res_ey = (int32_t)((tip >> 16) & 0xFFu) - 128;
+            res_ez = (int32_t)(tip >> 24) - 128;
+            res_lw = alive ? lw : -__builtin_huge_val();
+            res_wx = alive ? wx : 0ull;
+            res_grown = grown;
+            res_alive = alive;
+            pending = false;
         }
-        tip = step_ok ? nxt : tip;
-        pos[i] = tip;
-        if (step_ok) {
-            // n_m field at bit 6 (m - 2) mod 32: m = 2..5 at 0, 6, 12, 18, m = 1
-            // at 26 (unused); step 1 always has m = 6 and is not counted
-            if constexpr (i >= 2) cntp += 1u << ((6u * m + 20u) & 31u);
-            if (EXACT) wx = wx * (uint64_t)m;
-        }
-    });
-    if (alive) grown = N;
-    // log W = sum over m = 1..6, ascending, of n_m log m (one rounding each);
-    // n_1 log 1 = 0 and m_1 = 6 always
-    double lw = 0.0;
-    if (N >= 2) {
-        lw = lw + (double)(cntp & 63u) * logm[2];
-        lw = lw + (double)((cntp >> 6) & 63u) * logm[3];
-        lw = lw + (double)((cntp >> 12) & 63u) * logm[4];
-        lw = lw + (double)((cntp >> 18) & 63u) * logm[5];
-        lw = lw + logm[6];
+        if (__ballot(pending) == 0) break;
     }
-
-    // observables over the g placed monomers, from the biased coordinate bytes
-    uint32_t sx = 0, sy = 0, sz = 0, s2 = 0;
-    static_for<0, NMAX>([&](auto J) {
-        constexpr int j = J.value;
-        const uint32_t w = j < grown ? (pos[j] & 0xFFFFFF00u) : 0u;
-        sx = __builtin_amdgcn_udot4(w, 0x00000100u, sx, false);
-        sy = __builtin_amdgcn_udot4(w, 0x00010000u, sy, false);
-        sz = __builtin_amdgcn_udot4(w, 0x01000000u, sz, false);
-        s2 = __builtin_amdgcn_udot4(w, w, s2, false);
-    });
-    const int64_t gg = grown;
-    const int64_t Sx = (int64_t)sx - 128 * gg, Sy = (int64_t)sy - 128 * gg, Sz = (int64_t)sz - 128 * gg;
-    const int64_t S2 = (int64_t)s2 - 256 * ((int64_t)sx + (int64_t)sy + (int64_t)sz) + 3 * 16384 * gg;
-    const int64_t nn = gg * S2 - (Sx * Sx + Sy * Sy + Sz * Sz);
-    const int32_t ex = (int32_t)((tip >> 8) & 0xFFu) - 128;
-    const int32_t ey = (int32_t)((tip >> 16) & 0xFFu) - 128;
-    const int32_t ez = (int32_t)(tip >> 24) - 128;
-    const double logw = alive ? lw : -__builtin_huge_val();
 
     if (valid) {
-        if (a.log_w) a.log_w[c] = logw;
-        if (EXACT && a.w_exact) a.w_exact[c] = alive ? wx : 0ull;
+        if (a.log_w) a.log_w[c] = res_lw;
+        if (EXACT && a.w_exact) a.w_exact[c] = res_wx;
         if (a.r_end) {
             CT *re = (CT *)a.r_end;
-            re[c] = (CT)ex;
-            re[a.n_chains + c] = (CT)ey;
-            re[2 * a.n_chains + c] = (CT)ez;
+            re[c] = (CT)res_ex;
+            re[a.n_chains + c] = (CT)res_ey;
+            re[2 * a.n_chains + c] = (CT)res_ez;
         }
-        if (a.r2) a.r2[c] = (double)(ex * ex + ey * ey + ez * ez);
-        if (a.n2rg2) a.n2rg2[c] = nn;
-        if (a.rg2) a.rg2[c] = (double)nn / ((double)gg * (double)gg);
-        if (a.n_grown) a.n_grown[c] = (uint16_t)grown;
+        if (a.r2) a.r2[c] = (double)(res_ex * res_ex + res_ey * res_ey + res_ez * res_ez);
+        if (a.n2rg2) a.n2rg2[c] = res_nn;
+        if (a.rg2) a.rg2[c] = (double)res_nn / ((double)res_grown * (double)res_grown);
+        if (a.n_grown) a.n_grown[c] = (uint16_t)res_grown;
     }
     if (rng_fail) atomicExch(a.status, 6);
-    const uint64_t bits = alive ? (uint64_t)__double_as_longlong(lw) : 0ull;
+    const uint64_t bits = res_alive ? (uint64_t)__double_as_longlong(res_lw) : 0ull;
     const uint64_t wmax = wave_max_u64(bits);
     if ((threadIdx.x & 63) == 0 && wmax != 0) atomicMax(a.log_w_max_bits, (unsigned long long)wmax);
 }

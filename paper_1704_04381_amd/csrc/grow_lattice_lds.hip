@@ -114,157 +114,187 @@ __device__ __forceinline__ void grow_lattice_lds_body(const GrowArgs &a, uint64_
     const int N = a.n_monomers;
     uint32_t *base = chains + chb * S;
 
-    uint32_t ta = WIDE ? kWideOriginA : kByteOrigin; // tip, A word (or the byte word)
-    uint32_t tb = WIDE ? kWideOriginB : 0u;          // tip, B word (wide only)
-    if (t == 0) {
-        base[0] = ta;
-        if constexpr (WIDE) base[H] = tb;
-    }
-    lattice_wave_sync();
-
-    bool alive = valid;
+    uint32_t ta = 0, tb = 0; // tip: A word (or the byte word) and B word (wide only)
+    bool alive = false;
     int grown = 1;
     uint64_t cnt = 0; // 16-bit fields: steps with m = 2, 3, 4, 5 (step 1 has m = 6)
     bool rng_fail = false;
     Philox4 blk{0, 0, 0, 0};
+    // outputs of the attempt that ends the chain (see the register kernel)
+    double res_lw = -__builtin_huge_val();
+    int64_t res_nn = 0;
+    int32_t res_ex = 0, res_ey = 0, res_ez = 0;
+    int res_grown = 1;
+    bool res_alive = false;
+    bool pending = valid;
 
-    for (int i = 1; i < N; ++i) {
-        // occupied-neighbour mask: the group scans the plane of parity i
-        const uint32_t *pa = base + (i & 1) * WPM * H;
-        const uint32_t *pb = pa + H;
-        const int nrel = i >> 1;
-        const int passes = (nrel + 4 * G - 1) / (4 * G);
-        const uint32_t tref = WIDE ? ta : (ta & 0xFFFFFF00u);
-        const uint32_t tbh = tb & 0xFFFF0000u;
-        const uint32_t tq = (WIDE ? tb : ta) - 3u;
-        uint32_t occ = 0, occ2 = 0;
-        for (int q = 0; q < passes; ++q) {
-            const int k = q * 4 * G + 4 * t;
-            const uint4 wa = *(const uint4 *)(pa + k);
-            uint4 wb = make_uint4(0u, 0u, 0u, 0u);
-            if constexpr (WIDE) wb = *(const uint4 *)(pb + k);
-            occ |= pair_bits<WIDE>(wa.x, wb.x, tref, tbh, tq);
-            occ2 |= pair_bits<WIDE>(wa.y, wb.y, tref, tbh, tq);
-            occ |= pair_bits<WIDE>(wa.z, wb.z, tref, tbh, tq);
-            occ2 |= pair_bits<WIDE>(wa.w, wb.w, tref, tbh, tq);
-        }
-        occ |= occ2;
-        occ = group_or<G>(occ);
-        const uint32_t freem = ~occ & 0x77u;
-        const uint32_t m = __builtin_popcount(freem);
-
-        // 16-bit selection word: half i mod 8 of one Philox block per 8 steps
-        if (i == 1 || (i & 7) == 0) blk = draw(a.seed, g, (uint32_t)(i >> 3), kSlotSelect, 0);
-        const uint32_t x = half_word(blk, (uint32_t)(i & 7));
-        const uint32_t p = x * m;
-        uint32_t r = p >> 16;
-        if (__builtin_expect(alive && (p & 0xFFFFu) < m, 0)) {
-            r = lemire_redraw16(a.seed, g, (uint32_t)i, m, x);
-            if (r == kPickFailed) {
-                rng_fail = true;
-                r = 0;
-            }
-        }
-
-        const bool step_ok = alive && m != 0;
-        const uint32_t li = (freem << 3) | (r & 7u);
-        uint32_t na, nb = 0u;
-        if constexpr (WIDE) {
-            na = ta + lut[li];
-            nb = ((tb + lutb[li]) & 0xFFFF001Fu) | 0x40u;
-        } else {
-            const uint32_t mv = lut[li];
-            na = ((ta & 0xFFFFFF00u) + (mv & 0xFFFFFF00u)) | ((ta + mv) & 0xFFu);
-        }
-        if (alive && m == 0) {
-            alive = false;
-            grown = i;
-        }
-        if (step_ok) {
-            ta = na;
-            tb = nb;
-            if (i >= 2 && m >= 2) cnt += 1ull << (16u * (m - 2u));
-            if (t == 0) {
-                uint32_t *wp = base + (i & 1) * WPM * H + (i >> 1);
-                wp[0] = na;
-                if constexpr (WIDE) wp[H] = nb;
-            }
+    for (uint32_t rd = 0; rd < a.max_rounds; ++rd) {
+        // (re)start the chains still growing: clear their planes back to the
+        // sentinel and place monomer 0 at the origin
+        if (pending) {
+            if (rd > 0)
+                for (int w = t; w < S; w += G) base[w] = 0u;
+            ta = WIDE ? kWideOriginA : kByteOrigin;
+            tb = WIDE ? kWideOriginB : 0u;
+            cnt = 0;
         }
         lattice_wave_sync();
-    }
-    if (alive) grown = N;
-
-    // log W = sum over m = 1..6, ascending, of n_m log m; n_1 log 1 = 0 and
-    // m_1 = 6 always
-    double lw = 0.0;
-    if (N >= 2) {
-        lw = lw + (double)(uint32_t)(cnt & 0xFFFFu) * a.logm[2];
-        lw = lw + (double)(uint32_t)((cnt >> 16) & 0xFFFFu) * a.logm[3];
-        lw = lw + (double)(uint32_t)((cnt >> 32) & 0xFFFFu) * a.logm[4];
-        lw = lw + (double)(uint32_t)((cnt >> 48) & 0xFFFFu) * a.logm[5];
-        lw = lw + a.logm[6];
-    }
-
-    // observables over the placed monomers (integer sums: any order)
-    int32_t sx = 0, sy = 0, sz = 0;
-    int64_t s2 = 0;
-    for (int j = t; j < grown; j += G) {
-        const uint32_t *wp = base + (j & 1) * WPM * H + (j >> 1);
-        int32_t x, y, z;
-        if constexpr (WIDE) {
-            const uint32_t wa = wp[0], wb = wp[H];
-            x = (int32_t)(wa & 0xFFFFu) - 32768;
-            y = (int32_t)(wa >> 16) - 32768;
-            z = (int32_t)(wb >> 16) - 32768;
-        } else {
-            const uint32_t w = wp[0];
-            x = (int32_t)((w >> 8) & 0xFFu) - 128;
-            y = (int32_t)((w >> 16) & 0xFFu) - 128;
-            z = (int32_t)(w >> 24) - 128;
+        if (pending && t == 0) {
+            base[0] = ta;
+            if constexpr (WIDE) base[H] = tb;
         }
-        sx += x;
-        sy += y;
-        sz += z;
-        s2 += (int64_t)(x * x + y * y + z * z);
+        lattice_wave_sync();
+        alive = pending;
+        grown = 1;
+        const uint32_t hi = rd << 16; // attempt in the high half of the step word
+
+        for (int i = 1; i < N; ++i) {
+            // occupied-neighbour mask: the group scans the plane of parity i
+            const uint32_t *pa = base + (i & 1) * WPM * H;
+            const uint32_t *pb = pa + H;
+            const int nrel = i >> 1;
+            const int passes = (nrel + 4 * G - 1) / (4 * G);
+            const uint32_t tref = WIDE ? ta : (ta & 0xFFFFFF00u);
+            const uint32_t tbh = tb & 0xFFFF0000u;
+            const uint32_t tq = (WIDE ? tb : ta) - 3u;
+            uint32_t occ = 0, occ2 = 0;
+            for (int q = 0; q < passes; ++q) {
+                const int k = q * 4 * G + 4 * t;
+                const uint4 wa = *(const uint4 *)(pa + k);
+                uint4 wb = make_uint4(0u, 0u, 0u, 0u);
+                if constexpr (WIDE) wb = *(const uint4 *)(pb + k);
+                occ |= pair_bits<WIDE>(wa.x, wb.x, tref, tbh, tq);
+                occ2 |= pair_bits<WIDE>(wa.y, wb.y, tref, tbh, tq);
+                occ |= pair_bits<WIDE>(wa.z, wb.z, tref, tbh, tq);
+                occ2 |= pair_bits<WIDE>(wa.w, wb.w, tref, tbh, tq);
+            }
+            occ |= occ2;
+            occ = group_or<G>(occ);
+            const uint32_t freem = ~occ & 0x77u;
+            const uint32_t m = __builtin_popcount(freem);
+
+            // 16-bit selection word: half i mod 8 of one Philox block per 8 steps
+            if (i == 1 || (i & 7) == 0) blk = draw(a.seed, g, (uint32_t)(i >> 3) | hi, kSlotSelect, 0);
+            const uint32_t x = half_word(blk, (uint32_t)(i & 7));
+            const uint32_t p = x * m;
+            uint32_t r = p >> 16;
+            if (__builtin_expect(alive && (p & 0xFFFFu) < m, 0)) {
+                r = lemire_redraw16(a.seed, g, (uint32_t)i | hi, m, x);
+                if (r == kPickFailed) {
+                    rng_fail = true;
+                    r = 0;
+                }
+            }
+
+            const bool step_ok = alive && m != 0;
+            const uint32_t li = (freem << 3) | (r & 7u);
+            uint32_t na, nb = 0u;
+            if constexpr (WIDE) {
+                na = ta + lut[li];
+                nb = ((tb + lutb[li]) & 0xFFFF001Fu) | 0x40u;
+            } else {
+                const uint32_t mv = lut[li];
+                na = ((ta & 0xFFFFFF00u) + (mv & 0xFFFFFF00u)) | ((ta + mv) & 0xFFu);
+            }
+            if (alive && m == 0) {
+                alive = false;
+                grown = i;
+            }
+            if (step_ok) {
+                ta = na;
+                tb = nb;
+                if (i >= 2 && m >= 2) cnt += 1ull << (16u * (m - 2u));
+                if (t == 0) {
+                    uint32_t *wp = base + (i & 1) * WPM * H + (i >> 1);
+                    wp[0] = na;
+                    if constexpr (WIDE) wp[H] = nb;
+                }
+            }
+            lattice_wave_sync();
+        }
+        if (alive) grown = N;
+        // log W = sum over m = 1..6, ascending, of n_m log m; n_1 log 1 = 0 and
+        // m_1 = 6 always
+        double lw = 0.0;
+        if (N >= 2) {
+            lw = lw + (double)(uint32_t)(cnt & 0xFFFFu) * a.logm[2];
+            lw = lw + (double)(uint32_t)((cnt >> 16) & 0xFFFFu) * a.logm[3];
+            lw = lw + (double)(uint32_t)((cnt >> 32) & 0xFFFFu) * a.logm[4];
+            lw = lw + (double)(uint32_t)((cnt >> 48) & 0xFFFFu) * a.logm[5];
+            lw = lw + a.logm[6];
+        }
+
+        // observables over the placed monomers (integer sums: any order)
+        int32_t sx = 0, sy = 0, sz = 0;
+        int64_t s2 = 0;
+        for (int j = t; j < grown; j += G) {
+            const uint32_t *wp = base + (j & 1) * WPM * H + (j >> 1);
+            int32_t x, y, z;
+            if constexpr (WIDE) {
+                const uint32_t wa = wp[0], wb = wp[H];
+                x = (int32_t)(wa & 0xFFFFu) - 32768;
+                y = (int32_t)(wa >> 16) - 32768;
+                z = (int32_t)(wb >> 16) - 32768;
+            } else {
+                const uint32_t w = wp[0];
+                x = (int32_t)((w >> 8) & 0xFFu) - 128;
+                y = (int32_t)((w >> 16) & 0xFFu) - 128;
+                z = (int32_t)(w >> 24) - 128;
+            }
+            sx += x;
+            sy += y;
+            sz += z;
+            s2 += (int64_t)(x * x + y * y + z * z);
+        }
+    #pragma unroll
+        for (int off = 1; off < G; off <<= 1) {
+            sx += __shfl_xor(sx, off, 64);
+            sy += __shfl_xor(sy, off, 64);
+            sz += __shfl_xor(sz, off, 64);
+            const int lo = __shfl_xor((int)(uint32_t)s2, off, 64);
+            const int hi = __shfl_xor((int)(uint32_t)((uint64_t)s2 >> 32), off, 64);
+            s2 += (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+        }
+        const int64_t gg = grown;
+        const int64_t nn = gg * s2 - ((int64_t)sx * sx + (int64_t)sy * sy + (int64_t)sz * sz);
+        int32_t ex, ey, ez;
+        if constexpr (WIDE) {
+            ex = (int32_t)(ta & 0xFFFFu) - 32768;
+            ey = (int32_t)(ta >> 16) - 32768;
+            ez = (int32_t)(tb >> 16) - 32768;
+        } else {
+            ex = (int32_t)((ta >> 8) & 0xFFu) - 128;
+            ey = (int32_t)((ta >> 16) & 0xFFu) - 128;
+            ez = (int32_t)(ta >> 24) - 128;
+        }
+        if (pending && (alive || rd + 1 >= a.max_rounds)) {
+            res_lw = alive ? lw : -__builtin_huge_val();
+            res_nn = nn;
+            res_ex = ex;
+            res_ey = ey;
+            res_ez = ez;
+            res_grown = grown;
+            res_alive = alive;
+            pending = false;
+        }
+        if (__ballot(pending) == 0) break;
     }
-#pragma unroll
-    for (int off = 1; off < G; off <<= 1) {
-        sx += __shfl_xor(sx, off, 64);
-        sy += __shfl_xor(sy, off, 64);
-        sz += __shfl_xor(sz, off, 64);
-        const int lo = __shfl_xor((int)(uint32_t)s2, off, 64);
-        const int hi = __shfl_xor((int)(uint32_t)((uint64_t)s2 >> 32), off, 64);
-        s2 += (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-    }
-    const int64_t gg = grown;
-    const int64_t nn = gg * s2 - ((int64_t)sx * sx + (int64_t)sy * sy + (int64_t)sz * sz);
-    int32_t ex, ey, ez;
-    if constexpr (WIDE) {
-        ex = (int32_t)(ta & 0xFFFFu) - 32768;
-        ey = (int32_t)(ta >> 16) - 32768;
-        ez = (int32_t)(tb >> 16) - 32768;
-    } else {
-        ex = (int32_t)((ta >> 8) & 0xFFu) - 128;
-        ey = (int32_t)((ta >> 16) & 0xFFu) - 128;
-        ez = (int32_t)(ta >> 24) - 128;
-    }
-    const double logw = alive ? lw : -__builtin_huge_val();
 
     if (valid && t == 0) {
-        if (a.log_w) a.log_w[c] = logw;
+        if (a.log_w) a.log_w[c] = res_lw;
         if (a.r_end) {
             CT *re = (CT *)a.r_end;
-            re[c] = (CT)ex;
-            re[a.n_chains + c] = (CT)ey;
-            re[2 * a.n_chains + c] = (CT)ez;
+            re[c] = (CT)res_ex;
+            re[a.n_chains + c] = (CT)res_ey;
+            re[2 * a.n_chains + c] = (CT)res_ez;
         }
-        if (a.r2) a.r2[c] = (double)((int64_t)ex * ex + (int64_t)ey * ey + (int64_t)ez * ez);
-        if (a.n2rg2) a.n2rg2[c] = nn;
-        if (a.rg2) a.rg2[c] = (double)nn / ((double)gg * (double)gg);
-        if (a.n_grown) a.n_grown[c] = (uint16_t)grown;
+        if (a.r2) a.r2[c] = (double)((int64_t)res_ex * res_ex + (int64_t)res_ey * res_ey + (int64_t)res_ez * res_ez);
+        if (a.n2rg2) a.n2rg2[c] = res_nn;
+        if (a.rg2) a.rg2[c] = (double)res_nn / ((double)res_grown * (double)res_grown);
+        if (a.n_grown) a.n_grown[c] = (uint16_t)res_grown;
     }
     if (rng_fail) atomicExch(a.status, 6);
-    const uint64_t bits = (alive && t == 0) ? (uint64_t)__double_as_longlong(lw) : 0ull;
+    const uint64_t bits = (res_alive && t == 0) ? (uint64_t)__double_as_longlong(res_lw) : 0ull;
     const uint64_t wmax = wave_max_u64(bits);
     if ((threadIdx.x & 63) == 0 && wmax != 0) atomicMax(a.log_w_max_bits, (unsigned long long)wmax);
 }

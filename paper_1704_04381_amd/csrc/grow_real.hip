@@ -124,209 +124,231 @@ __device__ __forceinline__ void grow_real_body(const GrowArgs &a, uint64_t bid)
     __syncthreads();
 
     double tx = 0.0, ty = 0.0, tz = 0.0;
-    bool alive = valid;
+    bool alive = false;
     int grown = 1;
     uint32_t n_mine = 0; // steps with m = t + 1 (lane t counts one value of m)
     bool rng_fail = false;
     Philox4 sel{0, 0, 0, 0};
+    // the attempt that ends the chain: the first complete one, or the last
+    // allowed one (one attempt without restarts); bead 0 stays at the origin
+    bool res_alive = false;
+    double res_lw = -__builtin_huge_val();
+    bool pending = valid;
 
-    for (int i = 1; i < N; ++i) {
-        // 1. Marsaglia direction of trial t: the first accepted attempt.
-        // Round 1: every lane tries attempt 0 of its own trial.  Round 2: the
-        // 64 lanes of the wave serve the trials that failed, lane l taking
-        // the failed trial of rank q = l mod nF at attempt 1 + l / nF; each
-        // failed trial then takes its first accepting helper in lane order,
-        // which is its smallest accepted attempt.  Values move through the
-        // cross-lane permute network (no LDS storage).  A trial whose helpers
-        // all rejected continues alone after its last helped attempt.
-        double v1 = 0.0, v2 = 0.0, s = 0.5;
-        const bool need = alive && has_trial;
-        bool acc = marsaglia_try(draw(a.seed, g, (uint32_t)i, (uint32_t)t, 0), v1, v2, s);
-        uint32_t att = 1;
-        const uint64_t F = __ballot(need && !acc);
-        if (F != 0) {
-            const uint32_t nF = (uint32_t)__popcll(F);
-            const bool failing = need && !acc;
-            const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(F >> 32),
-                                  __builtin_amdgcn_mbcnt_lo((uint32_t)F, 0u));
-            // lane q < nF learns the lane of the failed trial of rank q
-            const int owner_of_q = __builtin_amdgcn_ds_permute((int)((failing ? rank : 63u) * 4u), lane);
-            // l / nF and l mod nF (l < 64: the float quotient is never within
-            // rounding of an integer boundary)
-            const uint32_t jh = (uint32_t)(((float)lane + 0.5f) * __builtin_amdgcn_rcpf((float)nF));
-            const uint32_t q = (uint32_t)lane - jh * nF;
-            const int owner = __builtin_amdgcn_ds_bpermute((int)(q * 4u), owner_of_q);
-            const uint64_t og = a.chain_offset + bid * cpb +
-                                (uint64_t)(((threadIdx.x & ~63) + (owner & ~(G - 1))) / G);
-            double h1 = 0.0, h2 = 0.0, hs = 0.5;
-            const bool hok = marsaglia_try(draw(a.seed, og, (uint32_t)i, (uint32_t)(owner & (G - 1)), 1u + jh),
-                                           h1, h2, hs);
-            const uint64_t H = __ballot(hok);
-            // helpers of rank r are lanes r, r + nF, r + 2 nF, ...
-            uint64_t pattern = 0;
-            for (uint32_t l = 0; l < 64u; l += nF) pattern |= 1ull << l;
-            const uint64_t mine = failing ? (H & (pattern << rank)) : 0ull;
-            const int src = mine ? __builtin_ctzll(mine) : lane;
-            const auto pull = [&](double v) {
-                const int64_t bits = __double_as_longlong(v);
-                const int lo = __builtin_amdgcn_ds_bpermute(src * 4, (int)(uint32_t)bits);
-                const int hi = __builtin_amdgcn_ds_bpermute(src * 4, (int)(uint32_t)(bits >> 32));
-                return __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
-            };
-            const double n1 = pull(h1), n2 = pull(h2), ns = pull(hs);
-            if (failing) {
-                if (mine) {
-                    v1 = n1; v2 = n2; s = ns;
-                    acc = true;
-                } else {
-                    att = 1u + (64u - rank + nF - 1u) / nF;
+    for (uint32_t rd = 0; rd < a.max_rounds; ++rd) {
+        if (pending) {
+            tx = 0.0; ty = 0.0; tz = 0.0;
+            n_mine = 0;
+        }
+        alive = pending;
+        grown = 1;
+        const uint32_t hi = rd << 16; // attempt in the high half of the step word
+
+        for (int i = 1; i < N; ++i) {
+            // 1. Marsaglia direction of trial t: the first accepted attempt.
+            // Round 1: every lane tries attempt 0 of its own trial.  Round 2: the
+            // 64 lanes of the wave serve the trials that failed, lane l taking
+            // the failed trial of rank q = l mod nF at attempt 1 + l / nF; each
+            // failed trial then takes its first accepting helper in lane order,
+            // which is its smallest accepted attempt.  Values move through the
+            // cross-lane permute network (no LDS storage).  A trial whose helpers
+            // all rejected continues alone after its last helped attempt.
+            double v1 = 0.0, v2 = 0.0, s = 0.5;
+            const bool need = alive && has_trial;
+            bool acc = marsaglia_try(draw(a.seed, g, (uint32_t)i | hi, (uint32_t)t, 0), v1, v2, s);
+            uint32_t att = 1;
+            const uint64_t F = __ballot(need && !acc);
+            if (F != 0) {
+                const uint32_t nF = (uint32_t)__popcll(F);
+                const bool failing = need && !acc;
+                const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(F >> 32),
+                                      __builtin_amdgcn_mbcnt_lo((uint32_t)F, 0u));
+                // lane q < nF learns the lane of the failed trial of rank q
+                const int owner_of_q = __builtin_amdgcn_ds_permute((int)((failing ? rank : 63u) * 4u), lane);
+                // l / nF and l mod nF (l < 64: the float quotient is never within
+                // rounding of an integer boundary)
+                const uint32_t jh = (uint32_t)(((float)lane + 0.5f) * __builtin_amdgcn_rcpf((float)nF));
+                const uint32_t q = (uint32_t)lane - jh * nF;
+                const int owner = __builtin_amdgcn_ds_bpermute((int)(q * 4u), owner_of_q);
+                const uint64_t og = a.chain_offset + bid * cpb +
+                                    (uint64_t)(((threadIdx.x & ~63) + (owner & ~(G - 1))) / G);
+                double h1 = 0.0, h2 = 0.0, hs = 0.5;
+                const bool hok = marsaglia_try(draw(a.seed, og, (uint32_t)i | hi, (uint32_t)(owner & (G - 1)), 1u + jh),
+                                               h1, h2, hs);
+                const uint64_t H = __ballot(hok);
+                // helpers of rank r are lanes r, r + nF, r + 2 nF, ...
+                uint64_t pattern = 0;
+                for (uint32_t l = 0; l < 64u; l += nF) pattern |= 1ull << l;
+                const uint64_t mine = failing ? (H & (pattern << rank)) : 0ull;
+                const int src = mine ? __builtin_ctzll(mine) : lane;
+                const auto pull = [&](double v) {
+                    const int64_t bits = __double_as_longlong(v);
+                    const int lo = __builtin_amdgcn_ds_bpermute(src * 4, (int)(uint32_t)bits);
+                    const int hi = __builtin_amdgcn_ds_bpermute(src * 4, (int)(uint32_t)(bits >> 32));
+                    return __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+                };
+                const double n1 = pull(h1), n2 = pull(h2), ns = pull(hs);
+                if (failing) {
+                    if (mine) {
+                        v1 = n1; v2 = n2; s = ns;
+                        acc = true;
+                    } else {
+                        att = 1u + (64u - rank + nF - 1u) / nF;
+                    }
                 }
             }
-        }
-        // round 3 (rare): the remaining trials continue alone
-        bool done = !need || acc;
-        while (!done) {
-            if (marsaglia_try(draw(a.seed, g, (uint32_t)i, (uint32_t)t, att), v1, v2, s)) {
-                done = true;
-            } else if (++att == kMaxAttempt) {
-                rng_fail = true;
-                done = true;
+            // round 3 (rare): the remaining trials continue alone
+            bool done = !need || acc;
+            while (!done) {
+                if (marsaglia_try(draw(a.seed, g, (uint32_t)i | hi, (uint32_t)t, att), v1, v2, s)) {
+                    done = true;
+                } else if (++att == kMaxAttempt) {
+                    rng_fail = true;
+                    done = true;
+                }
             }
-        }
-        const double qf = 2.0 * sqrt(1.0 - s);
-        const double ex = v1 * qf, ey = v2 * qf, ez = 1.0 - 2.0 * s;
-        const double cx = tx + b * ex, cy = ty + b * ey, cz = tz + b * ez;
+            const double qf = 2.0 * sqrt(1.0 - s);
+            const double ex = v1 * qf, ey = v2 * qf, ez = 1.0 - 2.0 * s;
+            const double cx = tx + b * ex, cy = ty + b * ey, cz = tz + b * ez;
 
-        // 2-3. exact test of this lane's candidate: beads i-2 and i-3 (within
-        // 2b of the tip) directly, beads 0 .. i-4 after the culling pass
-        bool blocked = false; // bitwise accumulation keeps the tests branch-free
-        const auto test_bead = [&](int j) {
-            const int o = at(j);
-            const double dx = cx - X[o], dy = cy - Y[o], dz = cz - Z[o];
-            double d2 = dx * dx + dy * dy;
-            d2 = d2 + dz * dz;
-            blocked = blocked | (d2 < sigma2);
-        };
-        const auto is_near = [&](int j) {
-            const int o = at(j);
-            const double dx = X[o] - tx, dy = Y[o] - ty, dz = Z[o] - tz;
-            double d2 = dx * dx + dy * dy;
-            d2 = d2 + dz * dz;
-            return !(d2 >= cull2);
-        };
-        if (i >= 2) test_bead(i - 2);
-        if (i >= 3) test_bead(i - 3);
-        const int nb = __builtin_amdgcn_readfirstlane(i - 3);
-        for (int b0 = 0; b0 < nb; b0 += 2 * G) {
-            // two blocks of G beads per pass, lane t taking bead b0 + t and
-            // b0 + G + t; the offsets flagged by any chain of the wave are
-            // re-tested exactly by every chain (a culled bead cannot
-            // overlap, so testing it again changes nothing)
-            // (indices clamped so that both loads issue unconditionally)
-            const int j0 = b0 + t, j1 = b0 + G + t;
-            const bool d0 = is_near(j0 < nb ? j0 : nb - 1);
-            const bool d1 = is_near(j1 < nb ? j1 : nb - 1);
-            const bool n0 = alive & (j0 < nb) & d0;
-            const bool n1 = alive & (j1 < nb) & d1;
-            uint64_t u0 = fold_groups<G>(__ballot(n0));
-            uint64_t u1 = fold_groups<G>(__ballot(n1));
-            while (u0) {
-                const int q = __builtin_ctzll(u0);
-                u0 &= u0 - 1;
-                test_bead(b0 + q);
+            // 2-3. exact test of this lane's candidate: beads i-2 and i-3 (within
+            // 2b of the tip) directly, beads 0 .. i-4 after the culling pass
+            bool blocked = false; // bitwise accumulation keeps the tests branch-free
+            const auto test_bead = [&](int j) {
+                const int o = at(j);
+                const double dx = cx - X[o], dy = cy - Y[o], dz = cz - Z[o];
+                double d2 = dx * dx + dy * dy;
+                d2 = d2 + dz * dz;
+                blocked = blocked | (d2 < sigma2);
+            };
+            const auto is_near = [&](int j) {
+                const int o = at(j);
+                const double dx = X[o] - tx, dy = Y[o] - ty, dz = Z[o] - tz;
+                double d2 = dx * dx + dy * dy;
+                d2 = d2 + dz * dz;
+                return !(d2 >= cull2);
+            };
+            if (i >= 2) test_bead(i - 2);
+            if (i >= 3) test_bead(i - 3);
+            const int nb = __builtin_amdgcn_readfirstlane(i - 3);
+            for (int b0 = 0; b0 < nb; b0 += 2 * G) {
+                // two blocks of G beads per pass, lane t taking bead b0 + t and
+                // b0 + G + t; the offsets flagged by any chain of the wave are
+                // re-tested exactly by every chain (a culled bead cannot
+                // overlap, so testing it again changes nothing)
+                // (indices clamped so that both loads issue unconditionally)
+                const int j0 = b0 + t, j1 = b0 + G + t;
+                const bool d0 = is_near(j0 < nb ? j0 : nb - 1);
+                const bool d1 = is_near(j1 < nb ? j1 : nb - 1);
+                const bool n0 = alive & (j0 < nb) & d0;
+                const bool n1 = alive & (j1 < nb) & d1;
+                uint64_t u0 = fold_groups<G>(__ballot(n0));
+                uint64_t u1 = fold_groups<G>(__ballot(n1));
+                while (u0) {
+                    const int q = __builtin_ctzll(u0);
+                    u0 &= u0 - 1;
+                    test_bead(b0 + q);
+                }
+                while (u1) {
+                    const int q = __builtin_ctzll(u1);
+                    u1 &= u1 - 1;
+                    test_bead(b0 + G + q);
+                }
             }
-            while (u1) {
-                const int q = __builtin_ctzll(u1);
-                u1 &= u1 - 1;
-                test_bead(b0 + G + q);
+
+            const bool fr = alive & has_trial & !blocked;
+
+            // 4. free mask of the group and m
+            const uint64_t bal = __ballot(fr);
+            const uint64_t gm = (bal >> gbase) & gmask_bits;
+            const uint32_t m = (uint32_t)__popcll(gm);
+
+            // 5. uniform pick among the free trials (16-bit Lemire word)
+            if (i == 1 || (i & 7) == 0) sel = draw(a.seed, g, (uint32_t)(i >> 3) | hi, kSlotSelect, 0);
+            const uint32_t x = half_word(sel, (uint32_t)(i & 7));
+            const uint32_t p = x * m;
+            uint32_t r = p >> 16;
+            if (__builtin_expect(alive && (p & 0xFFFFu) < m, 0)) {
+                r = lemire_redraw16(a.seed, g, (uint32_t)i | hi, m, x);
+                if (r == kPickFailed) {
+                    rng_fail = true;
+                    r = 0;
+                }
             }
-        }
+            const uint64_t below = (t == 0) ? 0ull : (gm & ((1ull << t) - 1ull));
+            const bool chosen = fr && ((uint32_t)__popcll(below) == r);
+            const uint64_t cb = __ballot(chosen);
+            const uint64_t gcb = (cb >> gbase) & gmask_bits;
+            const int src = gbase + (gcb ? (__ffsll((long long)gcb) - 1) : 0);
+            const double nx = __shfl(cx, src, 64);
+            const double ny = __shfl(cy, src, 64);
+            const double nz = __shfl(cz, src, 64);
 
-        const bool fr = alive & has_trial & !blocked;
-
-        // 4. free mask of the group and m
-        const uint64_t bal = __ballot(fr);
-        const uint64_t gm = (bal >> gbase) & gmask_bits;
-        const uint32_t m = (uint32_t)__popcll(gm);
-
-        // 5. uniform pick among the free trials (16-bit Lemire word)
-        if (i == 1 || (i & 7) == 0) sel = draw(a.seed, g, (uint32_t)(i >> 3), kSlotSelect, 0);
-        const uint32_t x = half_word(sel, (uint32_t)(i & 7));
-        const uint32_t p = x * m;
-        uint32_t r = p >> 16;
-        if (__builtin_expect(alive && (p & 0xFFFFu) < m, 0)) {
-            r = lemire_redraw16(a.seed, g, (uint32_t)i, m, x);
-            if (r == kPickFailed) {
-                rng_fail = true;
-                r = 0;
+            if (alive && m == 0) {
+                alive = false;
+                grown = i;
             }
-        }
-        const uint64_t below = (t == 0) ? 0ull : (gm & ((1ull << t) - 1ull));
-        const bool chosen = fr && ((uint32_t)__popcll(below) == r);
-        const uint64_t cb = __ballot(chosen);
-        const uint64_t gcb = (cb >> gbase) & gmask_bits;
-        const int src = gbase + (gcb ? (__ffsll((long long)gcb) - 1) : 0);
-        const double nx = __shfl(cx, src, 64);
-        const double ny = __shfl(cy, src, 64);
-        const double nz = __shfl(cz, src, 64);
-
-        if (alive && m == 0) {
-            alive = false;
-            grown = i;
-        }
-        if (alive) {
-            if (chosen) {
-                const int o = at(i);
-                X[o] = nx; Y[o] = ny; Z[o] = nz;
+            if (alive) {
+                if (chosen) {
+                    const int o = at(i);
+                    X[o] = nx; Y[o] = ny; Z[o] = nz;
+                }
+                tx = nx; ty = ny; tz = nz;
+                n_mine += (m == (uint32_t)t + 1u) ? 1u : 0u;
             }
-            tx = nx; ty = ny; tz = nz;
-            n_mine += (m == (uint32_t)t + 1u) ? 1u : 0u;
+            wave_sync();
         }
-        wave_sync();
-    }
-    if (alive) grown = N;
+        if (alive) grown = N;
+        const bool ends = pending && (alive || rd + 1 >= a.max_rounds);
 
-    // log W = sum over m = 1..k, ascending, of n_m log m (Eq. 3 grouped by
-    // value); n_m is held by lane m - 1 of the group
-    double lw = 0.0;
-    for (int mm = 1; mm <= k; ++mm) {
-        const uint32_t nm = __shfl(n_mine, gbase + mm - 1, 64);
-        lw = lw + (double)nm * logm[mm];
-    }
-    if (!alive) lw = -__builtin_huge_val();
+        // log W = sum over m = 1..k, ascending, of n_m log m (Eq. 3 grouped by
+        // value); n_m is held by lane m - 1 of the group
+        double lw = 0.0;
+        for (int mm = 1; mm <= k; ++mm) {
+            const uint32_t nm = __shfl(n_mine, gbase + mm - 1, 64);
+            lw = lw + (double)nm * logm[mm];
+        }
+        if (!alive) lw = -__builtin_huge_val();
 
-    // observables, lane 0 of the group, in bead order
-    if (t == 0 && valid) {
-        double sx = 0.0, sy = 0.0, sz = 0.0;
-        for (int j = 0; j < grown; ++j) {
-            const int o = at(j);
-            sx = sx + X[o]; sy = sy + Y[o]; sz = sz + Z[o];
+        // observables, lane 0 of the group, in bead order
+        if (ends && t == 0 && valid) {
+            double sx = 0.0, sy = 0.0, sz = 0.0;
+            for (int j = 0; j < grown; ++j) {
+                const int o = at(j);
+                sx = sx + X[o]; sy = sy + Y[o]; sz = sz + Z[o];
+            }
+            const double gd = (double)grown;
+            const double cmx = sx / gd, cmy = sy / gd, cmz = sz / gd;
+            double acc = 0.0;
+            for (int j = 0; j < grown; ++j) {
+                const int o = at(j);
+                const double dx = X[o] - cmx, dy = Y[o] - cmy, dz = Z[o] - cmz;
+                double q = dx * dx + dy * dy;
+                q = q + dz * dz;
+                acc = acc + q;
+            }
+            const int oe = at(grown - 1);
+            const double ex = X[oe], ey = Y[oe], ez = Z[oe];
+            double r2 = ex * ex + ey * ey;
+            r2 = r2 + ez * ez;
+            if (a.log_w) a.log_w[c] = lw;
+            if (a.r_end) {
+                double *o = (double *)a.r_end;
+                o[c] = ex; o[a.n_chains + c] = ey; o[2 * a.n_chains + c] = ez;
+            }
+            if (a.r2) a.r2[c] = r2;
+            if (a.rg2) a.rg2[c] = acc / gd;
+            if (a.n_grown) a.n_grown[c] = (uint16_t)grown;
         }
-        const double gd = (double)grown;
-        const double cmx = sx / gd, cmy = sy / gd, cmz = sz / gd;
-        double acc = 0.0;
-        for (int j = 0; j < grown; ++j) {
-            const int o = at(j);
-            const double dx = X[o] - cmx, dy = Y[o] - cmy, dz = Z[o] - cmz;
-            double q = dx * dx + dy * dy;
-            q = q + dz * dz;
-            acc = acc + q;
+        if (ends) {
+            res_alive = alive;
+            res_lw = lw;
+            pending = false;
         }
-        const int oe = at(grown - 1);
-        const double ex = X[oe], ey = Y[oe], ez = Z[oe];
-        double r2 = ex * ex + ey * ey;
-        r2 = r2 + ez * ez;
-        if (a.log_w) a.log_w[c] = lw;
-        if (a.r_end) {
-            double *o = (double *)a.r_end;
-            o[c] = ex; o[a.n_chains + c] = ey; o[2 * a.n_chains + c] = ez;
-        }
-        if (a.r2) a.r2[c] = r2;
-        if (a.rg2) a.rg2[c] = acc / gd;
-        if (a.n_grown) a.n_grown[c] = (uint16_t)grown;
+        if (__ballot(pending) == 0) break;
     }
     if (rng_fail) atomicExch(a.status, 6);
-    const uint64_t bits = (alive && t == 0) ? (uint64_t)__double_as_longlong(lw) : 0ull;
+    const uint64_t bits = (res_alive && t == 0) ? (uint64_t)__double_as_longlong(res_lw) : 0ull;
     const uint64_t wmax = wave_max_u64(bits);
     if (lane == 0 && wmax != 0) atomicMax(a.log_w_max_bits, (unsigned long long)wmax);
 }

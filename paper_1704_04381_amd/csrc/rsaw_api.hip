@@ -193,7 +193,7 @@ rsaw_status validate(const rsaw_config *cfg)
     if (cfg->n_chains >= (1ull << 32)) return fail(RSAW_E_INVALID, "n_chains must be below 2^32");
     if (cfg->hist_bins < 0) return fail(RSAW_E_INVALID, "hist_bins must be >= 0");
     if (cfg->hist_bins > rsaw::kMaxBins) return fail(RSAW_E_UNSUPPORTED, "hist_bins above 256");
-    if (cfg->flags & ~RSAW_EXACT_W) return fail(RSAW_E_INVALID, "unknown flag bits");
+    if (cfg->flags & ~(RSAW_EXACT_W | RSAW_RESTART)) return fail(RSAW_E_INVALID, "unknown flag bits");
     if (cfg->geometry == RSAW_LATTICE_SC) {
         if (cfg->k_trials != 6) return fail(RSAW_E_INVALID, "lattice needs k_trials == 6");
         if (cfg->coord_type != RSAW_I16 && cfg->coord_type != RSAW_I32)
@@ -300,6 +300,7 @@ rsaw::GrowArgs grow_args(const rsaw_config *cfg, const rsaw_chain_out &o, const 
     a.sigma2 = cfg->bead_diameter * cfg->bead_diameter;
     const double bs = cfg->bond_length + cfg->bead_diameter;
     a.cull2 = bs * bs * (1.0 + 0x1p-30);
+    a.max_rounds = (cfg->flags & RSAW_RESTART) ? 65536u : 1u;
     a.log_w = o.log_w;
     a.w_exact = o.w_exact;
     a.r_end = o.r_end;

@@ -108,6 +108,7 @@ struct GrowArgs {
     double bond_length;
     double sigma2;
     double cull2; // (b + sigma)^2 (1 + 2^-30): beads at or beyond it cannot overlap
+    uint32_t max_rounds; // growth attempts per chain: 1, or 65536 when a dead end restarts
     // per-chain outputs (device, any may be null)
     double *log_w;
     uint64_t *w_exact;

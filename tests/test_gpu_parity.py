@@ -69,10 +69,10 @@ def _check_summary(s, ref, M, exact_ref=None):
         assert s["sum_w_n2rg2_exact"] == exact_ref["sum_w_n2rg2"]
 
 
-def _lattice_case(N, M, seed, coord="i32", exact_w=False, bins=0, offset=0):
+def _lattice_case(N, M, seed, coord="i32", exact_w=False, bins=0, offset=0, restart=False):
     out, s = _gpu("lattice", N, 6, M, seed, coord=coord, exact_w=exact_w, hist_bins=bins,
-                  chain_offset=offset)
-    ref = oracle.gen_lattice(seed, N, M, chain_offset=offset)
+                  chain_offset=offset, restart=restart)
+    ref = oracle.gen_lattice(seed, N, M, chain_offset=offset, restart=restart)
     np.testing.assert_array_equal(out["n_grown"].view(np.uint16), ref["n_grown"])
     np.testing.assert_array_equal(out["log_w"], ref["log_w"])
     np.testing.assert_array_equal(out["r_end"].astype(np.int32), ref["r_end"])
@@ -120,10 +120,10 @@ def test_lattice_dead_chains_bit_exact():
     assert (out["n_grown"].view(np.uint16) < 64).sum() > 10
 
 
-def _real_case(N, k, M, seed, b=1.0, sigma=1.0, bins=0, offset=0):
+def _real_case(N, k, M, seed, b=1.0, sigma=1.0, bins=0, offset=0, restart=False):
     out, s = _gpu("real", N, k, M, seed, bond_length=b, bead_diameter=sigma, hist_bins=bins,
-                  chain_offset=offset)
-    ref = oracle.gen_real(seed, N, k, M, b=b, sigma=sigma, chain_offset=offset)
+                  chain_offset=offset, restart=restart)
+    ref = oracle.gen_real(seed, N, k, M, b=b, sigma=sigma, chain_offset=offset, restart=restart)
     np.testing.assert_array_equal(out["n_grown"].view(np.uint16), ref["n_grown"])
     alive = np.isfinite(ref["log_w"])
     np.testing.assert_array_equal(np.isfinite(out["log_w"]), alive)
@@ -163,6 +163,20 @@ def test_real_parity(N, k, M, seed):
 def test_real_long_chains(N, k, M, seed, sigma):
     _, _, exact = _real_case(N, k, M, seed, sigma=sigma, bins=64)
     assert exact
+
+
+@pytest.mark.parametrize("N,M,seed,coord,exact", [(64, 20_000, 31, "i16", False), (28, 5_000, 32, "i32", True),
+                                                  (200, 500, 33, "i32", False), (2_049, 40, 34, "i16", False)])
+def test_lattice_restart_bit_exact(N, M, seed, coord, exact):
+    out, s = _lattice_case(N, M, seed, coord=coord, exact_w=exact, bins=64, restart=True)
+    assert s["n_alive"] == M
+
+
+@pytest.mark.parametrize("N,k,M,seed,sigma", [(64, 8, 2_000, 31, 1.0), (40, 4, 300, 32, 1.4),
+                                              (300, 8, 30, 33, 1.0)])
+def test_real_restart_bit_exact(N, k, M, seed, sigma):
+    out, s, exact = _real_case(N, k, M, seed, sigma=sigma, bins=32, restart=True)
+    assert exact and s["n_alive"] == M
 
 
 def test_real_ideal_chain_and_bond_length():
