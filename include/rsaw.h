@@ -31,7 +31,9 @@
  *     available from rsaw_last_error().
  *   - Thread safety: calls on different streams may run concurrently; the
  *     library keeps one internal workspace per (device, stream), so calls
- *     on the same stream are ordered by that stream.
+ *     on the same stream are ordered by that stream.  Calls on one stream
+ *     must come from one host thread at a time (they share that workspace
+ *     and its staging buffer).
  */
 #ifndef RSAW_H
 #define RSAW_H
@@ -158,7 +160,7 @@ typedef struct {
  * coord_type, lattice k != 6, real-space k outside 1..64, b <= 0,
  * sigma < 0, hist_bins < 0, n_chains >= 2^32 (split larger ensembles
  * over calls with chain_offset);
- * RSAW_E_UNSUPPORTED for lattice N > 16384 or real-space N > 6144 (no kernel in
+ * RSAW_E_UNSUPPORTED for lattice or real-space N > 16384 (no kernel in
  * this build); RSAW_E_OVERFLOW for RSAW_EXACT_W with N > 28;
  * RSAW_E_NOMEM / RSAW_E_DEVICE for runtime failures.  A Marsaglia or Lemire
  * rejection loop that reaches its cap (probability below 2^-100000) sets

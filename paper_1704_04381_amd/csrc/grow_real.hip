@@ -87,8 +87,25 @@ __device__ __forceinline__ void wave_sync()
 // uses an odd row and no swizzle instead.
 __host__ __device__ inline int plane_row(int cpb, int G) { return G == 64 ? (cpb | 1) : cpb; }
 
-template <int G>
-__device__ __forceinline__ void grow_real_body(const GrowArgs &a, uint64_t bid)
+// Orders the plane accesses of the lanes of one wave: LDS planes need the
+// wavefront scope, planes in global memory (one wave per block) the
+// workgroup scope, which waits for the stores before later loads.
+template <bool HBM>
+__device__ __forceinline__ void plane_sync()
+{
+    if constexpr (HBM) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    } else {
+        wave_sync();
+    }
+}
+
+// HBM: the planes of chain `bid` live in global memory, in the region of
+// resident block `slot` (one 64-lane chain per block, row 1, no swizzle).
+template <int G, bool HBM>
+__device__ __forceinline__ void grow_real_body(const GrowArgs &a, uint64_t bid, uint32_t slot = 0)
 {
     extern __shared__ double lds[]; // X, Y, Z planes of [N][row], swizzled
     __shared__ double logm[65];
@@ -99,9 +116,10 @@ __device__ __forceinline__ void grow_real_body(const GrowArgs &a, uint64_t bid)
     const int swz_mul = G == 64 ? 0 : 32 / G;
     const int swz_mask = cpb - 1;
     const int N = a.n_monomers;
-    double *X = lds;
-    double *Y = lds + (size_t)N * row;
-    double *Z = lds + (size_t)2 * N * row;
+    double *planes = HBM ? a.bead_slots + (size_t)slot * 3 * N : lds;
+    double *X = planes;
+    double *Y = planes + (size_t)N * row;
+    double *Z = planes + (size_t)2 * N * row;
     const int t = threadIdx.x & (G - 1);
     const int chb = threadIdx.x / G;
     const int lane = threadIdx.x & 63;
@@ -121,6 +139,7 @@ __device__ __forceinline__ void grow_real_body(const GrowArgs &a, uint64_t bid)
     if (t == 0) {
         X[at(0)] = 0.0; Y[at(0)] = 0.0; Z[at(0)] = 0.0;
     }
+    if constexpr (HBM) plane_sync<true>();
     __syncthreads();
 
     double tx = 0.0, ty = 0.0, tz = 0.0;
@@ -296,7 +315,7 @@ __device__ __forceinline__ void grow_real_body(const GrowArgs &a, uint64_t bid)
                 tx = nx; ty = ny; tz = nz;
                 n_mine += (m == (uint32_t)t + 1u) ? 1u : 0u;
             }
-            wave_sync();
+            plane_sync<HBM>();
         }
         if (alive) grown = N;
         const bool ends = pending && (alive || rd + 1 >= a.max_rounds);
@@ -356,7 +375,7 @@ __device__ __forceinline__ void grow_real_body(const GrowArgs &a, uint64_t bid)
 template <int G>
 __global__ __launch_bounds__(256) void grow_real_tp(GrowArgs a)
 {
-    grow_real_body<G>(a, blockIdx.x);
+    grow_real_body<G, false>(a, blockIdx.x);
 }
 
 // Batched launch: block b serves the ensemble whose block range holds b.
@@ -364,12 +383,28 @@ template <int G>
 __global__ __launch_bounds__(256) void grow_real_tp_batch(const GrowEntry *tab, const uint64_t *block0, int n)
 {
     const int e = find_segment(block0, n, blockIdx.x);
-    grow_real_body<G>(tab[e].a, blockIdx.x - block0[e]);
+    grow_real_body<G, false>(tab[e].a, blockIdx.x - block0[e]);
 }
 
-// Largest bead count of the LDS-resident kernel: one chain per wave, three
-// binary64 planes of N beads within a CU's 160 KiB.
-int real_max_monomers() { return 6144; }
+// Chains beyond the LDS limit: a persistent grid of one-wave blocks, block s
+// growing chains s, s + grid, s + 2 grid, ... in its own HBM plane region.
+__global__ __launch_bounds__(64) void grow_real_hbm(GrowArgs a)
+{
+    for (uint64_t bid = blockIdx.x; bid < a.n_chains; bid += gridDim.x)
+        grow_real_body<64, true>(a, bid, blockIdx.x);
+}
+
+// Largest bead count of the LDS-resident kernel (one chain per wave, three
+// binary64 planes of N beads within a CU's 160 KiB) and of the HBM one.
+constexpr int kRealLdsMax = 6144;
+int real_max_monomers() { return 16384; }
+
+// Resident blocks (and HBM plane regions) of the HBM kernel for M chains.
+uint32_t real_hbm_slots(int n_monomers, uint64_t n_chains)
+{
+    if (n_monomers <= kRealLdsMax) return 0;
+    return (uint32_t)(n_chains < 2048 ? n_chains : 2048);
+}
 
 // Lanes per chain: at least the next power of two >= k (one trial per
 // lane), and enough that the chains whose planes fit in a CU's LDS still
@@ -379,6 +414,19 @@ int real_max_monomers() { return 6144; }
 hipError_t real_variant(const GrowArgs &a, GrowVariant *v)
 {
     const int N = a.n_monomers;
+    if (N > kRealLdsMax) {
+        // HBM planes, launched on its own (p1 = 1)
+        v->family = 2;
+        v->p0 = 64;
+        v->p1 = 1;
+        v->p2 = 0;
+        v->threads = 64;
+        v->cpb = 1;
+        v->shmem = 0;
+        v->H = 0;
+        v->S = 0;
+        return hipSuccess;
+    }
     int need = a.k_trials;
     const int occ = (3 * N + 39) / 40; // ceil(0.075 N)
     if (occ > need) need = occ;
@@ -434,6 +482,11 @@ hipError_t launch_grow_real(const GrowArgs &a, hipStream_t s)
     GrowVariant v;
     hipError_t e = real_variant(a, &v);
     if (e != hipSuccess) return e;
+    if (v.p1) {
+        if (!a.bead_slots || a.n_slots == 0) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(grow_real_hbm, dim3(a.n_slots), dim3(64), 0, s, a);
+        return hipGetLastError();
+    }
     const uint64_t blocks = (a.n_chains + v.cpb - 1) / v.cpb;
     return dispatch_real(a, v, nullptr, nullptr, 0, blocks, v.shmem, s);
 }

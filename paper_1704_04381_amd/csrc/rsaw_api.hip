@@ -23,6 +23,7 @@ namespace rsaw {
 hipError_t launch_grow_lattice(const GrowArgs &a, bool exact, bool i16, hipStream_t s);
 hipError_t launch_grow_real(const GrowArgs &a, hipStream_t s);
 int real_max_monomers();
+uint32_t real_hbm_slots(int n_monomers, uint64_t n_chains);
 int lattice_lds_max_monomers();
 void lattice_reg_variant(const GrowArgs &a, bool exact, bool i16, GrowVariant *v);
 hipError_t lattice_lds_variant(const GrowArgs &a, bool i16, GrowVariant *v);
@@ -212,7 +213,7 @@ rsaw_status validate(const rsaw_config *cfg)
             return fail(RSAW_E_INVALID, "bead_diameter must be finite and >= 0");
         if (cfg->flags & RSAW_EXACT_W) return fail(RSAW_E_INVALID, "RSAW_EXACT_W is lattice-only");
         if (N > rsaw::real_max_monomers())
-            return fail(RSAW_E_UNSUPPORTED, "real-space kernel supports n_monomers <= 6144");
+            return fail(RSAW_E_UNSUPPORTED, "real-space kernels support n_monomers <= 16384");
     } else {
         return fail(RSAW_E_INVALID, "unknown geometry");
     }
@@ -229,6 +230,8 @@ struct EnsLayout {
     uint64_t chunk;    // chains per reduce block
     size_t off_lmax, off_status, off_summary, off_part, off_hacc;
     size_t off_lw, off_r2, off_rg2, off_ng, off_wx, off_nn;
+    size_t off_slots;  // HBM bead planes of the long hard-sphere kernel
+    uint32_t n_slots;
     bool need_lw, need_r2, need_rg2, need_ng, need_wx, need_nn;
 };
 
@@ -268,6 +271,9 @@ void layout_ensemble(const rsaw_config *cfg, const rsaw_chain_out &o, bool reduc
     L->off_ng = x; if (L->need_ng) x = align256(x + M * sizeof(uint16_t));
     L->off_wx = x; if (L->need_wx) x = align256(x + M * sizeof(uint64_t));
     L->off_nn = x; if (L->need_nn) x = align256(x + M * sizeof(int64_t));
+    L->n_slots = L->lattice ? 0u : rsaw::real_hbm_slots(cfg->n_monomers, M);
+    L->off_slots = x;
+    x = align256(x + (size_t)L->n_slots * 3 * (size_t)cfg->n_monomers * sizeof(double));
     *off = x;
 }
 
@@ -301,6 +307,8 @@ rsaw::GrowArgs grow_args(const rsaw_config *cfg, const rsaw_chain_out &o, const 
     const double bs = cfg->bond_length + cfg->bead_diameter;
     a.cull2 = bs * bs * (1.0 + 0x1p-30);
     a.max_rounds = (cfg->flags & RSAW_RESTART) ? 65536u : 1u;
+    a.bead_slots = L.n_slots ? (double *)(ws + L.off_slots) : nullptr;
+    a.n_slots = L.n_slots;
     a.log_w = o.log_w;
     a.w_exact = o.w_exact;
     a.r_end = o.r_end;
@@ -530,7 +538,11 @@ rsaw_status batch_impl(const rsaw_config *cfgs, const rsaw_chain_out *outs, int3
         bool timed = false;
         st = timing_start(s, &tp, &timed);
         if (st != RSAW_OK) return st;
-        if (v.family == 0)
+        if (v.family == 2 && v.p1) {
+            // HBM planes: each ensemble runs its own persistent grid
+            for (int32_t q = G.first; q < G.last && e == hipSuccess; ++q)
+                e = rsaw::launch_grow_real(gtab[q].a, s);
+        } else if (v.family == 0)
             e = rsaw::launch_lattice_reg_batch(v, d_gtab + G.first, d_gb0 + G.first, cnt, G.blocks, s);
         else if (v.family == 1)
             e = rsaw::launch_lattice_lds_batch(v, d_gtab + G.first, d_gb0 + G.first, cnt, G.blocks, G.shmem, s);

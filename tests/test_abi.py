@@ -48,7 +48,7 @@ BAD = [
     (dict(geometry="real", N=16, k=8, bead_diameter=-1.0), 1),
     (dict(geometry="real", N=16, k=8, bond_length=float("nan")), 1),
     (dict(geometry="real", N=16, k=8, exact_w=True), 1),
-    (dict(geometry="real", N=6145, k=8), 2),
+    (dict(geometry="real", N=16385, k=8), 2),
     (dict(geometry=7, N=16, k=6), 1),
     (dict(geometry="lattice", N=16, k=6, hist_bins=-1), 1),
     (dict(geometry="lattice", N=16, k=6, hist_bins=300), 2),

@@ -159,7 +159,9 @@ def test_real_parity(N, k, M, seed):
     # one wave per chain: 256-thread blocks up to N = 682, one-wave blocks
     # (LDS planes beyond 64 KiB) up to the largest N
     (300, 8, 64, 41, 1.0), (700, 8, 24, 42, 1.0), (700, 16, 12, 43, 0.8),
-    (2_048, 8, 6, 44, 0.5), (6_144, 8, 3, 45, 0.5)])
+    (2_048, 8, 6, 44, 0.5), (6_144, 8, 3, 45, 0.5),
+    # HBM-resident planes beyond the LDS limit (persistent grid)
+    (6_145, 8, 3, 46, 0.5), (10_000, 8, 3, 47, 0.4), (16_384, 16, 2, 48, 0.4)])
 def test_real_long_chains(N, k, M, seed, sigma):
     _, _, exact = _real_case(N, k, M, seed, sigma=sigma, bins=64)
     assert exact
