@@ -394,9 +394,12 @@ __global__ __launch_bounds__(64) void grow_real_hbm(GrowArgs a)
         grow_real_body<64, true>(a, bid, blockIdx.x);
 }
 
-// Largest bead count of the LDS-resident kernel (one chain per wave, three
-// binary64 planes of N beads within a CU's 160 KiB) and of the HBM one.
-constexpr int kRealLdsMax = 6144;
+// Largest bead count of the LDS-resident kernel, and of the HBM one.  LDS
+// planes fit up to N = 6826, but beyond N ~ 1500 they leave fewer than 4
+// waves per CU, and the HBM planes (8 waves per CU, cached in L2) are faster:
+// measured on MI355X, k = 8, per launch: N = 1024 LDS 15.7 ms / HBM 20.3 ms,
+// N = 2048 30.8 / 28.4, N = 4096 121.7 / 53.2, N = 6144 126.2 / 78.0.
+constexpr int kRealLdsMax = 1536;
 int real_max_monomers() { return 16384; }
 
 // Resident blocks (and HBM plane regions) of the HBM kernel for M chains.
