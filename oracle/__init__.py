@@ -136,21 +136,23 @@ def overlaps(c, r, sigma2):
 
 
 RESTART = 2  # flag: a dead end restarts the chain with the next round of random numbers
+Z26 = 4      # flag: lattice with the 26 neighbours of the tip as candidates
 
 
-def lattice_chain(seed, chain, N, restart=False):
+def lattice_chain(seed, chain, N, restart=False, z26=False):
     """One lattice chain with its coordinates and the m_i sequence (of the
     final growth attempt); ``rounds`` counts the attempts."""
     lib = _load()
     xyz = np.zeros((N, 3), dtype=np.int32)
     mseq = np.zeros(N, dtype=np.int32)
     lw = np.zeros(1); we = np.zeros(1, np.uint64); ok = np.zeros(1, np.int32)
+    flags = (RESTART if restart else 0) | (Z26 if z26 else 0)
     g = np.zeros(1, np.int32); e = np.zeros(3, np.int32)
     r2 = np.zeros(1, np.int64); nn = np.zeros(1, np.int64); rg = np.zeros(1)
     rounds = np.zeros(1, np.int32)
     _check(lib.oro_lattice_chain(seed, chain, N, _p(xyz), _p(mseq), _p(lw), _p(we),
                                  _p(ok), _p(g), _p(e), _p(r2), _p(nn), _p(rg),
-                                 RESTART if restart else 0, _p(rounds)),
+                                 flags, _p(rounds)),
            "lattice_chain")
     n = int(g[0])
     return dict(xyz=xyz[:n], m=mseq, log_w=float(lw[0]), w_exact=int(we[0]),
@@ -175,7 +177,7 @@ def real_chain(seed, chain, N, k, b=1.0, sigma=1.0, restart=False):
                 r2=float(r2[0]), rg2=float(rg[0]), rounds=int(rounds[0]))
 
 
-def gen_lattice(seed, N, n_chains, chain_offset=0, restart=False):
+def gen_lattice(seed, N, n_chains, chain_offset=0, restart=False, z26=False):
     """Per-chain lattice outputs for chains chain_offset .. +n_chains-1."""
     lib = _load()
     n = int(n_chains)
@@ -186,7 +188,8 @@ def gen_lattice(seed, N, n_chains, chain_offset=0, restart=False):
     _check(lib.oro_gen_lattice(seed, chain_offset, n, N, _p(out["log_w"]),
                                _p(out["w_exact"]), _p(out["w_exact_ok"]),
                                _p(out["r_end"]), _p(out["r2"]), _p(out["n2rg2"]),
-                               _p(out["rg2"]), _p(out["n_grown"]), RESTART if restart else 0),
+                               _p(out["rg2"]), _p(out["n_grown"]),
+                               (RESTART if restart else 0) | (Z26 if z26 else 0)),
            "gen_lattice")
     return out
 

@@ -85,6 +85,7 @@ static void draw_block(uint64_t seed, uint64_t chain, uint32_t c2,
 #define SLOT_REDRAW 0xFFFEu   /* Lemire redraw half-words for step i                */
 #define MAX_ATTEMPT 65536u
 #define ORO_RESTART 2        /* flag: a dead end restarts the chain (Sec. 3.3.2)  */
+#define ORO_Z26 4            /* flag: the 26 neighbours of the tip are candidates */
 #define MAX_ROUNDS 65536u    /* growth attempts of a chain with ORO_RESTART       */
 
 /* 16-bit half h (0..7) of a Philox block: word h / 2, low half for even h. */
@@ -166,6 +167,24 @@ static const int32_t LATTICE_DIR[6][3] = {
     {0, 0, -1}, {0, -1, 0}, {-1, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}
 };
 
+/* The 26-neighbour variant (the "z = 26 possible lattice space" of Sec.
+ * 3.3.2): every displacement in {-1, 0, 1}^3 but zero, in the order of the
+ * code (dx + 1) + 3 (dy + 1) + 9 (dz + 1).  Its six face neighbours come in
+ * the same relative order as LATTICE_DIR. */
+static int32_t DIR26[26][3];
+
+static void init_dir26(void)
+{
+    int q = 0;
+    for (int c = 0; c < 27; ++c) {
+        if (c == 13) continue;
+        DIR26[q][0] = c % 3 - 1;
+        DIR26[q][1] = (c / 3) % 3 - 1;
+        DIR26[q][2] = c / 9 - 1;
+        ++q;
+    }
+}
+
 /*
  * Grow one lattice chain of N monomers for RNG chain index `chain`.
  * Outputs (each pointer may be NULL):
@@ -189,7 +208,10 @@ int oro_lattice_chain(uint64_t seed, uint64_t chain, int32_t N,
     if (N < 1) return ORO_E_INVALID;
     int32_t *pos = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)N);
     if (!pos) return ORO_E_NOMEM;
-    int64_t n_of_m[7];
+    int64_t n_of_m[27];
+    const int nd = (flags & ORO_Z26) ? 26 : 6;
+    if (nd == 26) init_dir26();
+    const int32_t (*dir)[3] = (nd == 26) ? (const int32_t (*)[3])DIR26 : LATTICE_DIR;
     uint64_t w;
     int w_ok;
     int32_t g;
@@ -201,7 +223,7 @@ int oro_lattice_chain(uint64_t seed, uint64_t chain, int32_t N,
      * again from the origin with the next round of random numbers. */
     for (;;) {
     pos[0] = 0; pos[1] = 0; pos[2] = 0;
-    for (int q = 0; q < 7; ++q) n_of_m[q] = 0; /* steps with m_i = m */
+    for (int q = 0; q < 27; ++q) n_of_m[q] = 0; /* steps with m_i = m */
     w = 1;
     w_ok = 1;
     g = 1;
@@ -210,12 +232,12 @@ int oro_lattice_chain(uint64_t seed, uint64_t chain, int32_t N,
 
     for (int32_t i = 1; i < N; ++i) {
         const int32_t *tip = &pos[3 * (i - 1)];
-        int free_[6];
+        int free_[26];
         uint32_t m = 0;
-        for (int d = 0; d < 6; ++d) {
-            int32_t cx = tip[0] + LATTICE_DIR[d][0];
-            int32_t cy = tip[1] + LATTICE_DIR[d][1];
-            int32_t cz = tip[2] + LATTICE_DIR[d][2];
+        for (int d = 0; d < nd; ++d) {
+            int32_t cx = tip[0] + dir[d][0];
+            int32_t cy = tip[1] + dir[d][1];
+            int32_t cz = tip[2] + dir[d][2];
             free_[d] = 1;
             for (int32_t j = 0; j < i; ++j) {
                 if (pos[3 * j] == cx && pos[3 * j + 1] == cy && pos[3 * j + 2] == cz)
@@ -233,15 +255,15 @@ int oro_lattice_chain(uint64_t seed, uint64_t chain, int32_t N,
         if (status != ORO_OK) break;
         int chosen = -1;
         uint32_t seen = 0;
-        for (int d = 0; d < 6; ++d) {
+        for (int d = 0; d < nd; ++d) {
             if (free_[d]) {
                 if (seen == pick) { chosen = d; break; }
                 ++seen;
             }
         }
-        pos[3 * i] = tip[0] + LATTICE_DIR[chosen][0];
-        pos[3 * i + 1] = tip[1] + LATTICE_DIR[chosen][1];
-        pos[3 * i + 2] = tip[2] + LATTICE_DIR[chosen][2];
+        pos[3 * i] = tip[0] + dir[chosen][0];
+        pos[3 * i + 1] = tip[1] + dir[chosen][1];
+        pos[3 * i + 2] = tip[2] + dir[chosen][2];
         g = i + 1;
         n_of_m[m] += 1;
         if (w_ok && w > UINT64_MAX / m) w_ok = 0;
@@ -256,7 +278,7 @@ int oro_lattice_chain(uint64_t seed, uint64_t chain, int32_t N,
     }
     if (rounds) *rounds = (int32_t)round + 1;
 
-    double lw = log_weight(n_of_m, 6);
+    double lw = log_weight(n_of_m, nd);
 
     /* Observables of the placed monomers 0 .. g-1. */
     int64_t sx = 0, sy = 0, sz = 0, s2 = 0;
