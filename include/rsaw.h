@@ -49,7 +49,7 @@ typedef enum {
     RSAW_OK = 0,
     RSAW_E_INVALID = 1,     /* bad argument (see rsaw_last_error)                 */
     RSAW_E_UNSUPPORTED = 2, /* valid request this build has no kernel for         */
-    RSAW_E_OVERFLOW = 3,    /* exact 64-bit weight requested for N > 28           */
+    RSAW_E_OVERFLOW = 3,    /* exact 64-bit weight requested beyond its N limit   */
     RSAW_E_NOMEM = 4,       /* device allocation of the workspace failed          */
     RSAW_E_DEVICE = 5,      /* a HIP runtime call failed                          */
     RSAW_E_RNG = 6          /* a rejection loop reached its 65536-attempt cap     */
@@ -58,6 +58,10 @@ typedef enum {
 /* geometry */
 #define RSAW_LATTICE_SC 0 /* simple cubic lattice, k = 6 (Sec. 3.3.2)          */
 #define RSAW_REAL_HS 1    /* hard spheres in continuous space (Sec. 3.3.3)    */
+/* 26-neighbour lattice (the z = 26 lattice space of Sec. 3.3.2), k = 26: the
+ * candidates of a step are the 26 sites within Chebyshev distance 1 of the
+ * tip, in the order of the code (dx + 1) + 3 (dy + 1) + 9 (dz + 1). */
+#define RSAW_LATTICE_26 2
 
 /* element type of the r_end output planes */
 #define RSAW_I16 0 /* lattice only */
@@ -65,7 +69,7 @@ typedef enum {
 #define RSAW_F64 2 /* real space only */
 
 /* flags */
-#define RSAW_EXACT_W 1u /* lattice: also keep W exactly as uint64 (needs N <= 28) */
+#define RSAW_EXACT_W 1u /* lattice: also keep W exactly as uint64 (N <= 28; N <= 14 for k = 26) */
 /*
  * RSAW_RESTART: a dead end discards the chain and grows it again from the
  * origin (the rule of Sec. 3.3.2 and 3.3.3), up to 65536 attempts; attempt
@@ -78,9 +82,9 @@ typedef enum {
 #define RSAW_RESTART 2u
 
 typedef struct {
-    int32_t geometry;      /* RSAW_LATTICE_SC or RSAW_REAL_HS                        */
+    int32_t geometry;      /* RSAW_LATTICE_SC, RSAW_REAL_HS or RSAW_LATTICE_26        */
     int32_t n_monomers;    /* N >= 1 monomers per chain (N - 1 growth steps)         */
-    int32_t k_trials;      /* candidates per step: 6 on the lattice, 1..64 real space */
+    int32_t k_trials;      /* candidates per step: 6 or 26 (lattices), 1..64 (real)   */
     int32_t coord_type;    /* RSAW_I16 / RSAW_I32 (lattice) or RSAW_F64 (real space)  */
     uint64_t n_chains;     /* M >= 0 chains                                          */
     uint64_t seed;         /* Philox key                                             */
@@ -151,17 +155,21 @@ typedef struct {
  *   d_hist_w   device array of cfg->hist_bins doubles (W-weighted histogram
  *              of R^2, w as in the summary), or NULL.
  *   d_hist_n   device array of cfg->hist_bins uint64 (live-chain counts), or
- *              NULL.  Bin of a chain: floor((R^2 B) / ((N-1)^2 + 1)).
+ *              NULL.  Bin of a chain: floor((R^2 B) / ((N-1)^2 + 1)),
+ *              clamped to B - 1 (the last bin also holds the R^2 above
+ *              (N-1)^2 that diagonal steps or b > 1 can reach).
  *   stream     hipStream_t or NULL.
  *
  * Asynchronous: returns after enqueueing.  The results are deterministic:
  * the same config gives bit-identical outputs run to run.
  * Errors: RSAW_E_INVALID for N < 1, N > 65535, unknown geometry or
- * coord_type, lattice k != 6, real-space k outside 1..64, b <= 0,
+ * coord_type, lattice k != 6 (26 for RSAW_LATTICE_26), real-space k outside
+ * 1..64, b <= 0,
  * sigma < 0, hist_bins < 0, n_chains >= 2^32 (split larger ensembles
  * over calls with chain_offset);
- * RSAW_E_UNSUPPORTED for lattice or real-space N > 16384 (no kernel in
- * this build); RSAW_E_OVERFLOW for RSAW_EXACT_W with N > 28;
+ * RSAW_E_UNSUPPORTED for N > 16384 in any geometry (no kernel in this
+ * build); RSAW_E_OVERFLOW for RSAW_EXACT_W with N > 28 (N > 14 on the
+ * 26-neighbour lattice);
  * RSAW_E_NOMEM / RSAW_E_DEVICE for runtime failures.  A Marsaglia or Lemire
  * rejection loop that reaches its cap (probability below 2^-100000) sets
  * d_summary->status = RSAW_E_RNG.

@@ -20,6 +20,8 @@ LIB_PATH = os.path.join(_PKG, "librsaw.so")
 
 RSAW_LATTICE_SC = 0
 RSAW_REAL_HS = 1
+RSAW_LATTICE_26 = 2
+GEOMETRIES = {"lattice": RSAW_LATTICE_SC, "real": RSAW_REAL_HS, "lattice26": RSAW_LATTICE_26}
 RSAW_I16, RSAW_I32, RSAW_F64 = 0, 1, 2
 RSAW_EXACT_W = 1
 RSAW_RESTART = 2
@@ -131,8 +133,7 @@ def _check(status):
 
 def make_config(geometry, N, k, n_chains, seed, *, coord=None, chain_offset=0,
                 bond_length=1.0, bead_diameter=1.0, hist_bins=0, exact_w=False, restart=False):
-    geo = {"lattice": RSAW_LATTICE_SC, "real": RSAW_REAL_HS}[geometry] \
-        if isinstance(geometry, str) else int(geometry)
+    geo = GEOMETRIES[geometry] if isinstance(geometry, str) else int(geometry)
     if coord is None:
         coord = "f64" if geo == RSAW_REAL_HS else "i32"
     ct = {"i16": RSAW_I16, "i32": RSAW_I32, "f64": RSAW_F64}[coord]
@@ -172,7 +173,7 @@ def _alloc_outputs(cfg: rsaw_config, dev, per_chain: bool, hist_bins: int):
     import torch
 
     M = int(cfg.n_chains)
-    lattice = cfg.geometry == RSAW_LATTICE_SC
+    lattice = cfg.geometry != RSAW_REAL_HS
     out = {}
     o = rsaw_chain_out()
     if per_chain:

@@ -15,7 +15,8 @@ REPO = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(REPO, "include")
 LIB = os.path.join(PKG, "librsaw.so")
-SOURCES = ["rsaw_api.hip", "rsaw_server.hip", "grow_lattice.hip", "grow_lattice_lds.hip", "grow_real.hip",
+SOURCES = ["rsaw_api.hip", "rsaw_server.hip", "grow_lattice.hip", "grow_lattice_lds.hip", "grow_lattice26.hip",
+           "grow_real.hip",
            "reduce.hip"]
 ARCH = "gfx950"
 

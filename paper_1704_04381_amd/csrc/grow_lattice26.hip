@@ -1,0 +1,339 @@
+// 26-neighbour lattice variant (the "z = 26 possible lattice space" of Sec.
+// 3.3.2): the candidates of a step are all 26 sites within Chebyshev
+// distance 1 of the tip, numbered by the code (dx + 1) + 3 (dy + 1) +
+// 9 (dz + 1) (13, the tip itself, excluded); the growth rule and weight are
+// those of Algorithm 1 and Eq. 3 with m_i <= 26.
+//
+// G lanes per chain (32, or 64 for long chains), the history in LDS as two
+// words per monomer, A = (x + 2^15) | (y + 2^15) << 16 and B = z + 2^15,
+// in two planes of H words (monomer order; no bipartite pruning on this
+// lattice: a diagonal step keeps the parity).  Entries not yet placed hold
+// A = 0 (x = y = -2^15, far from every tip) and B = 2^15.  Pair test of monomer j against tip t:
+//   (dx, dy) as packed 16-bit differences of the A words, dz = B_j - B_t
+//   q  = dx^2 + dy^2 + dz^2          (dot2 onto a 24-bit product)
+//   s  = |dx| + |dy| + |dz|          (two chained sad_u16 operations)
+//   the site is a candidate iff max(|dx|, |dy|, |dz|) <= 1, i.e. iff q = s
+//   (d^2 = |d| for |d| <= 1, d^2 >= |d| + 2 otherwise), so
+//   bit = sat((s + 1) - q) and code = dx + 3 dy + 9 dz + 13 (dot2 onto a
+//   24-bit multiply-add);  occ |= bit << code
+// ten operations per pair.  The G partial masks are OR-reduced across
+// the group; every lane then picks the same r-th free code (Lemire on the
+// same 16-bit words as the six-neighbour lattice); lane m - 1 counts the
+// steps with m free candidates for log W.
+#include "rsaw_device.hpp"
+
+namespace rsaw {
+
+__device__ __forceinline__ void z26_wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int G>
+__device__ __forceinline__ uint32_t z26_group_or(uint32_t v)
+{
+    v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
+    v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
+    v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);
+    v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false);
+    {
+        const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        v = p[0] | p[1];
+    }
+    if constexpr (G >= 64) {
+        const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        v = p[0] | p[1];
+    }
+    return v;
+}
+
+typedef short short2_t __attribute__((ext_vector_type(2)));
+
+constexpr uint32_t kZ26OriginA = 0x80008000u; // x = y = 0
+constexpr uint32_t kZ26OriginB = 0x00008000u; // z = 0 (also the B sentinel)
+constexpr uint32_t kZ26Codes = 0x7FFFFFFu & ~(1u << 13);
+
+__device__ __forceinline__ uint32_t z26_bits(uint32_t wa, uint32_t wb, uint32_t ta, uint32_t tb)
+{
+    // (dx, dy) as 16-bit wrapping differences: exact for placed monomers
+    // (|d| < 2^15), at least 2^14 + 1 in |dx| against the zero A sentinel;
+    // dz exact (both B words are below 2^16, the sentinel's z is 0).  Hence
+    // q < 2^32 without wrap, and q < s + 1 only for true neighbours.
+    const short2_t dA = __builtin_bit_cast(short2_t, wa) - __builtin_bit_cast(short2_t, ta);
+    const int dz = (int)(wb - tb);
+    const short2_t w13 = {1, 3};
+    const uint32_t q = (uint32_t)__builtin_amdgcn_sdot2(dA, dA, __mul24(dz, dz), false);
+    const uint32_t s1 = __builtin_amdgcn_sad_u16(wa, ta, __builtin_amdgcn_sad_u16(wb, tb, 1u));
+    const int code = __builtin_amdgcn_sdot2(dA, w13, __mul24(dz, 9) + 13, false);
+    const uint32_t bit = __builtin_elementwise_sub_sat(s1, q);
+    return bit << ((uint32_t)code & 31u);
+}
+
+template <int G, bool EXACT, typename CT>
+__device__ __forceinline__ void grow_lattice26_body(const GrowArgs &a, uint64_t bid, int H)
+{
+    const int cpb = blockDim.x / G;
+    extern __shared__ uint32_t z26_lds[];
+    uint32_t *lutA = z26_lds;        // [27] A-word move of each code
+    uint32_t *lutB = z26_lds + 32;   // [27] B-word move
+    uint32_t *chains = z26_lds + 64; // cpb chains of 2 H words
+    __shared__ double logm[27];
+    for (int q = threadIdx.x; q < 27; q += blockDim.x) {
+        const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = q / 9 - 1;
+        lutA[q] = (uint32_t)(dx + dy * 65536);
+        lutB[q] = (uint32_t)dz;
+        logm[q] = a.logm[q];
+    }
+    for (int w = threadIdx.x; w < cpb * 2 * H; w += blockDim.x) chains[w] = (w / H) & 1 ? kZ26OriginB : 0u;
+    __syncthreads();
+
+    const int t = threadIdx.x & (G - 1);
+    const int chb = threadIdx.x / G;
+    const int lane = threadIdx.x & 63;
+    const int gbase = lane & ~(G - 1);
+    const uint64_t c = bid * cpb + chb;
+    const bool valid = c < a.n_chains;
+    const uint64_t g = a.chain_offset + c;
+    const int N = a.n_monomers;
+    uint32_t *PA = chains + chb * 2 * H;
+    uint32_t *PB = PA + H;
+
+    uint32_t ta = 0, tb = 0;
+    bool alive = false;
+    int grown = 1;
+    uint32_t n_mine = 0; // steps with m = t + 1
+    uint64_t wx = 1;
+    bool rng_fail = false;
+    Philox4 blk{0, 0, 0, 0};
+    double res_lw = -__builtin_huge_val();
+    uint64_t res_wx = 0;
+    int64_t res_nn = 0;
+    int32_t res_ex = 0, res_ey = 0, res_ez = 0;
+    int res_grown = 1;
+    bool res_alive = false;
+    bool pending = valid;
+
+    for (uint32_t rd = 0; rd < a.max_rounds; ++rd) {
+        if (pending) {
+            if (rd > 0)
+                for (int w = t; w < 2 * H; w += G) PA[w] = w < H ? 0u : kZ26OriginB;
+            ta = kZ26OriginA;
+            tb = kZ26OriginB;
+            n_mine = 0;
+            wx = 1;
+        }
+        z26_wave_sync();
+        if (pending && t == 0) {
+            PA[0] = ta;
+            PB[0] = tb;
+        }
+        z26_wave_sync();
+        alive = pending;
+        grown = 1;
+        const uint32_t hi = rd << 16;
+
+        for (int i = 1; i < N; ++i) {
+            // monomers 0 .. i-2 can occupy a candidate site (i-1 is the tip)
+            const int nrel = i - 1;
+            const int passes = (nrel + 4 * G - 1) / (4 * G);
+            uint32_t occ = 0, occ2 = 0;
+            for (int q = 0; q < passes; ++q) {
+                const int kk = q * 4 * G + 4 * t;
+                const uint4 wa = *(const uint4 *)(PA + kk);
+                const uint4 wb = *(const uint4 *)(PB + kk);
+                // entries at nrel and beyond hold the sentinel (never a
+                // candidate) or the tip (code 13, masked below)
+                occ |= z26_bits(wa.x, wb.x, ta, tb);
+                occ2 |= z26_bits(wa.y, wb.y, ta, tb);
+                occ |= z26_bits(wa.z, wb.z, ta, tb);
+                occ2 |= z26_bits(wa.w, wb.w, ta, tb);
+            }
+            occ = z26_group_or<G>(occ | occ2);
+            const uint32_t freem = ~occ & kZ26Codes;
+            const uint32_t m = __builtin_popcount(freem);
+
+            if (i == 1 || (i & 7) == 0) blk = draw(a.seed, g, (uint32_t)(i >> 3) | hi, kSlotSelect, 0);
+            const uint32_t x = half_word(blk, (uint32_t)(i & 7));
+            const uint32_t p = x * m;
+            uint32_t r = p >> 16;
+            if (__builtin_expect(alive && (p & 0xFFFFu) < m, 0)) {
+                r = lemire_redraw16(a.seed, g, (uint32_t)i | hi, m, x);
+                if (r == kPickFailed) {
+                    rng_fail = true;
+                    r = 0;
+                }
+            }
+            // the r-th free code
+            uint32_t msk = freem;
+            for (uint32_t q = 0; q < r; ++q) msk &= msk - 1u;
+            const uint32_t code = msk ? (uint32_t)__builtin_ctz(msk) : 13u;
+
+            const bool step_ok = alive && m != 0;
+            if (alive && m == 0) {
+                alive = false;
+                grown = i;
+            }
+            if (step_ok) {
+                ta = ta + lutA[code];
+                tb = tb + lutB[code];
+                n_mine += (m == (uint32_t)t + 1u) ? 1u : 0u;
+                if (EXACT) wx = wx * (uint64_t)m;
+                if (t == 0) {
+                    PA[i] = ta;
+                    PB[i] = tb;
+                }
+            }
+            z26_wave_sync();
+        }
+        if (alive) grown = N;
+
+        // log W = sum over m = 1..26, ascending, of n_m log m; n_m is held by
+        // lane m - 1 of the group
+        double lw = 0.0;
+        for (int mm = 1; mm <= 26; ++mm) {
+            const uint32_t nm = __shfl(n_mine, gbase + mm - 1, 64);
+            lw = lw + (double)nm * logm[mm];
+        }
+        // observables over the placed monomers (integer sums: any order)
+        int32_t sx = 0, sy = 0, sz = 0;
+        int64_t s2 = 0;
+        for (int j = t; j < grown; j += G) {
+            const int32_t xx = (int32_t)(PA[j] & 0xFFFFu) - 32768;
+            const int32_t yy = (int32_t)(PA[j] >> 16) - 32768;
+            const int32_t zz = (int32_t)(PB[j] & 0xFFFFu) - 32768;
+            sx += xx;
+            sy += yy;
+            sz += zz;
+            s2 += (int64_t)(xx * xx + yy * yy + zz * zz);
+        }
+#pragma unroll
+        for (int off = 1; off < G; off <<= 1) {
+            sx += __shfl_xor(sx, off, 64);
+            sy += __shfl_xor(sy, off, 64);
+            sz += __shfl_xor(sz, off, 64);
+            const int lo = __shfl_xor((int)(uint32_t)s2, off, 64);
+            const int hh = __shfl_xor((int)(uint32_t)((uint64_t)s2 >> 32), off, 64);
+            s2 += (int64_t)(((uint64_t)(uint32_t)hh << 32) | (uint32_t)lo);
+        }
+        if (pending && (alive || rd + 1 >= a.max_rounds)) {
+            const int64_t gg = grown;
+            res_nn = gg * s2 - ((int64_t)sx * sx + (int64_t)sy * sy + (int64_t)sz * sz);
+            res_ex = (int32_t)(ta & 0xFFFFu) - 32768;
+            res_ey = (int32_t)(ta >> 16) - 32768;
+            res_ez = (int32_t)(tb & 0xFFFFu) - 32768;
+            res_lw = alive ? lw : -__builtin_huge_val();
+            res_wx = alive ? wx : 0ull;
+            res_grown = grown;
+            res_alive = alive;
+            pending = false;
+        }
+        if (__ballot(pending) == 0) break;
+    }
+
+    if (valid && t == 0) {
+        if (a.log_w) a.log_w[c] = res_lw;
+        if (EXACT && a.w_exact) a.w_exact[c] = res_wx;
+        if (a.r_end) {
+            CT *re = (CT *)a.r_end;
+            re[c] = (CT)res_ex;
+            re[a.n_chains + c] = (CT)res_ey;
+            re[2 * a.n_chains + c] = (CT)res_ez;
+        }
+        if (a.r2) a.r2[c] = (double)((int64_t)res_ex * res_ex + (int64_t)res_ey * res_ey + (int64_t)res_ez * res_ez);
+        if (a.n2rg2) a.n2rg2[c] = res_nn;
+        if (a.rg2) a.rg2[c] = (double)res_nn / ((double)res_grown * (double)res_grown);
+        if (a.n_grown) a.n_grown[c] = (uint16_t)res_grown;
+    }
+    if (rng_fail) atomicExch(a.status, 6);
+    const uint64_t bits = (res_alive && t == 0) ? (uint64_t)__double_as_longlong(res_lw) : 0ull;
+    const uint64_t wmax = wave_max_u64(bits);
+    if ((threadIdx.x & 63) == 0 && wmax != 0) atomicMax(a.log_w_max_bits, (unsigned long long)wmax);
+}
+
+template <int G, bool EXACT, typename CT>
+__global__ __launch_bounds__(256) void grow_lattice26(GrowArgs a, int H)
+{
+    grow_lattice26_body<G, EXACT, CT>(a, blockIdx.x, H);
+}
+
+template <int G, bool EXACT, typename CT>
+__global__ __launch_bounds__(256) void grow_lattice26_batch(const GrowEntry *tab, const uint64_t *block0, int n)
+{
+    const int e = find_segment(block0, n, blockIdx.x);
+    grow_lattice26_body<G, EXACT, CT>(tab[e].a, blockIdx.x - block0[e], tab[e].H);
+}
+
+int lattice26_max_monomers() { return 16384; }
+
+// G = 32 lanes per chain up to N = 4096, 64 beyond; 256-thread blocks when
+// the block's planes fit in half a CU's LDS, else one wave.
+hipError_t lattice26_variant(const GrowArgs &a, bool exact, bool i16, GrowVariant *v)
+{
+    const int N = a.n_monomers;
+    const int G = N <= 4096 ? 32 : 64;
+    const int H = (N + 4 * G - 1) / (4 * G) * (4 * G);
+    auto bytes = [&](int threads) { return ((size_t)64 + (size_t)(threads / G) * 2 * H) * sizeof(uint32_t); };
+    const int threads = bytes(256) <= 81920 ? 256 : 64;
+    if (bytes(threads) > 163840) return hipErrorInvalidValue;
+    v->family = 3;
+    v->p0 = G;
+    v->p1 = exact ? 1 : 0;
+    v->p2 = i16 ? 1 : 0;
+    v->threads = threads;
+    v->cpb = threads / G;
+    v->shmem = bytes(threads);
+    v->H = H;
+    v->S = 0;
+    return hipSuccess;
+}
+
+template <int G, bool EXACT, typename CT>
+static hipError_t launch26(const GrowArgs &a, const GrowVariant &v, const GrowEntry *tab, const uint64_t *block0,
+                           int n, uint64_t blocks, size_t shmem, hipStream_t s)
+{
+    const void *fn = tab ? (const void *)grow_lattice26_batch<G, EXACT, CT> : (const void *)grow_lattice26<G, EXACT, CT>;
+    if (shmem > 65536) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+        if (e != hipSuccess) return e;
+    }
+    if (tab)
+        hipLaunchKernelGGL((grow_lattice26_batch<G, EXACT, CT>), dim3((uint32_t)blocks), dim3(v.threads), shmem, s,
+                           tab, block0, n);
+    else
+        hipLaunchKernelGGL((grow_lattice26<G, EXACT, CT>), dim3((uint32_t)blocks), dim3(v.threads), shmem, s, a,
+                           v.H);
+    return hipGetLastError();
+}
+
+static hipError_t dispatch26(const GrowArgs &a, const GrowVariant &v, const GrowEntry *tab, const uint64_t *block0,
+                             int n, uint64_t blocks, size_t shmem, hipStream_t s)
+{
+    const bool i16 = v.p2 != 0;
+    if (v.p1) // exact weights (N <= 14)
+        return i16 ? launch26<32, true, int16_t>(a, v, tab, block0, n, blocks, shmem, s)
+                   : launch26<32, true, int32_t>(a, v, tab, block0, n, blocks, shmem, s);
+    if (v.p0 == 32)
+        return i16 ? launch26<32, false, int16_t>(a, v, tab, block0, n, blocks, shmem, s)
+                   : launch26<32, false, int32_t>(a, v, tab, block0, n, blocks, shmem, s);
+    return i16 ? launch26<64, false, int16_t>(a, v, tab, block0, n, blocks, shmem, s)
+               : launch26<64, false, int32_t>(a, v, tab, block0, n, blocks, shmem, s);
+}
+
+hipError_t launch_grow_lattice26(const GrowArgs &a, bool exact, bool i16, hipStream_t s)
+{
+    GrowVariant v;
+    hipError_t e = lattice26_variant(a, exact, i16, &v);
+    if (e != hipSuccess) return e;
+    const uint64_t blocks = (a.n_chains + v.cpb - 1) / v.cpb;
+    return dispatch26(a, v, nullptr, nullptr, 0, blocks, v.shmem, s);
+}
+
+hipError_t launch_lattice26_batch(const GrowVariant &v, const GrowEntry *tab, const uint64_t *block0, int n,
+                                  uint64_t blocks, size_t shmem, hipStream_t s)
+{
+    return dispatch26(GrowArgs{}, v, tab, block0, n, blocks, shmem, s);
+}
+
+} // namespace rsaw

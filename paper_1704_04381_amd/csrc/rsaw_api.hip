@@ -34,6 +34,11 @@ hipError_t launch_lattice_lds_batch(const GrowVariant &v, const GrowEntry *tab, 
                                     int n, uint64_t blocks, size_t shmem, hipStream_t s);
 hipError_t launch_real_batch(const GrowVariant &v, const GrowEntry *tab, const uint64_t *block0, int n,
                              uint64_t blocks, size_t shmem, hipStream_t s);
+int lattice26_max_monomers();
+hipError_t lattice26_variant(const GrowArgs &a, bool exact, bool i16, GrowVariant *v);
+hipError_t launch_grow_lattice26(const GrowArgs &a, bool exact, bool i16, hipStream_t s);
+hipError_t launch_lattice26_batch(const GrowVariant &v, const GrowEntry *tab, const uint64_t *block0, int n,
+                                  uint64_t blocks, size_t shmem, hipStream_t s);
 } // namespace rsaw
 
 namespace {
@@ -203,6 +208,14 @@ rsaw_status validate(const rsaw_config *cfg)
             return fail(RSAW_E_OVERFLOW, "RSAW_EXACT_W needs n_monomers <= 28");
         if (N > rsaw::lattice_lds_max_monomers())
             return fail(RSAW_E_UNSUPPORTED, "lattice kernels support n_monomers <= 16384");
+    } else if (cfg->geometry == RSAW_LATTICE_26) {
+        if (cfg->k_trials != 26) return fail(RSAW_E_INVALID, "26-neighbour lattice needs k_trials == 26");
+        if (cfg->coord_type != RSAW_I16 && cfg->coord_type != RSAW_I32)
+            return fail(RSAW_E_INVALID, "lattice coord_type must be RSAW_I16 or RSAW_I32");
+        if ((cfg->flags & RSAW_EXACT_W) && N > 14)
+            return fail(RSAW_E_OVERFLOW, "RSAW_EXACT_W on the 26-neighbour lattice needs n_monomers <= 14");
+        if (N > rsaw::lattice26_max_monomers())
+            return fail(RSAW_E_UNSUPPORTED, "26-neighbour lattice kernels support n_monomers <= 16384");
     } else if (cfg->geometry == RSAW_REAL_HS) {
         if (cfg->k_trials < 1 || cfg->k_trials > 64)
             return fail(RSAW_E_INVALID, "real-space k_trials must be in 1..64");
@@ -224,7 +237,7 @@ rsaw_status validate(const rsaw_config *cfg)
 // histogram accumulators and the per-chain arrays the reduction needs when
 // the caller does not supply them.
 struct EnsLayout {
-    bool lattice, exact, reduce;
+    bool lattice, z26, exact, reduce;
     int bins;
     uint32_t n_blocks; // reduce blocks
     uint64_t chunk;    // chains per reduce block
@@ -240,7 +253,8 @@ void layout_ensemble(const rsaw_config *cfg, const rsaw_chain_out &o, bool reduc
                      EnsLayout *L)
 {
     const uint64_t M = cfg->n_chains;
-    L->lattice = cfg->geometry == RSAW_LATTICE_SC;
+    L->lattice = cfg->geometry != RSAW_REAL_HS;
+    L->z26 = cfg->geometry == RSAW_LATTICE_26;
     L->exact = L->lattice && (cfg->flags & RSAW_EXACT_W);
     L->reduce = reduce;
     L->bins = reduce ? cfg->hist_bins : 0;
@@ -383,8 +397,10 @@ rsaw_status gen_impl(const rsaw_config *cfg, const rsaw_chain_out *out, rsaw_sum
         bool timed = false;
         st = timing_start(s, &tp, &timed);
         if (st != RSAW_OK) return st;
-        e = L.lattice ? rsaw::launch_grow_lattice(a, L.exact, cfg->coord_type == RSAW_I16, s)
-                      : rsaw::launch_grow_real(a, s);
+        const bool i16 = cfg->coord_type == RSAW_I16;
+        e = L.z26       ? rsaw::launch_grow_lattice26(a, L.exact, i16, s)
+            : L.lattice ? rsaw::launch_grow_lattice(a, L.exact, i16, s)
+                        : rsaw::launch_grow_real(a, s);
         if (timed) {
             st = timing_stop(s, tp);
             if (st != RSAW_OK) return st;
@@ -441,6 +457,8 @@ rsaw_status batch_impl(const rsaw_config *cfgs, const rsaw_chain_out *outs, int3
         const bool i16 = cfgs[i].coord_type == RSAW_I16;
         if (!L[i].lattice) {
             e = rsaw::real_variant(probe, &var[i]);
+        } else if (L[i].z26) {
+            e = rsaw::lattice26_variant(probe, L[i].exact, i16, &var[i]);
         } else if (L[i].exact || cfgs[i].n_monomers <= 64) {
             rsaw::lattice_reg_variant(probe, L[i].exact, i16, &var[i]);
             e = hipSuccess;
@@ -546,6 +564,8 @@ rsaw_status batch_impl(const rsaw_config *cfgs, const rsaw_chain_out *outs, int3
             e = rsaw::launch_lattice_reg_batch(v, d_gtab + G.first, d_gb0 + G.first, cnt, G.blocks, s);
         else if (v.family == 1)
             e = rsaw::launch_lattice_lds_batch(v, d_gtab + G.first, d_gb0 + G.first, cnt, G.blocks, G.shmem, s);
+        else if (v.family == 3)
+            e = rsaw::launch_lattice26_batch(v, d_gtab + G.first, d_gb0 + G.first, cnt, G.blocks, G.shmem, s);
         else
             e = rsaw::launch_real_batch(v, d_gtab + G.first, d_gb0 + G.first, cnt, G.blocks, G.shmem, s);
         if (timed) {

@@ -148,7 +148,7 @@ __device__ __forceinline__ int find_segment(const uint64_t *block0, int n, uint6
 // Launch shape of one growth kernel variant; ensembles with equal kernel,
 // template parameters and block size share one batched launch.
 struct GrowVariant {
-    int family;         // 0 lattice (registers), 1 lattice (LDS), 2 hard spheres
+    int family;         // 0 lattice (registers), 1 lattice (LDS), 2 hard spheres, 3 26-neighbour lattice
     int p0, p1, p2;     // template parameters of the family
     int threads;        // threads per block
     int cpb;            // chains per block

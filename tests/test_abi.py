@@ -49,6 +49,11 @@ BAD = [
     (dict(geometry="real", N=16, k=8, bond_length=float("nan")), 1),
     (dict(geometry="real", N=16, k=8, exact_w=True), 1),
     (dict(geometry="real", N=16385, k=8), 2),
+    (dict(geometry="lattice26", N=16, k=6), 1),
+    (dict(geometry="lattice26", N=16, k=26, coord="f64"), 1),
+    (dict(geometry="lattice26", N=15, k=26, exact_w=True), 3),
+    (dict(geometry="lattice26", N=16385, k=26), 2),
+    (dict(geometry="lattice", N=16, k=26), 1),
     (dict(geometry=7, N=16, k=6), 1),
     (dict(geometry="lattice", N=16, k=6, hist_bins=-1), 1),
     (dict(geometry="lattice", N=16, k=6, hist_bins=300), 2),

@@ -1,0 +1,109 @@
+"""Parity of the 26-neighbour lattice kernel (RSAW_LATTICE_26, the z = 26
+lattice space of Sec. 3.3.2) with the oracle, bit for bit: log W, exact W,
+end vector, R^2, g^2 Rg^2, Rg^2 and monomers placed per chain, and the
+ensemble summary and histogram.  Sizes cover one and several 128-monomer
+scan passes, the switch from 32 to 64 lanes per chain above N = 4096, the
+largest N, and ragged chain counts over 256-thread blocks.
+
+Dead ends are too rare on this lattice to appear in test-sized ensembles
+(none in 10^4 chains of N <= 3000 in the oracle), so the dead-end and
+restart branches are exercised here only in their no-dead-end form.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+import paper_1704_04381_amd as rs
+
+pytestmark = pytest.mark.gpu
+
+RTOL_SUM = 1e-12
+
+
+def _case(N, M, seed, coord="i32", exact_w=False, bins=0, offset=0, restart=False):
+    print(f"[gpu] lattice26 N={N} M={M} seed={seed} coord={coord} exact={exact_w} "
+          f"bins={bins} offset={offset} restart={restart}", flush=True)
+    out, s = rs.gen_chains("lattice26", N, 26, M, seed, coord=coord, exact_w=exact_w,
+                           hist_bins=bins, chain_offset=offset, restart=restart)
+    torch.cuda.synchronize()
+    out = {n: t.cpu().numpy() for n, t in out.items()}
+    ref = oracle.gen_lattice(seed, N, M, chain_offset=offset, restart=restart, z26=True)
+    np.testing.assert_array_equal(out["n_grown"].view(np.uint16), ref["n_grown"])
+    np.testing.assert_array_equal(out["log_w"], ref["log_w"])
+    np.testing.assert_array_equal(out["r_end"].astype(np.int32), ref["r_end"])
+    np.testing.assert_array_equal(out["r2"], ref["r2"].astype(np.float64))
+    np.testing.assert_array_equal(out["n2rg2"], ref["n2rg2"])
+    np.testing.assert_array_equal(out["rg2"], ref["rg2"])
+    if exact_w:
+        assert ref["w_exact_ok"].all()
+        np.testing.assert_array_equal(out["w_exact"], ref["w_exact"])
+    red = oracle.reduce(N, ref["log_w"], ref["r2"], ref["rg2"], ref["n_grown"], bins=bins)
+    assert s["status"] == 0 and s["n_chains"] == M
+    assert s["n_alive"] == red["alive"] and s["steps"] == red["steps"]
+    if red["alive"]:
+        assert s["log_w_max"] == red["log_w_max"]
+        for key in ("sum_w", "sum_w2", "sum_w_r2", "sum_w_rg2", "log_c_est", "r2_mean",
+                    "rg2_mean", "ess"):
+            assert abs(s[key] - red[key]) <= RTOL_SUM * abs(red[key]), (key, s[key], red[key])
+    if exact_w:
+        ex = oracle.reduce_exact(ref["w_exact"], ref["r2"], ref["n2rg2"])
+        assert s["exact_valid"] == 1
+        assert s["sum_w_exact"] == ex["sum_w"]
+        assert s["sum_w_r2_exact"] == ex["sum_w_r2"]
+        assert s["sum_w_n2rg2_exact"] == ex["sum_w_n2rg2"]
+    if bins:
+        np.testing.assert_array_equal(out["hist_n"], red["hist_n"])
+        np.testing.assert_allclose(out["hist_w"], red["hist_w"], rtol=RTOL_SUM, atol=0)
+    return out, s
+
+
+@pytest.mark.parametrize("N,M,seed,coord", [
+    (1, 300, 1, "i32"), (2, 257, 2, "i16"), (3, 1_000, 3, "i32"), (5, 999, 4, "i16"),
+    (16, 5_000, 5, "i32"), (64, 20_000, 6, "i16"), (100, 3_001, 7, "i32"),
+    (129, 1_000, 8, "i16"), (300, 700, 9, "i32")])
+def test_lattice26_bit_exact(N, M, seed, coord):
+    _case(N, M, seed, coord=coord, bins=256 if N > 1 else 0)
+
+
+@pytest.mark.parametrize("N,M,seed", [(14, 20_000, 11), (10, 3_333, 12), (2, 100, 13)])
+def test_lattice26_exact_weights(N, M, seed):
+    _case(N, M, seed, exact_w=True, bins=64)
+
+
+@pytest.mark.parametrize("N,M,seed,coord", [
+    (1_000, 65, 21, "i16"), (4_096, 5, 22, "i32"), (4_097, 5, 23, "i16"),
+    (6_000, 3, 24, "i32"), (16_384, 1, 25, "i16")])
+def test_lattice26_long_chains(N, M, seed, coord):
+    _case(N, M, seed, coord=coord, bins=256)
+
+
+def test_lattice26_offset_and_restart():
+    _case(64, 2_000, 31, offset=123_456_789, bins=32)
+    a, sa = _case(40, 3_000, 32, restart=True)
+    b, sb = _case(40, 3_000, 32, restart=False)
+    for key in a:
+        np.testing.assert_array_equal(a[key], b[key])
+
+
+def test_lattice26_in_mixed_batch_equals_single_calls():
+    specs = [dict(geometry="lattice26", N=64, k=26, n_chains=5_000, seed=41, coord="i16", hist_bins=64),
+             dict(geometry="lattice", N=64, k=6, n_chains=3_000, seed=42, coord="i16"),
+             dict(geometry="lattice26", N=12, k=26, n_chains=777, seed=43, exact_w=True),
+             dict(geometry="lattice26", N=200, k=26, n_chains=300, seed=44),
+             dict(geometry="real", N=30, k=8, n_chains=500, seed=45),
+             dict(geometry="lattice26", N=5_000, k=26, n_chains=2, seed=46)]
+    print("[gpu] lattice26 mixed batch", flush=True)
+    res = rs.gen_batch(specs)
+    torch.cuda.synchronize()
+    for i, (sp, (out, s)) in enumerate(zip(specs, res)):
+        sp = dict(sp)
+        one, one_s = rs.gen_chains(sp.pop("geometry"), sp.pop("N"), sp.pop("k"), sp.pop("n_chains"),
+                                   sp.pop("seed"), **sp)
+        torch.cuda.synchronize()
+        for key in out:
+            np.testing.assert_array_equal(out[key].cpu().numpy(), one[key].cpu().numpy(),
+                                          err_msg=f"ensemble {i} {key}")
+        for key in s:
+            assert s[key] == one_s[key] or (s[key] != s[key] and one_s[key] != one_s[key]), (i, key)
