@@ -200,25 +200,28 @@ __device__ __forceinline__ void grow_lattice_reg_body(const GrowArgs &a, uint64_
 }
 
 template <int NMAX, bool EXACT, typename CT>
-__global__ __launch_bounds__(256) void grow_lattice_reg(GrowArgs a)
+__global__ __launch_bounds__(256) void grow_lattice_reg(GrowArgs a, uint64_t base)
 {
-    grow_lattice_reg_body<NMAX, EXACT, CT>(a, blockIdx.x);
+    grow_lattice_reg_body<NMAX, EXACT, CT>(a, base + blockIdx.x);
 }
 
 // Batched launch: block b serves the ensemble whose block range holds b.
 template <int NMAX, bool EXACT, typename CT>
-__global__ __launch_bounds__(256) void grow_lattice_reg_batch(const GrowEntry *tab, const uint64_t *block0, int n)
+__global__ __launch_bounds__(256) void grow_lattice_reg_batch(const GrowEntry *tab, const uint64_t *block0, int n,
+                                                              uint64_t base)
 {
-    const int e = find_segment(block0, n, blockIdx.x);
-    grow_lattice_reg_body<NMAX, EXACT, CT>(tab[e].a, blockIdx.x - block0[e]);
+    const uint64_t bid = base + blockIdx.x;
+    const int e = find_segment(block0, n, bid);
+    grow_lattice_reg_body<NMAX, EXACT, CT>(tab[e].a, bid - block0[e]);
 }
 
 template <int NMAX, bool EXACT, typename CT>
 static hipError_t launch(const GrowArgs &a, hipStream_t s)
 {
     const uint64_t blocks = (a.n_chains + 255) / 256;
-    hipLaunchKernelGGL((grow_lattice_reg<NMAX, EXACT, CT>), dim3((uint32_t)blocks), dim3(256), 0, s, a);
-    return hipGetLastError();
+    return launch_sliced(blocks, 256, [&](uint64_t b0, uint32_t nb) {
+        hipLaunchKernelGGL((grow_lattice_reg<NMAX, EXACT, CT>), dim3(nb), dim3(256), 0, s, a, b0);
+    });
 }
 
 // Dispatch on the N bucket, exact-weight flag and output coordinate type.
@@ -257,9 +260,10 @@ template <int NMAX, bool EXACT, typename CT>
 static hipError_t launch_batch(const GrowEntry *tab, const uint64_t *block0, int n, uint64_t blocks,
                                hipStream_t s)
 {
-    hipLaunchKernelGGL((grow_lattice_reg_batch<NMAX, EXACT, CT>), dim3((uint32_t)blocks), dim3(256), 0, s,
-                       tab, block0, n);
-    return hipGetLastError();
+    return launch_sliced(blocks, 256, [&](uint64_t b0, uint32_t nb) {
+        hipLaunchKernelGGL((grow_lattice_reg_batch<NMAX, EXACT, CT>), dim3(nb), dim3(256), 0, s, tab, block0, n,
+                           b0);
+    });
 }
 
 hipError_t launch_lattice_reg_batch(const GrowVariant &v, const GrowEntry *tab, const uint64_t *block0,

@@ -253,16 +253,18 @@ __device__ __forceinline__ void grow_lattice26_body(const GrowArgs &a, uint64_t 
 }
 
 template <int G, bool EXACT, typename CT>
-__global__ __launch_bounds__(256) void grow_lattice26(GrowArgs a, int H)
+__global__ __launch_bounds__(256) void grow_lattice26(GrowArgs a, int H, uint64_t base)
 {
-    grow_lattice26_body<G, EXACT, CT>(a, blockIdx.x, H);
+    grow_lattice26_body<G, EXACT, CT>(a, base + blockIdx.x, H);
 }
 
 template <int G, bool EXACT, typename CT>
-__global__ __launch_bounds__(256) void grow_lattice26_batch(const GrowEntry *tab, const uint64_t *block0, int n)
+__global__ __launch_bounds__(256) void grow_lattice26_batch(const GrowEntry *tab, const uint64_t *block0, int n,
+                                                            uint64_t base)
 {
-    const int e = find_segment(block0, n, blockIdx.x);
-    grow_lattice26_body<G, EXACT, CT>(tab[e].a, blockIdx.x - block0[e], tab[e].H);
+    const uint64_t bid = base + blockIdx.x;
+    const int e = find_segment(block0, n, bid);
+    grow_lattice26_body<G, EXACT, CT>(tab[e].a, bid - block0[e], tab[e].H);
 }
 
 int lattice26_max_monomers() { return 16384; }
@@ -298,13 +300,13 @@ static hipError_t launch26(const GrowArgs &a, const GrowVariant &v, const GrowEn
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
         if (e != hipSuccess) return e;
     }
-    if (tab)
-        hipLaunchKernelGGL((grow_lattice26_batch<G, EXACT, CT>), dim3((uint32_t)blocks), dim3(v.threads), shmem, s,
-                           tab, block0, n);
-    else
-        hipLaunchKernelGGL((grow_lattice26<G, EXACT, CT>), dim3((uint32_t)blocks), dim3(v.threads), shmem, s, a,
-                           v.H);
-    return hipGetLastError();
+    return launch_sliced(blocks, v.threads, [&](uint64_t b0, uint32_t nb) {
+        if (tab)
+            hipLaunchKernelGGL((grow_lattice26_batch<G, EXACT, CT>), dim3(nb), dim3(v.threads), shmem, s, tab,
+                               block0, n, b0);
+        else
+            hipLaunchKernelGGL((grow_lattice26<G, EXACT, CT>), dim3(nb), dim3(v.threads), shmem, s, a, v.H, b0);
+    });
 }
 
 static hipError_t dispatch26(const GrowArgs &a, const GrowVariant &v, const GrowEntry *tab, const uint64_t *block0,

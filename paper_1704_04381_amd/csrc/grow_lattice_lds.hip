@@ -300,18 +300,19 @@ __device__ __forceinline__ void grow_lattice_lds_body(const GrowArgs &a, uint64_
 }
 
 template <int G, bool WIDE, typename CT>
-__global__ __launch_bounds__(256) void grow_lattice_lds(GrowArgs a, int H, int S)
+__global__ __launch_bounds__(256) void grow_lattice_lds(GrowArgs a, int H, int S, uint64_t base)
 {
-    grow_lattice_lds_body<G, WIDE, CT>(a, blockIdx.x, H, S);
+    grow_lattice_lds_body<G, WIDE, CT>(a, base + blockIdx.x, H, S);
 }
 
 // Batched launch: block b serves the ensemble whose block range holds b.
 template <int G, bool WIDE, typename CT>
 __global__ __launch_bounds__(256) void grow_lattice_lds_batch(const GrowEntry *tab, const uint64_t *block0,
-                                                              int n)
+                                                              int n, uint64_t base)
 {
-    const int e = find_segment(block0, n, blockIdx.x);
-    grow_lattice_lds_body<G, WIDE, CT>(tab[e].a, blockIdx.x - block0[e], tab[e].H, tab[e].S);
+    const uint64_t bid = base + blockIdx.x;
+    const int e = find_segment(block0, n, bid);
+    grow_lattice_lds_body<G, WIDE, CT>(tab[e].a, bid - block0[e], tab[e].H, tab[e].S);
 }
 
 // Largest lattice chain of the LDS kernel (wide words: 128 KiB per chain).
@@ -361,13 +362,14 @@ static hipError_t launch_lds(const GrowArgs &a, const GrowVariant &v, const Grow
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
         if (e != hipSuccess) return e;
     }
-    if (tab)
-        hipLaunchKernelGGL((grow_lattice_lds_batch<G, WIDE, CT>), dim3((uint32_t)blocks), dim3(v.threads),
-                           shmem, s, tab, block0, n);
-    else
-        hipLaunchKernelGGL((grow_lattice_lds<G, WIDE, CT>), dim3((uint32_t)blocks), dim3(v.threads), shmem, s,
-                           a, v.H, v.S);
-    return hipGetLastError();
+    return launch_sliced(blocks, v.threads, [&](uint64_t b0, uint32_t nb) {
+        if (tab)
+            hipLaunchKernelGGL((grow_lattice_lds_batch<G, WIDE, CT>), dim3(nb), dim3(v.threads), shmem, s, tab,
+                               block0, n, b0);
+        else
+            hipLaunchKernelGGL((grow_lattice_lds<G, WIDE, CT>), dim3(nb), dim3(v.threads), shmem, s, a, v.H, v.S,
+                               b0);
+    });
 }
 
 static hipError_t dispatch_lds(const GrowArgs &a, const GrowVariant &v, const GrowEntry *tab,

@@ -373,17 +373,19 @@ __device__ __forceinline__ void grow_real_body(const GrowArgs &a, uint64_t bid, 
 }
 
 template <int G>
-__global__ __launch_bounds__(256) void grow_real_tp(GrowArgs a)
+__global__ __launch_bounds__(256) void grow_real_tp(GrowArgs a, uint64_t base)
 {
-    grow_real_body<G, false>(a, blockIdx.x);
+    grow_real_body<G, false>(a, base + blockIdx.x);
 }
 
 // Batched launch: block b serves the ensemble whose block range holds b.
 template <int G>
-__global__ __launch_bounds__(256) void grow_real_tp_batch(const GrowEntry *tab, const uint64_t *block0, int n)
+__global__ __launch_bounds__(256) void grow_real_tp_batch(const GrowEntry *tab, const uint64_t *block0, int n,
+                                                          uint64_t base)
 {
-    const int e = find_segment(block0, n, blockIdx.x);
-    grow_real_body<G, false>(tab[e].a, blockIdx.x - block0[e]);
+    const uint64_t bid = base + blockIdx.x;
+    const int e = find_segment(block0, n, bid);
+    grow_real_body<G, false>(tab[e].a, bid - block0[e]);
 }
 
 // Chains beyond the LDS limit: a persistent grid of one-wave blocks, block s
@@ -461,12 +463,12 @@ static hipError_t launch_g(const GrowArgs &a, const GrowVariant &v, const GrowEn
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
         if (e != hipSuccess) return e;
     }
-    if (tab)
-        hipLaunchKernelGGL((grow_real_tp_batch<G>), dim3((uint32_t)blocks), dim3(v.threads), shmem, s, tab,
-                           block0, n);
-    else
-        hipLaunchKernelGGL((grow_real_tp<G>), dim3((uint32_t)blocks), dim3(v.threads), shmem, s, a);
-    return hipGetLastError();
+    return launch_sliced(blocks, v.threads, [&](uint64_t b0, uint32_t nb) {
+        if (tab)
+            hipLaunchKernelGGL((grow_real_tp_batch<G>), dim3(nb), dim3(v.threads), shmem, s, tab, block0, n, b0);
+        else
+            hipLaunchKernelGGL((grow_real_tp<G>), dim3(nb), dim3(v.threads), shmem, s, a, b0);
+    });
 }
 
 static hipError_t dispatch_real(const GrowArgs &a, const GrowVariant &v, const GrowEntry *tab,

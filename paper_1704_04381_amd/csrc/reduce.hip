@@ -222,9 +222,9 @@ __global__ __launch_bounds__(kRT) void reduce_final(ReduceArgs a, uint32_t n_blo
 }
 
 // Batched forms: one entry per ensemble.
-__global__ void reduce_init_batch(const ReduceEntry *tab, int n)
+__global__ void reduce_init_batch(const ReduceEntry *tab, int n, uint64_t base)
 {
-    const ReduceEntry &e = tab[blockIdx.x];
+    const ReduceEntry &e = tab[base + blockIdx.x];
     if (threadIdx.x == 0) {
         *e.lmax = 0ull;
         *e.status = 0;
@@ -232,15 +232,17 @@ __global__ void reduce_init_batch(const ReduceEntry *tab, int n)
     for (int q = threadIdx.x; q < 4 * e.r.bins; q += blockDim.x) e.r.hist_acc[q] = 0ull;
 }
 
-__global__ __launch_bounds__(kRT) void reduce_partials_batch(const ReduceEntry *tab, const uint64_t *block0, int n)
+__global__ __launch_bounds__(kRT) void reduce_partials_batch(const ReduceEntry *tab, const uint64_t *block0, int n,
+                                                              uint64_t base)
 {
-    const int e = find_segment(block0, n, blockIdx.x);
-    reduce_partials_body(tab[e].r, blockIdx.x - block0[e]);
+    const uint64_t bid = base + blockIdx.x;
+    const int e = find_segment(block0, n, bid);
+    reduce_partials_body(tab[e].r, bid - block0[e]);
 }
 
-__global__ __launch_bounds__(kRT) void reduce_final_batch(const ReduceEntry *tab, int n)
+__global__ __launch_bounds__(kRT) void reduce_final_batch(const ReduceEntry *tab, int n, uint64_t base)
 {
-    const ReduceEntry &e = tab[blockIdx.x];
+    const ReduceEntry &e = tab[base + blockIdx.x];
     reduce_final_body(e.r, e.n_blocks, e.out, e.hist_w, e.hist_n);
 }
 
@@ -272,18 +274,18 @@ hipError_t launch_reduce_batch(const ReduceEntry *tab, const uint64_t *block0, i
                                int max_bins, hipStream_t s, bool init_only)
 {
     if (n <= 0) return hipSuccess;
-    if (init_only) {
-        hipLaunchKernelGGL(reduce_init_batch, dim3((uint32_t)n), dim3(256), 0, s, tab, n);
-        return hipGetLastError();
-    }
-    if (total_blocks > 0) {
-        hipLaunchKernelGGL(reduce_partials_batch, dim3((uint32_t)total_blocks), dim3(kRT),
-                           reduce_partials_shmem(max_bins), s, tab, block0, n);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(reduce_final_batch, dim3((uint32_t)n), dim3(kRT), 0, s, tab, n);
-    return hipGetLastError();
+    if (init_only)
+        return launch_sliced((uint64_t)n, 256, [&](uint64_t b0, uint32_t nb) {
+            hipLaunchKernelGGL(reduce_init_batch, dim3(nb), dim3(256), 0, s, tab, n, b0);
+        });
+    const size_t shmem = reduce_partials_shmem(max_bins);
+    hipError_t e = launch_sliced(total_blocks, kRT, [&](uint64_t b0, uint32_t nb) {
+        hipLaunchKernelGGL(reduce_partials_batch, dim3(nb), dim3(kRT), shmem, s, tab, block0, n, b0);
+    });
+    if (e != hipSuccess) return e;
+    return launch_sliced((uint64_t)n, kRT, [&](uint64_t b0, uint32_t nb) {
+        hipLaunchKernelGGL(reduce_final_batch, dim3(nb), dim3(kRT), 0, s, tab, n, b0);
+    });
 }
 
 } // namespace rsaw

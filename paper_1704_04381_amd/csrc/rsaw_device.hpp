@@ -145,6 +145,22 @@ __device__ __forceinline__ int find_segment(const uint64_t *block0, int n, uint6
     return lo;
 }
 
+// Grids are issued in slices of at most 2^31 work-items (a dispatch packet
+// counts work-items in 32 bits); each slice passes its first block index
+// `base`, and block b of it serves block base + b of the whole grid.
+template <typename F>
+inline hipError_t launch_sliced(uint64_t blocks, int threads, F &&launch_one)
+{
+    const uint64_t step = ((uint64_t)1 << 31) / (uint64_t)threads;
+    for (uint64_t b0 = 0; b0 < blocks; b0 += step) {
+        const uint64_t nb = blocks - b0 < step ? blocks - b0 : step;
+        launch_one(b0, (uint32_t)nb);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // Launch shape of one growth kernel variant; ensembles with equal kernel,
 // template parameters and block size share one batched launch.
 struct GrowVariant {

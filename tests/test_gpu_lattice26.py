@@ -107,3 +107,28 @@ def test_lattice26_in_mixed_batch_equals_single_calls():
                                           err_msg=f"ensemble {i} {key}")
         for key in s:
             assert s[key] == one_s[key] or (s[key] != s[key] and one_s[key] != one_s[key]), (i, key)
+
+
+def test_grid_slices_cover_every_chain():
+    """A grid above 2^31 work-items is issued in slices: 1.5e8 chains of 32
+    lanes each take three launches; every chain must be grown once, with the
+    chains at the slice boundaries equal to the oracle's."""
+    N, M, seed = 2, 150_000_000, 51
+    print(f"[gpu] lattice26 sliced grid N={N} M={M}", flush=True)
+    out, s = rs.gen_chains("lattice26", N, 26, M, seed, coord="i16", hist_bins=4)
+    torch.cuda.synchronize()
+    assert s["status"] == 0 and s["n_alive"] == M and s["steps"] == M
+    assert s["sum_w"] == float(M)  # every chain has W = 26 = max W
+    hn = out["hist_n"].cpu().numpy()
+    assert hn.sum() == M and hn[0] == 0 and hn[1] == 0
+    # R^2 in {1, 2, 3} with probabilities 6, 12, 8 over 26
+    p1 = hn[2] / M
+    assert abs(p1 - 6 / 26) < 6 * (6 / 26 * 20 / 26 / M) ** 0.5
+    per_slice = ((1 << 31) // 256) * 8
+    for c0 in (0, per_slice - 3, 2 * per_slice - 3, M - 5):
+        ref = oracle.gen_lattice(seed, N, 6, chain_offset=c0, z26=True)
+        np.testing.assert_array_equal(out["r_end"][:, c0:c0 + 6].cpu().numpy().astype(np.int32),
+                                      ref["r_end"][:, :min(6, M - c0)])
+        np.testing.assert_array_equal(out["log_w"][c0:c0 + 6].cpu().numpy(), ref["log_w"][:min(6, M - c0)])
+    del out
+    torch.cuda.empty_cache()
