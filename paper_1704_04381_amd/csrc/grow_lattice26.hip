@@ -267,28 +267,275 @@ __global__ __launch_bounds__(256) void grow_lattice26_batch(const GrowEntry *tab
     grow_lattice26_body<G, EXACT, CT>(tab[e].a, bid - block0[e], tab[e].H);
 }
 
+// Short chains (N <= 64): one lane per chain.  The lane's history sits in
+// LDS as one word per monomer, bytes (x + 64, y + 64, z + 64) plus 128 each
+// (coordinates stay within +-63), four monomers to a 16-byte group; group g
+// of lane L is entry g * T + L of the block's group array, so a wave reads
+// 1 KB of consecutive groups per ds_read_b128.  Unplaced entries hold the
+// sentinel 0x00808080 (raw coordinates -64, at least 2 from every tip).
+// Pair test of a stored word w against the tip word t (raw, unbiased):
+//   e  = (w - t) ^ 0x00808080       signed bytes (dx, dy, dz, 0), no borrow
+//   q  = dot4(e, e) = dx^2 + dy^2 + dz^2
+//   s1 = sad_u8(w, t + 0x00808080) + 1 = |dx| + |dy| + |dz| + 1
+//   code = dot4(e, (1, 3, 9, 0)) + 13;   occ |= sat(s1 - q) << code
+// nine operations with the two accumulator copies.  The counts n_m of the
+// steps with m free candidates are 8-bit fields in LDS (seven words per
+// lane); the r-th free code comes from the byte holding it and a 2 KB table
+// of the k-th set bit of every byte value.
+constexpr int kZ26LaneMax = 64;
+constexpr int kZ26LaneThreads = 256;
+constexpr uint32_t kZ26Bias = 0x00808080u;
+constexpr uint32_t kZ26LaneOrigin = 0x00404040u; // raw (64, 64, 64): the origin
+
+__host__ __device__ constexpr size_t z26_lane_shmem(int N, int T)
+{
+    return (size_t)((N + 3) / 4) * T * 16 + (size_t)7 * T * 4 + 32 * 4 + 2048;
+}
+
+__device__ __forceinline__ uint32_t z26_bits8(uint32_t w, uint32_t t, uint32_t tb)
+{
+    const uint32_t e = (w - t) ^ kZ26Bias;
+    const uint32_t q = (uint32_t)__builtin_amdgcn_sdot4((int)e, (int)e, 0, false);
+    const uint32_t s1 = __builtin_amdgcn_sad_u8(w, tb, 1u);
+    const int code = __builtin_amdgcn_sdot4((int)e, 0x00090301, 13, false);
+    return __builtin_elementwise_sub_sat(s1, q) << ((uint32_t)code & 31u);
+}
+
+// Index of the r-th (from 0) set bit of f, r < popcount(f) <= 27.
+__device__ __forceinline__ uint32_t z26_select(uint32_t f, uint32_t r, const uint8_t *sel)
+{
+    const uint32_t c0 = __builtin_popcount(f & 0xFFu);
+    const uint32_t c1 = __builtin_popcount(f & 0xFFFFu);
+    const uint32_t c2 = __builtin_popcount(f & 0xFFFFFFu);
+    uint32_t k = 0, before = 0;
+    if (r >= c0) { k = 8; before = c0; }
+    if (r >= c1) { k = 16; before = c1; }
+    if (r >= c2) { k = 24; before = c2; }
+    const uint32_t byte = (f >> k) & 0xFFu;
+    return k + sel[byte * 8 + (r - before)];
+}
+
+template <bool EXACT, typename CT>
+__device__ __forceinline__ void grow_lattice26_lane_body(const GrowArgs &a, uint64_t bid)
+{
+    constexpr int T = kZ26LaneThreads;
+    const int N = a.n_monomers;
+    const int NQ = (N + 3) >> 2;
+    extern __shared__ uint4 z26l_lds[];
+    uint4 *groups = z26l_lds;                                   // [NQ][T]
+    uint32_t *hist = (uint32_t *)(groups + (size_t)NQ * T);     // [7][T]
+    uint32_t *lut = hist + 7 * T;                               // [32]
+    uint8_t *sel = (uint8_t *)(lut + 32);                       // [256][8]
+    __shared__ double logm[27];
+    for (int q = threadIdx.x; q < 27; q += T) {
+        const int dx = q % 3, dy = (q / 3) % 3, dz = q / 9; // each + 1
+        lut[q] = (uint32_t)(dx | dy << 8 | dz << 16);
+        logm[q] = a.logm[q];
+    }
+    for (int q = threadIdx.x; q < 2048; q += T) {
+        const uint32_t byte = (uint32_t)q >> 3, k = (uint32_t)q & 7u;
+        uint32_t b = byte;
+        for (uint32_t j = 0; j < k && b; ++j) b &= b - 1u;
+        sel[q] = (uint8_t)(b ? __builtin_ctz(b) : 0);
+    }
+    const uint4 sent = {kZ26Bias, kZ26Bias, kZ26Bias, kZ26Bias};
+    for (int q = threadIdx.x; q < NQ * T; q += T) groups[q] = sent;
+    __syncthreads();
+
+    const int L = threadIdx.x;
+    const uint64_t c = bid * T + L;
+    const bool valid = c < a.n_chains;
+    const uint64_t g = a.chain_offset + c;
+    uint32_t *words = (uint32_t *)groups;
+    auto slot = [&](int j) -> uint32_t & { return words[(((size_t)(j >> 2) * T + L) << 2) + (j & 3)]; };
+
+    uint32_t tip = kZ26LaneOrigin;
+    bool alive = false;
+    int grown = 1;
+    uint64_t wx = 1;
+    bool rng_fail = false;
+    Philox4 blk{0, 0, 0, 0};
+    double res_lw = -__builtin_huge_val();
+    uint64_t res_wx = 0;
+    int64_t res_nn = 0;
+    int32_t res_ex = 0, res_ey = 0, res_ez = 0;
+    int res_grown = 1;
+    bool res_alive = false;
+    bool pending = valid;
+
+    for (uint32_t rd = 0; rd < a.max_rounds; ++rd) {
+        if (pending) {
+            if (rd > 0)
+                for (int q = 0; q < NQ; ++q) groups[(size_t)q * T + L] = sent;
+            for (int q = 0; q < 7; ++q) hist[q * T + L] = 0u;
+            tip = kZ26LaneOrigin;
+            slot(0) = tip + kZ26Bias;
+            wx = 1;
+        }
+        alive = pending;
+        grown = 1;
+        const uint32_t hi = rd << 16;
+
+        for (int i = 1; i < N; ++i) {
+            // monomers 0 .. i-2 in groups of four; the last group may also hold
+            // the tip (code 13, masked) and sentinels
+            const int ng = (i + 2) >> 2;
+            const uint32_t tb = tip + kZ26Bias;
+            uint32_t occ = 0, occ2 = 0;
+            for (int q = 0; q < ng; ++q) {
+                const uint4 w = groups[(size_t)q * T + L];
+                occ |= z26_bits8(w.x, tip, tb);
+                occ2 |= z26_bits8(w.y, tip, tb);
+                occ |= z26_bits8(w.z, tip, tb);
+                occ2 |= z26_bits8(w.w, tip, tb);
+            }
+            const uint32_t freem = ~(occ | occ2) & kZ26Codes;
+            const uint32_t m = __builtin_popcount(freem);
+
+            if (i == 1 || (i & 7) == 0) blk = draw(a.seed, g, (uint32_t)(i >> 3) | hi, kSlotSelect, 0);
+            const uint32_t x = half_word(blk, (uint32_t)(i & 7));
+            const uint32_t p = x * m;
+            uint32_t r = p >> 16;
+            if (__builtin_expect(alive && (p & 0xFFFFu) < m, 0)) {
+                r = lemire_redraw16(a.seed, g, (uint32_t)i | hi, m, x);
+                if (r == kPickFailed) {
+                    rng_fail = true;
+                    r = 0;
+                }
+            }
+            if (alive && m == 0) {
+                alive = false;
+                grown = i;
+            }
+            if (alive) {
+                const uint32_t code = z26_select(freem, r, sel);
+                tip = tip + lut[code] - 0x00010101u;
+                slot(i) = tip + kZ26Bias;
+                atomicAdd(&hist[(m >> 2) * T + L], 1u << ((m & 3u) * 8u));
+                if (EXACT) wx = wx * (uint64_t)m;
+            }
+        }
+        if (alive) grown = N;
+
+        if (pending && (alive || rd + 1 >= a.max_rounds)) {
+            // log W = sum over m = 1..26, ascending, of n_m log m
+            double lw = 0.0;
+            for (int mm = 1; mm <= 26; ++mm) {
+                const uint32_t nm = (hist[(mm >> 2) * T + L] >> ((mm & 3) * 8)) & 0xFFu;
+                lw = lw + (double)nm * logm[mm];
+            }
+            int32_t sx = 0, sy = 0, sz = 0, s2 = 0;
+            for (int j = 0; j < grown; ++j) {
+                const uint32_t w = slot(j) - kZ26Bias;
+                const int32_t xx = (int32_t)(w & 0xFFu) - 64;
+                const int32_t yy = (int32_t)((w >> 8) & 0xFFu) - 64;
+                const int32_t zz = (int32_t)((w >> 16) & 0xFFu) - 64;
+                sx += xx;
+                sy += yy;
+                sz += zz;
+                s2 += xx * xx + yy * yy + zz * zz;
+            }
+            const int64_t gg = grown;
+            res_nn = gg * (int64_t)s2 - ((int64_t)sx * sx + (int64_t)sy * sy + (int64_t)sz * sz);
+            res_ex = (int32_t)(tip & 0xFFu) - 64;
+            res_ey = (int32_t)((tip >> 8) & 0xFFu) - 64;
+            res_ez = (int32_t)((tip >> 16) & 0xFFu) - 64;
+            res_lw = alive ? lw : -__builtin_huge_val();
+            res_wx = alive ? wx : 0ull;
+            res_grown = grown;
+            res_alive = alive;
+            pending = false;
+        }
+        if (__ballot(pending) == 0) break;
+    }
+
+    if (valid) {
+        if (a.log_w) a.log_w[c] = res_lw;
+        if (EXACT && a.w_exact) a.w_exact[c] = res_wx;
+        if (a.r_end) {
+            CT *re = (CT *)a.r_end;
+            re[c] = (CT)res_ex;
+            re[a.n_chains + c] = (CT)res_ey;
+            re[2 * a.n_chains + c] = (CT)res_ez;
+        }
+        if (a.r2) a.r2[c] = (double)(res_ex * res_ex + res_ey * res_ey + res_ez * res_ez);
+        if (a.n2rg2) a.n2rg2[c] = res_nn;
+        if (a.rg2) a.rg2[c] = (double)res_nn / ((double)res_grown * (double)res_grown);
+        if (a.n_grown) a.n_grown[c] = (uint16_t)res_grown;
+    }
+    if (rng_fail) atomicExch(a.status, 6);
+    const uint64_t bits = res_alive ? (uint64_t)__double_as_longlong(res_lw) : 0ull;
+    const uint64_t wmax = wave_max_u64(bits);
+    if ((threadIdx.x & 63) == 0 && wmax != 0) atomicMax(a.log_w_max_bits, (unsigned long long)wmax);
+}
+
+template <bool EXACT, typename CT>
+__global__ __launch_bounds__(kZ26LaneThreads) void grow_lattice26_lane(GrowArgs a, uint64_t base)
+{
+    grow_lattice26_lane_body<EXACT, CT>(a, base + blockIdx.x);
+}
+
+template <bool EXACT, typename CT>
+__global__ __launch_bounds__(kZ26LaneThreads) void grow_lattice26_lane_batch(const GrowEntry *tab,
+                                                                            const uint64_t *block0, int n,
+                                                                            uint64_t base)
+{
+    const uint64_t bid = base + blockIdx.x;
+    const int e = find_segment(block0, n, bid);
+    grow_lattice26_lane_body<EXACT, CT>(tab[e].a, bid - block0[e]);
+}
+
 int lattice26_max_monomers() { return 16384; }
 
-// G = 32 lanes per chain up to N = 4096, 64 beyond; 256-thread blocks when
-// the block's planes fit in half a CU's LDS, else one wave.
+// One lane per chain up to N = 64 (and for exact weights, N <= 14); above,
+// G = 32 lanes per chain up to N = 4096 and 64 beyond, in 256-thread blocks
+// when the block's planes fit in half a CU's LDS, else in one wave.
 hipError_t lattice26_variant(const GrowArgs &a, bool exact, bool i16, GrowVariant *v)
 {
     const int N = a.n_monomers;
+    v->family = 3;
+    v->p1 = exact ? 1 : 0;
+    v->p2 = i16 ? 1 : 0;
+    v->S = 0;
+    if (N <= kZ26LaneMax) {
+        v->p0 = 1;
+        v->threads = kZ26LaneThreads;
+        v->cpb = kZ26LaneThreads;
+        v->shmem = z26_lane_shmem(N, kZ26LaneThreads);
+        v->H = 0;
+        return hipSuccess;
+    }
+    if (exact) return hipErrorInvalidValue;
     const int G = N <= 4096 ? 32 : 64;
     const int H = (N + 4 * G - 1) / (4 * G) * (4 * G);
     auto bytes = [&](int threads) { return ((size_t)64 + (size_t)(threads / G) * 2 * H) * sizeof(uint32_t); };
     const int threads = bytes(256) <= 81920 ? 256 : 64;
     if (bytes(threads) > 163840) return hipErrorInvalidValue;
-    v->family = 3;
     v->p0 = G;
-    v->p1 = exact ? 1 : 0;
-    v->p2 = i16 ? 1 : 0;
     v->threads = threads;
     v->cpb = threads / G;
     v->shmem = bytes(threads);
     v->H = H;
-    v->S = 0;
     return hipSuccess;
+}
+
+template <bool EXACT, typename CT>
+static hipError_t launch26_lane(const GrowArgs &a, const GrowVariant &v, const GrowEntry *tab,
+                                const uint64_t *block0, int n, uint64_t blocks, size_t shmem, hipStream_t s)
+{
+    const void *fn = tab ? (const void *)grow_lattice26_lane_batch<EXACT, CT>
+                         : (const void *)grow_lattice26_lane<EXACT, CT>;
+    if (shmem > 65536) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+        if (e != hipSuccess) return e;
+    }
+    return launch_sliced(blocks, v.threads, [&](uint64_t b0, uint32_t nb) {
+        if (tab)
+            hipLaunchKernelGGL((grow_lattice26_lane_batch<EXACT, CT>), dim3(nb), dim3(v.threads), shmem, s, tab,
+                               block0, n, b0);
+        else
+            hipLaunchKernelGGL((grow_lattice26_lane<EXACT, CT>), dim3(nb), dim3(v.threads), shmem, s, a, b0);
+    });
 }
 
 template <int G, bool EXACT, typename CT>
@@ -313,9 +560,13 @@ static hipError_t dispatch26(const GrowArgs &a, const GrowVariant &v, const Grow
                              int n, uint64_t blocks, size_t shmem, hipStream_t s)
 {
     const bool i16 = v.p2 != 0;
-    if (v.p1) // exact weights (N <= 14)
-        return i16 ? launch26<32, true, int16_t>(a, v, tab, block0, n, blocks, shmem, s)
-                   : launch26<32, true, int32_t>(a, v, tab, block0, n, blocks, shmem, s);
+    if (v.p0 == 1) {
+        if (v.p1)
+            return i16 ? launch26_lane<true, int16_t>(a, v, tab, block0, n, blocks, shmem, s)
+                       : launch26_lane<true, int32_t>(a, v, tab, block0, n, blocks, shmem, s);
+        return i16 ? launch26_lane<false, int16_t>(a, v, tab, block0, n, blocks, shmem, s)
+                   : launch26_lane<false, int32_t>(a, v, tab, block0, n, blocks, shmem, s);
+    }
     if (v.p0 == 32)
         return i16 ? launch26<32, false, int16_t>(a, v, tab, block0, n, blocks, shmem, s)
                    : launch26<32, false, int32_t>(a, v, tab, block0, n, blocks, shmem, s);
