@@ -4,11 +4,12 @@
 // 9 (dz + 1) (13, the tip itself, excluded); the growth rule and weight are
 // those of Algorithm 1 and Eq. 3 with m_i <= 26.
 //
-// G lanes per chain (32, or 64 for long chains), the history in LDS as two
-// words per monomer, A = (x + 2^15) | (y + 2^15) << 16 and B = z + 2^15,
-// in two planes of H words (monomer order; no bipartite pruning on this
-// lattice: a diagonal step keeps the parity).  Entries not yet placed hold
-// A = 0 (x = y = -2^15, far from every tip) and B = 2^15.  Pair test of monomer j against tip t:
+// Chains beyond N = 64: G lanes per chain (8 to 64, by N), the history in
+// LDS as two words per monomer, A = (x + 2^15) | (y + 2^15) << 16 and
+// B = z + 2^15, in two planes of H words (monomer order; no bipartite
+// pruning on this lattice: a diagonal step keeps the parity).  Entries not
+// yet placed hold A = 0 (x = y = -2^15, far from every tip) and B = 2^15.
+// Pair test of monomer j against tip t:
 //   (dx, dy) as packed 16-bit differences of the A words, dz = B_j - B_t
 //   q  = dx^2 + dy^2 + dz^2          (dot2 onto a 24-bit product)
 //   s  = |dx| + |dy| + |dz|          (two chained sad_u16 operations)
@@ -16,10 +17,11 @@
 //   (d^2 = |d| for |d| <= 1, d^2 >= |d| + 2 otherwise), so
 //   bit = sat((s + 1) - q) and code = dx + 3 dy + 9 dz + 13 (dot2 onto a
 //   24-bit multiply-add);  occ |= bit << code
-// ten operations per pair.  The G partial masks are OR-reduced across
-// the group; every lane then picks the same r-th free code (Lemire on the
-// same 16-bit words as the six-neighbour lattice); lane m - 1 counts the
-// steps with m free candidates for log W.
+// ten operations per pair.  The G partial masks are OR-reduced across the
+// group; every lane then picks the same r-th free code (Lemire on the same
+// 16-bit words as the six-neighbour lattice), and lane (m - 1) mod G counts
+// the steps with m free candidates for log W.  Short chains (N <= 64) use
+// the one-lane-per-chain kernel further down.
 #include "rsaw_device.hpp"
 
 namespace rsaw {
@@ -36,9 +38,9 @@ __device__ __forceinline__ uint32_t z26_group_or(uint32_t v)
 {
     v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
     v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
-    v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);
-    v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false);
-    {
+    if constexpr (G >= 8) v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);
+    if constexpr (G >= 16) v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false);
+    if constexpr (G >= 32) {
         const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
         v = p[0] | p[1];
     }
@@ -54,6 +56,7 @@ typedef short short2_t __attribute__((ext_vector_type(2)));
 constexpr uint32_t kZ26OriginA = 0x80008000u; // x = y = 0
 constexpr uint32_t kZ26OriginB = 0x00008000u; // z = 0 (also the B sentinel)
 constexpr uint32_t kZ26Codes = 0x7FFFFFFu & ~(1u << 13);
+constexpr int kZ26GroupHead = 64 + 512; // words before the chains: two move tables, select table
 
 __device__ __forceinline__ uint32_t z26_bits(uint32_t wa, uint32_t wb, uint32_t ta, uint32_t tb)
 {
@@ -71,14 +74,41 @@ __device__ __forceinline__ uint32_t z26_bits(uint32_t wa, uint32_t wb, uint32_t 
     return bit << ((uint32_t)code & 31u);
 }
 
+// Index of the r-th (from 0) set bit of f, r < popcount(f) <= 27: the byte
+// holding it from three prefix counts, then sel[byte][k], the index of the
+// k-th set bit of a byte value (a 2 KB table in LDS).
+__device__ __forceinline__ uint32_t z26_select(uint32_t f, uint32_t r, const uint8_t *sel)
+{
+    const uint32_t c0 = __builtin_popcount(f & 0xFFu);
+    const uint32_t c1 = __builtin_popcount(f & 0xFFFFu);
+    const uint32_t c2 = __builtin_popcount(f & 0xFFFFFFu);
+    uint32_t k = 0, before = 0;
+    if (r >= c0) { k = 8; before = c0; }
+    if (r >= c1) { k = 16; before = c1; }
+    if (r >= c2) { k = 24; before = c2; }
+    const uint32_t byte = (f >> k) & 0xFFu;
+    return k + sel[byte * 8 + (r - before)];
+}
+
+__device__ __forceinline__ void z26_fill_select_table(uint8_t *sel)
+{
+    for (int q = threadIdx.x; q < 2048; q += blockDim.x) {
+        const uint32_t byte = (uint32_t)q >> 3, k = (uint32_t)q & 7u;
+        uint32_t b = byte;
+        for (uint32_t j = 0; j < k && b; ++j) b &= b - 1u;
+        sel[q] = (uint8_t)(b ? __builtin_ctz(b) : 0);
+    }
+}
+
 template <int G, bool EXACT, typename CT>
 __device__ __forceinline__ void grow_lattice26_body(const GrowArgs &a, uint64_t bid, int H)
 {
     const int cpb = blockDim.x / G;
     extern __shared__ uint32_t z26_lds[];
-    uint32_t *lutA = z26_lds;        // [27] A-word move of each code
-    uint32_t *lutB = z26_lds + 32;   // [27] B-word move
-    uint32_t *chains = z26_lds + 64; // cpb chains of 2 H words
+    uint32_t *lutA = z26_lds;                    // [27] A-word move of each code
+    uint32_t *lutB = z26_lds + 32;               // [27] B-word move
+    uint8_t *sel = (uint8_t *)(z26_lds + 64);    // [256][8] select table
+    uint32_t *chains = z26_lds + kZ26GroupHead;  // cpb chains of 2 H words
     __shared__ double logm[27];
     for (int q = threadIdx.x; q < 27; q += blockDim.x) {
         const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = q / 9 - 1;
@@ -86,6 +116,7 @@ __device__ __forceinline__ void grow_lattice26_body(const GrowArgs &a, uint64_t 
         lutB[q] = (uint32_t)dz;
         logm[q] = a.logm[q];
     }
+    z26_fill_select_table(sel);
     for (int w = threadIdx.x; w < cpb * 2 * H; w += blockDim.x) chains[w] = (w / H) & 1 ? kZ26OriginB : 0u;
     __syncthreads();
 
@@ -103,7 +134,9 @@ __device__ __forceinline__ void grow_lattice26_body(const GrowArgs &a, uint64_t 
     uint32_t ta = 0, tb = 0;
     bool alive = false;
     int grown = 1;
-    uint32_t n_mine = 0; // steps with m = t + 1
+    // steps with m free candidates: lane t counts the m with (m - 1) mod G
+    // = t, in 16-bit fields at (m - 1) / G (one field for G >= 32)
+    uint64_t n_mine = 0;
     uint64_t wx = 1;
     bool rng_fail = false;
     Philox4 blk{0, 0, 0, 0};
@@ -139,16 +172,26 @@ __device__ __forceinline__ void grow_lattice26_body(const GrowArgs &a, uint64_t 
             const int nrel = i - 1;
             const int passes = (nrel + 4 * G - 1) / (4 * G);
             uint32_t occ = 0, occ2 = 0;
-            for (int q = 0; q < passes; ++q) {
-                const int kk = q * 4 * G + 4 * t;
-                const uint4 wa = *(const uint4 *)(PA + kk);
-                const uint4 wb = *(const uint4 *)(PB + kk);
-                // entries at nrel and beyond hold the sentinel (never a
-                // candidate) or the tip (code 13, masked below)
+            // two passes per iteration, so that the second pass's reads are in
+            // flight while the first is tested; entries at nrel and beyond hold
+            // the sentinel (never a candidate) or the tip (code 13, masked)
+            auto test4 = [&](const uint4 &wa, const uint4 &wb) {
                 occ |= z26_bits(wa.x, wb.x, ta, tb);
                 occ2 |= z26_bits(wa.y, wb.y, ta, tb);
                 occ |= z26_bits(wa.z, wb.z, ta, tb);
                 occ2 |= z26_bits(wa.w, wb.w, ta, tb);
+            };
+            int q = 0;
+            for (; q + 1 < passes; q += 2) {
+                const int k1 = q * 4 * G + 4 * t, k2 = k1 + 4 * G;
+                const uint4 a1 = *(const uint4 *)(PA + k1), b1 = *(const uint4 *)(PB + k1);
+                const uint4 a2 = *(const uint4 *)(PA + k2), b2 = *(const uint4 *)(PB + k2);
+                test4(a1, b1);
+                test4(a2, b2);
+            }
+            if (q < passes) {
+                const int k1 = q * 4 * G + 4 * t;
+                test4(*(const uint4 *)(PA + k1), *(const uint4 *)(PB + k1));
             }
             occ = z26_group_or<G>(occ | occ2);
             const uint32_t freem = ~occ & kZ26Codes;
@@ -159,16 +202,13 @@ __device__ __forceinline__ void grow_lattice26_body(const GrowArgs &a, uint64_t 
             const uint32_t p = x * m;
             uint32_t r = p >> 16;
             if (__builtin_expect(alive && (p & 0xFFFFu) < m, 0)) {
-                r = lemire_redraw16(a.seed, g, (uint32_t)i | hi, m, x);
+                r = lemire_redraw16_inline(a.seed, g, (uint32_t)i | hi, m, x);
                 if (r == kPickFailed) {
                     rng_fail = true;
                     r = 0;
                 }
             }
-            // the r-th free code
-            uint32_t msk = freem;
-            for (uint32_t q = 0; q < r; ++q) msk &= msk - 1u;
-            const uint32_t code = msk ? (uint32_t)__builtin_ctz(msk) : 13u;
+            const uint32_t code = m ? z26_select(freem, r, sel) : 13u; // the r-th free code
 
             const bool step_ok = alive && m != 0;
             if (alive && m == 0) {
@@ -178,7 +218,8 @@ __device__ __forceinline__ void grow_lattice26_body(const GrowArgs &a, uint64_t 
             if (step_ok) {
                 ta = ta + lutA[code];
                 tb = tb + lutB[code];
-                n_mine += (m == (uint32_t)t + 1u) ? 1u : 0u;
+                const uint32_t mm1 = m - 1u;
+                n_mine += (mm1 & (G - 1)) == (uint32_t)t ? 1ull << (16u * (mm1 / G)) : 0ull;
                 if (EXACT) wx = wx * (uint64_t)m;
                 if (t == 0) {
                     PA[i] = ta;
@@ -189,11 +230,15 @@ __device__ __forceinline__ void grow_lattice26_body(const GrowArgs &a, uint64_t 
         }
         if (alive) grown = N;
 
-        // log W = sum over m = 1..26, ascending, of n_m log m; n_m is held by
-        // lane m - 1 of the group
+        // log W = sum over m = 1..26, ascending, of n_m log m; n_m is field
+        // (m - 1) / G of lane (m - 1) mod G of the group
         double lw = 0.0;
+#pragma unroll 1
         for (int mm = 1; mm <= 26; ++mm) {
-            const uint32_t nm = __shfl(n_mine, gbase + mm - 1, 64);
+            const int f = (mm - 1) / G;
+            const uint32_t half = (uint32_t)(n_mine >> (32 * (f >> 1)));
+            const uint32_t v = (uint32_t)__shfl((int)half, gbase + ((mm - 1) & (G - 1)), 64);
+            const uint32_t nm = (v >> (16 * (f & 1))) & 0xFFFFu;
             lw = lw + (double)nm * logm[mm];
         }
         // observables over the placed monomers (integer sums: any order)
@@ -301,20 +346,6 @@ __device__ __forceinline__ uint32_t z26_bits8(uint32_t w, uint32_t t, uint32_t t
     return __builtin_elementwise_sub_sat(s1, q) << ((uint32_t)code & 31u);
 }
 
-// Index of the r-th (from 0) set bit of f, r < popcount(f) <= 27.
-__device__ __forceinline__ uint32_t z26_select(uint32_t f, uint32_t r, const uint8_t *sel)
-{
-    const uint32_t c0 = __builtin_popcount(f & 0xFFu);
-    const uint32_t c1 = __builtin_popcount(f & 0xFFFFu);
-    const uint32_t c2 = __builtin_popcount(f & 0xFFFFFFu);
-    uint32_t k = 0, before = 0;
-    if (r >= c0) { k = 8; before = c0; }
-    if (r >= c1) { k = 16; before = c1; }
-    if (r >= c2) { k = 24; before = c2; }
-    const uint32_t byte = (f >> k) & 0xFFu;
-    return k + sel[byte * 8 + (r - before)];
-}
-
 template <bool EXACT, typename CT>
 __device__ __forceinline__ void grow_lattice26_lane_body(const GrowArgs &a, uint64_t bid)
 {
@@ -332,12 +363,7 @@ __device__ __forceinline__ void grow_lattice26_lane_body(const GrowArgs &a, uint
         lut[q] = (uint32_t)(dx | dy << 8 | dz << 16);
         logm[q] = a.logm[q];
     }
-    for (int q = threadIdx.x; q < 2048; q += T) {
-        const uint32_t byte = (uint32_t)q >> 3, k = (uint32_t)q & 7u;
-        uint32_t b = byte;
-        for (uint32_t j = 0; j < k && b; ++j) b &= b - 1u;
-        sel[q] = (uint8_t)(b ? __builtin_ctz(b) : 0);
-    }
+    z26_fill_select_table(sel);
     const uint4 sent = {kZ26Bias, kZ26Bias, kZ26Bias, kZ26Bias};
     for (int q = threadIdx.x; q < NQ * T; q += T) groups[q] = sent;
     __syncthreads();
@@ -382,13 +408,20 @@ __device__ __forceinline__ void grow_lattice26_lane_body(const GrowArgs &a, uint
             const int ng = (i + 2) >> 2;
             const uint32_t tb = tip + kZ26Bias;
             uint32_t occ = 0, occ2 = 0;
-            for (int q = 0; q < ng; ++q) {
-                const uint4 w = groups[(size_t)q * T + L];
+            auto test4 = [&](const uint4 &w) {
                 occ |= z26_bits8(w.x, tip, tb);
                 occ2 |= z26_bits8(w.y, tip, tb);
                 occ |= z26_bits8(w.z, tip, tb);
                 occ2 |= z26_bits8(w.w, tip, tb);
+            };
+            int q = 0;
+            for (; q + 1 < ng; q += 2) { // two groups in flight, as in the group kernel
+                const uint4 w1 = groups[(size_t)q * T + L];
+                const uint4 w2 = groups[(size_t)(q + 1) * T + L];
+                test4(w1);
+                test4(w2);
             }
+            if (q < ng) test4(groups[(size_t)q * T + L]);
             const uint32_t freem = ~(occ | occ2) & kZ26Codes;
             const uint32_t m = __builtin_popcount(freem);
 
@@ -397,7 +430,7 @@ __device__ __forceinline__ void grow_lattice26_lane_body(const GrowArgs &a, uint
             const uint32_t p = x * m;
             uint32_t r = p >> 16;
             if (__builtin_expect(alive && (p & 0xFFFFu) < m, 0)) {
-                r = lemire_redraw16(a.seed, g, (uint32_t)i | hi, m, x);
+                r = lemire_redraw16_inline(a.seed, g, (uint32_t)i | hi, m, x);
                 if (r == kPickFailed) {
                     rng_fail = true;
                     r = 0;
@@ -420,6 +453,7 @@ __device__ __forceinline__ void grow_lattice26_lane_body(const GrowArgs &a, uint
         if (pending && (alive || rd + 1 >= a.max_rounds)) {
             // log W = sum over m = 1..26, ascending, of n_m log m
             double lw = 0.0;
+#pragma unroll 1
             for (int mm = 1; mm <= 26; ++mm) {
                 const uint32_t nm = (hist[(mm >> 2) * T + L] >> ((mm & 3) * 8)) & 0xFFu;
                 lw = lw + (double)nm * logm[mm];
@@ -488,8 +522,10 @@ __global__ __launch_bounds__(kZ26LaneThreads) void grow_lattice26_lane_batch(con
 int lattice26_max_monomers() { return 16384; }
 
 // One lane per chain up to N = 64 (and for exact weights, N <= 14); above,
-// G = 32 lanes per chain up to N = 4096 and 64 beyond, in 256-thread blocks
-// when the block's planes fit in half a CU's LDS, else in one wave.
+// G lanes per chain, G growing with N so that the chains a CU's LDS holds
+// still fill the CU (measured best widths): 8 up to N = 384, 16 up to 768,
+// 32 up to 1536, 64 beyond; 256-thread blocks when the block's planes fit in half a
+// CU's LDS, else one wave.
 hipError_t lattice26_variant(const GrowArgs &a, bool exact, bool i16, GrowVariant *v)
 {
     const int N = a.n_monomers;
@@ -506,9 +542,11 @@ hipError_t lattice26_variant(const GrowArgs &a, bool exact, bool i16, GrowVarian
         return hipSuccess;
     }
     if (exact) return hipErrorInvalidValue;
-    const int G = N <= 4096 ? 32 : 64;
+    const int G = N <= 384 ? 8 : (N <= 768 ? 16 : (N <= 1536 ? 32 : 64));
     const int H = (N + 4 * G - 1) / (4 * G) * (4 * G);
-    auto bytes = [&](int threads) { return ((size_t)64 + (size_t)(threads / G) * 2 * H) * sizeof(uint32_t); };
+    auto bytes = [&](int threads) {
+        return ((size_t)kZ26GroupHead + (size_t)(threads / G) * 2 * H) * sizeof(uint32_t);
+    };
     const int threads = bytes(256) <= 81920 ? 256 : 64;
     if (bytes(threads) > 163840) return hipErrorInvalidValue;
     v->p0 = G;
@@ -567,6 +605,12 @@ static hipError_t dispatch26(const GrowArgs &a, const GrowVariant &v, const Grow
         return i16 ? launch26_lane<false, int16_t>(a, v, tab, block0, n, blocks, shmem, s)
                    : launch26_lane<false, int32_t>(a, v, tab, block0, n, blocks, shmem, s);
     }
+    if (v.p0 == 8)
+        return i16 ? launch26<8, false, int16_t>(a, v, tab, block0, n, blocks, shmem, s)
+                   : launch26<8, false, int32_t>(a, v, tab, block0, n, blocks, shmem, s);
+    if (v.p0 == 16)
+        return i16 ? launch26<16, false, int16_t>(a, v, tab, block0, n, blocks, shmem, s)
+                   : launch26<16, false, int32_t>(a, v, tab, block0, n, blocks, shmem, s);
     if (v.p0 == 32)
         return i16 ? launch26<32, false, int16_t>(a, v, tab, block0, n, blocks, shmem, s)
                    : launch26<32, false, int32_t>(a, v, tab, block0, n, blocks, shmem, s);

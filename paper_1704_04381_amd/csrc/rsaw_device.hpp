@@ -69,8 +69,8 @@ __device__ __forceinline__ uint32_t half_word(const Philox4 &b, uint32_t h)
 // flag of the caller has its address taken (which would put it in scratch).
 constexpr uint32_t kPickFailed = 0xFFFFFFFFu;
 
-__device__ __noinline__ uint32_t lemire_redraw16(uint64_t seed, uint64_t g, uint32_t step,
-                                                 uint32_t m, uint32_t x)
+__device__ __forceinline__ uint32_t lemire_redraw16_inline(uint64_t seed, uint64_t g, uint32_t step,
+                                                           uint32_t m, uint32_t x)
 {
     const uint32_t threshold = 65536u % m;
     uint32_t p = x * m;
@@ -83,6 +83,15 @@ __device__ __noinline__ uint32_t lemire_redraw16(uint64_t seed, uint64_t g, uint
         }
     }
     return kPickFailed;
+}
+
+// The same as an out-of-line call: kernels whose live state across the rare
+// slow path is small keep it out of their code; the others inline it and
+// avoid the registers the call convention reserves.
+__device__ __noinline__ uint32_t lemire_redraw16(uint64_t seed, uint64_t g, uint32_t step,
+                                                 uint32_t m, uint32_t x)
+{
+    return lemire_redraw16_inline(seed, g, step, m, x);
 }
 
 // Wave-wide max of a 64-bit value (all 64 lanes must be active).
