@@ -5,7 +5,8 @@ A step is one pass of the whole path over one ensemble: grow every chain
 (weighted averages, c_n estimate, R^2 histogram).  The headline workload is
 the simple cubic lattice at N = 64 monomers, 10^7 chains, int16 coordinates,
 FP64 log-weights and a 256-bin histogram; the hard-sphere N = 64, k = 8,
-10^6-chain workload is reported beside it under "secondary", and a mixed
+10^6-chain workload is reported beside it under "secondary", the
+26-neighbour lattice at N = 64 and 10^7 chains under "variant", and a mixed
 batch of 256 ensembles (one batched call against per-ensemble calls) under
 "batch".
 
@@ -87,6 +88,18 @@ def real_alg_ops_per_chain(N: int, k: int) -> float:
     return tot
 
 
+def lattice26_alg_ops_per_chain(N: int) -> int:
+    """Algorithmic VALU lane-operations to grow one 26-neighbour lattice chain.
+
+    Per step i: the pair tests against monomers 0..i-2 (no parity pruning:
+    a diagonal step keeps the parity), 7 operations each (byte difference,
+    sign fix, squared distance, L1 distance, direction code, neighbour flag,
+    mask insert); 8 for the step's share of a Philox block; and 20 to count
+    the free codes, select the r-th, apply the move and tally m_i.
+    """
+    return sum(7 * max(i - 1, 0) + 8 + 20 for i in range(1, N))
+
+
 def _percentile(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -113,7 +126,7 @@ def run_gpu(w, steps, warmup, torch, rs):
     o = rs.rsaw_chain_out()
     o.log_w, o.r_end, o.r2, o.rg2, o.n_grown = (bufs[k].data_ptr() for k in
                                                   ("log_w", "r_end", "r2", "rg2", "n_grown"))
-    if w["geometry"] == "lattice":
+    if w["geometry"] != "real":
         bufs["n2rg2"] = torch.empty(M, dtype=torch.int64, device=dev)
         o.n2rg2 = bufs["n2rg2"].data_ptr()
     summ = torch.empty(rs.SUMMARY_BYTES, dtype=torch.uint8, device=dev)
@@ -307,6 +320,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="lattice_n64")
     ap.add_argument("--secondary", default="real_n64")
+    ap.add_argument("--variant", default="lattice26_n64",
+                    help="26-neighbour lattice workload reported under \"variant\" ('' to skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", action="store_true",
                     help="only run the serving benchmark (open-loop Poisson requests; about 2 minutes)")
@@ -418,6 +433,26 @@ def main():
                                      measured_traffic("grow_real_tp", "grow_real.hip", args.secondary)),
                          "kernel_ms": r2["grow_ms"], "alg_ops_per_launch": ops2},
             "physics": {k: r2["summary"][k] for k in ("n_alive", "log_c_est", "r2_mean",
+                                                      "r2_err", "rg2_mean", "rg2_err")},
+        }
+    if args.variant:
+        w3 = WORKLOADS[args.variant]
+        steps3 = max(3, args.steps // 4)
+        r3 = run_gpu(w3, steps3, 1, torch, rs)
+        T3 = sum(r3["lat"]) / 1e3
+        ops3 = lattice26_alg_ops_per_chain(w3["N"]) * w3["n_chains"]
+        ach3 = ops3 / (r3["grow_ms"] / 1e3) / 1e12
+        line["variant"] = {
+            "workload": args.variant, "value": w3["n_chains"] * (w3["N"] - 1) * steps3 / T3,
+            "unit": "monomer-steps/s", "steps": steps3, "ms_per_step": T3 * 1e3 / steps3,
+            "p50_ms": _percentile(r3["lat"], 0.5), "p99_ms": _percentile(r3["lat"], 0.99),
+            "roofline": {"bound": "alu", "achieved": ach3, "peak": VALU_PEAK_TOPS,
+                         "unit": "Tops/s", "frac": ach3 / VALU_PEAK_TOPS,
+                         "traffic": measured_traffic("grow_lattice26_lane", "grow_lattice26.hip",
+                                                     args.variant),
+                         "kernel": "grow_lattice26_lane",
+                         "kernel_ms": r3["grow_ms"], "alg_ops_per_launch": ops3},
+            "physics": {k: r3["summary"][k] for k in ("n_alive", "log_c_est", "r2_mean",
                                                       "r2_err", "rg2_mean", "rg2_err")},
         }
     if not args.no_batch:

@@ -20,6 +20,10 @@ WORKLOADS = {
     # directions, 10^6 chains, FP64.
     "real_n64": dict(geometry="real", N=64, k=8, n_chains=1_000_000, seed=1,
                      coord="f64", bond_length=1.0, bead_diameter=1.0, hist_bins=256),
+    # 26-neighbour lattice variant (Sec. 3.3.2), N = 64, 10^7 chains, int16
+    # coordinates, FP64 log W, 256-bin histogram.
+    "lattice26_n64": dict(geometry="lattice26", N=64, k=26, n_chains=10_000_000, seed=1,
+                          coord="i16", exact_w=False, hist_bins=256),
 }
 
 

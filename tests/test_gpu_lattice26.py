@@ -132,3 +132,36 @@ def test_grid_slices_cover_every_chain():
         np.testing.assert_array_equal(out["log_w"][c0:c0 + 6].cpu().numpy(), ref["log_w"][:min(6, M - c0)])
     del out
     torch.cuda.empty_cache()
+
+
+def test_workload_lattice26_n64_sampled():
+    """The benchmarked workload (N = 64, 10^7 chains, int16, 256 bins) in the
+    launch configuration the benchmark times: sampled chains against the
+    oracle one by one, and the full reduction against the oracle's reduction
+    of the same per-chain outputs."""
+    from paper_1704_04381_amd.workloads import WORKLOADS
+
+    w = WORKLOADS["lattice26_n64"]
+    M, N = w["n_chains"], w["N"]
+    print(f"[gpu] lattice26 workload N={N} M={M}", flush=True)
+    out, s = rs.gen_chains(w["geometry"], N, w["k"], M, w["seed"], coord=w["coord"],
+                           hist_bins=w["hist_bins"])
+    torch.cuda.synchronize()
+    out = {n: t.cpu().numpy() for n, t in out.items()}
+    rng = np.random.default_rng(97)
+    idx = np.unique(np.concatenate([np.arange(0, M, M // 1000), rng.integers(0, M, 1000), [M - 1]]))
+    for c in idx:
+        ch = oracle.lattice_chain(w["seed"], int(c), N, z26=True)
+        assert out["log_w"][c] == ch["log_w"]
+        assert int(out["n_grown"].view(np.uint16)[c]) == ch["n_grown"]
+        assert tuple(int(v) for v in out["r_end"][:, c]) == tuple(int(v) for v in ch["end"])
+        assert out["n2rg2"][c] == ch["n2rg2"]
+        assert out["rg2"][c] == ch["rg2"]
+    red = oracle.reduce(N, out["log_w"], out["r2"], out["rg2"],
+                        out["n_grown"].view(np.uint16).astype(np.int32), bins=w["hist_bins"])
+    assert s["status"] == 0 and s["n_alive"] == red["alive"] and s["steps"] == red["steps"]
+    assert s["log_w_max"] == red["log_w_max"]
+    for key in ("sum_w", "sum_w2", "sum_w_r2", "sum_w_rg2", "log_c_est", "r2_mean", "rg2_mean", "ess"):
+        assert abs(s[key] - red[key]) <= RTOL_SUM * abs(red[key]), (key, s[key], red[key])
+    np.testing.assert_array_equal(out["hist_n"], red["hist_n"])
+    np.testing.assert_allclose(out["hist_w"], red["hist_w"], rtol=RTOL_SUM, atol=0)
