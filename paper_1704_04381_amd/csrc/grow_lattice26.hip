@@ -135,7 +135,9 @@ __device__ __forceinline__ void grow_lattice26_body(const GrowArgs &a, uint64_t 
     bool alive = false;
     int grown = 1;
     // steps with m free candidates: lane t counts the m with (m - 1) mod G
-    // = t, in 16-bit fields at (m - 1) / G (one field for G >= 32)
+    // = t, in FW-bit fields at (m - 1) / G (one field for G >= 32; 8-bit
+    // fields for G = 4, whose seven fields need N <= 256)
+    constexpr uint32_t FW = G >= 8 ? 16u : 8u;
     uint64_t n_mine = 0;
     uint64_t wx = 1;
     bool rng_fail = false;
@@ -219,7 +221,7 @@ __device__ __forceinline__ void grow_lattice26_body(const GrowArgs &a, uint64_t 
                 ta = ta + lutA[code];
                 tb = tb + lutB[code];
                 const uint32_t mm1 = m - 1u;
-                n_mine += (mm1 & (G - 1)) == (uint32_t)t ? 1ull << (16u * (mm1 / G)) : 0ull;
+                n_mine += (mm1 & (G - 1)) == (uint32_t)t ? 1ull << (FW * (mm1 / G)) : 0ull;
                 if (EXACT) wx = wx * (uint64_t)m;
                 if (t == 0) {
                     PA[i] = ta;
@@ -235,10 +237,11 @@ __device__ __forceinline__ void grow_lattice26_body(const GrowArgs &a, uint64_t 
         double lw = 0.0;
 #pragma unroll 1
         for (int mm = 1; mm <= 26; ++mm) {
-            const int f = (mm - 1) / G;
-            const uint32_t half = (uint32_t)(n_mine >> (32 * (f >> 1)));
+            const int f = (mm - 1) / G;                    // field index
+            const int per = 32 / (int)FW;                     // fields per 32-bit half
+            const uint32_t half = (uint32_t)(n_mine >> (32 * (f / per)));
             const uint32_t v = (uint32_t)__shfl((int)half, gbase + ((mm - 1) & (G - 1)), 64);
-            const uint32_t nm = (v >> (16 * (f & 1))) & 0xFFFFu;
+            const uint32_t nm = (v >> (FW * (uint32_t)(f % per))) & ((1u << FW) - 1u);
             lw = lw + (double)nm * logm[mm];
         }
         // observables over the placed monomers (integer sums: any order)
@@ -523,8 +526,9 @@ int lattice26_max_monomers() { return 16384; }
 
 // One lane per chain up to N = 64 (and for exact weights, N <= 14); above,
 // G lanes per chain, G growing with N so that the chains a CU's LDS holds
-// still fill the CU (measured best widths): 8 up to N = 384, 16 up to 768,
-// 32 up to 1536, 64 beyond; 256-thread blocks when the block's planes fit in half a
+// still fill the CU (measured best widths): 4 up to N = 160 (whose 8-bit
+// n_m fields need N <= 256), 8 up to 384, 16 up to 768, 32 up to 1536, 64
+// beyond; 256-thread blocks when the block's planes fit in half a
 // CU's LDS, else one wave.
 hipError_t lattice26_variant(const GrowArgs &a, bool exact, bool i16, GrowVariant *v)
 {
@@ -542,7 +546,7 @@ hipError_t lattice26_variant(const GrowArgs &a, bool exact, bool i16, GrowVarian
         return hipSuccess;
     }
     if (exact) return hipErrorInvalidValue;
-    const int G = N <= 384 ? 8 : (N <= 768 ? 16 : (N <= 1536 ? 32 : 64));
+    const int G = N <= 160 ? 4 : (N <= 384 ? 8 : (N <= 768 ? 16 : (N <= 1536 ? 32 : 64)));
     const int H = (N + 4 * G - 1) / (4 * G) * (4 * G);
     auto bytes = [&](int threads) {
         return ((size_t)kZ26GroupHead + (size_t)(threads / G) * 2 * H) * sizeof(uint32_t);
@@ -605,6 +609,9 @@ static hipError_t dispatch26(const GrowArgs &a, const GrowVariant &v, const Grow
         return i16 ? launch26_lane<false, int16_t>(a, v, tab, block0, n, blocks, shmem, s)
                    : launch26_lane<false, int32_t>(a, v, tab, block0, n, blocks, shmem, s);
     }
+    if (v.p0 == 4)
+        return i16 ? launch26<4, false, int16_t>(a, v, tab, block0, n, blocks, shmem, s)
+                   : launch26<4, false, int32_t>(a, v, tab, block0, n, blocks, shmem, s);
     if (v.p0 == 8)
         return i16 ? launch26<8, false, int16_t>(a, v, tab, block0, n, blocks, shmem, s)
                    : launch26<8, false, int32_t>(a, v, tab, block0, n, blocks, shmem, s);

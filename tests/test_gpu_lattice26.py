@@ -1,9 +1,10 @@
 """Parity of the 26-neighbour lattice kernel (RSAW_LATTICE_26, the z = 26
 lattice space of Sec. 3.3.2) with the oracle, bit for bit: log W, exact W,
 end vector, R^2, g^2 Rg^2, Rg^2 and monomers placed per chain, and the
-ensemble summary and histogram.  Sizes cover one and several 128-monomer
-scan passes, the switch from 32 to 64 lanes per chain above N = 4096, the
-largest N, and ragged chain counts over 256-thread blocks.
+ensemble summary and histogram.  Sizes cover both kernels (one lane per
+chain up to N = 64, G = 4, 8, 16, 32 and 64 lanes per chain beyond), one
+and several scan passes, the largest N, and ragged chain counts over
+256-thread blocks.
 
 Dead ends are too rare on this lattice to appear in test-sized ensembles
 (none in 10^4 chains of N <= 3000 in the oracle), so the dead-end and
@@ -62,7 +63,7 @@ def _case(N, M, seed, coord="i32", exact_w=False, bins=0, offset=0, restart=Fals
 @pytest.mark.parametrize("N,M,seed,coord", [
     (1, 300, 1, "i32"), (2, 257, 2, "i16"), (3, 1_000, 3, "i32"), (5, 999, 4, "i16"),
     (16, 5_000, 5, "i32"), (64, 20_000, 6, "i16"), (100, 3_001, 7, "i32"),
-    (129, 1_000, 8, "i16"), (300, 700, 9, "i32")])
+    (129, 1_000, 8, "i16"), (161, 500, 10, "i16"), (300, 700, 9, "i32"), (600, 200, 14, "i16")])
 def test_lattice26_bit_exact(N, M, seed, coord):
     _case(N, M, seed, coord=coord, bins=256 if N > 1 else 0)
 
