@@ -112,7 +112,8 @@ __device__ __forceinline__ void grow_real_body(const GrowArgs &a, uint64_t bid, 
     for (int t = threadIdx.x; t < 65; t += blockDim.x) logm[t] = a.logm[t];
 
     const int cpb = blockDim.x / G;
-    const int row = plane_row(cpb, G);
+    // wave-uniform: bead offsets of uniform bead indices stay scalar
+    const int row = __builtin_amdgcn_readfirstlane(plane_row(cpb, G));
     const int swz_mul = G == 64 ? 0 : 32 / G;
     const int swz_mask = cpb - 1;
     const int N = a.n_monomers;
@@ -124,8 +125,12 @@ __device__ __forceinline__ void grow_real_body(const GrowArgs &a, uint64_t bid, 
     const int chb = threadIdx.x / G;
     const int lane = threadIdx.x & 63;
     const int gbase = lane & ~(G - 1);
-    // element of bead j of this chain in a plane
+    // element of bead j of this chain in a plane; at_t(b0) is at(b0 + t) for
+    // a wave-uniform b0 (b0 row scalar, t row computed once)
     const auto at = [&](int j) { return j * row + (chb ^ ((j * swz_mul) & swz_mask)); };
+    int trow = t * row;
+    asm volatile("" : "+v"(trow)); // keeps b0 row + t row from being re-fused into a vector multiply
+    const auto at_t = [&](int b0) { return b0 * row + trow + (chb ^ (((b0 + t) * swz_mul) & swz_mask)); };
     const uint64_t gmask_bits = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
     const uint64_t c = bid * cpb + chb;
     const bool valid = c < a.n_chains;
@@ -240,8 +245,7 @@ __device__ __forceinline__ void grow_real_body(const GrowArgs &a, uint64_t bid, 
                 d2 = d2 + dz * dz;
                 blocked = blocked | (d2 < sigma2);
             };
-            const auto is_near = [&](int j) {
-                const int o = at(j);
+            const auto is_near_at = [&](int o) {
                 const double dx = X[o] - tx, dy = Y[o] - ty, dz = Z[o] - tz;
                 double d2 = dx * dx + dy * dy;
                 d2 = d2 + dz * dz;
@@ -250,6 +254,7 @@ __device__ __forceinline__ void grow_real_body(const GrowArgs &a, uint64_t bid, 
             if (i >= 2) test_bead(i - 2);
             if (i >= 3) test_bead(i - 3);
             const int nb = __builtin_amdgcn_readfirstlane(i - 3);
+            const int o_last = nb > 0 ? at(nb - 1) : 0; // in-plane offset for lanes past nb
             for (int b0 = 0; b0 < nb; b0 += 2 * G) {
                 // two blocks of G beads per pass, lane t taking bead b0 + t and
                 // b0 + G + t; the offsets flagged by any chain of the wave are
@@ -257,8 +262,8 @@ __device__ __forceinline__ void grow_real_body(const GrowArgs &a, uint64_t bid, 
                 // overlap, so testing it again changes nothing)
                 // (indices clamped so that both loads issue unconditionally)
                 const int j0 = b0 + t, j1 = b0 + G + t;
-                const bool d0 = is_near(j0 < nb ? j0 : nb - 1);
-                const bool d1 = is_near(j1 < nb ? j1 : nb - 1);
+                const bool d0 = is_near_at(j0 < nb ? at_t(b0) : o_last);
+                const bool d1 = is_near_at(j1 < nb ? at_t(b0 + G) : o_last);
                 const bool n0 = alive & (j0 < nb) & d0;
                 const bool n1 = alive & (j1 < nb) & d1;
                 uint64_t u0 = fold_groups<G>(__ballot(n0));
