@@ -42,14 +42,26 @@
 
 namespace rsaw {
 
+// Uniform on [-1, 1) from the 53-bit integer j = (a >> 5) 2^26 + (b >> 6):
+// (j - 2^52) 2^-52, built from bits rather than converted.  With m the low
+// 52 bits of j, d = 1 + m 2^-52 is a double of exponent 0, and the result is
+// d - 1 when bit 52 of j (bit 31 of a) is set, else d - 2; both
+// subtractions are exact (Sterbenz), so the value is the same double.
+__device__ __forceinline__ double uniform53(uint32_t a, uint32_t b)
+{
+    const uint32_t lo = __builtin_amdgcn_alignbit(a >> 5, b, 6); // m bits 0..31
+    const uint32_t h = a >> 11;
+    const uint32_t hi = (h & 0xFFFFFu) | 0x3FF00000u;           // m bits 32..51, exponent 0
+    const uint32_t chi = 0x40000000u - (h & 0x100000u);         // 2.0, or 1.0 for bit 52
+    return __hiloint2double((int)hi, (int)lo) - __hiloint2double((int)chi, 0);
+}
+
 // One Marsaglia attempt from a Philox block: two 53-bit uniforms on [-1, 1)
 // and acceptance of the pair strictly inside the unit disc, off its centre.
 __device__ __forceinline__ bool marsaglia_try(const Philox4 q, double &v1, double &v2, double &s)
 {
-    const int64_t j1 = ((int64_t)(q.x0 >> 5) << 26) + (int64_t)(q.x1 >> 6);
-    const int64_t j2 = ((int64_t)(q.x2 >> 5) << 26) + (int64_t)(q.x3 >> 6);
-    const double u1 = (double)(j1 - (1ll << 52)) * 0x1p-52;
-    const double u2 = (double)(j2 - (1ll << 52)) * 0x1p-52;
+    const double u1 = uniform53(q.x0, q.x1);
+    const double u2 = uniform53(q.x2, q.x3);
     const double ss = u1 * u1 + u2 * u2;
     if (ss < 1.0 && ss != 0.0) {
         v1 = u1; v2 = u2; s = ss;
