@@ -306,6 +306,27 @@ rsaw_status rsaw_kernel_timing(int32_t enable);
  */
 rsaw_status rsaw_kernel_time(double *total_ms, uint64_t *launches);
 
+/*
+ * rsaw_workspace_size — device bytes of library workspace that
+ * rsaw_gen_chains(cfg, out, ...) needs on its stream: the reduction cells,
+ * block partials and histogram accumulators (Eqs. 2 and 6), the per-chain
+ * arrays the reduction reads that `out` does not supply (26 B per chain
+ * with no outputs), and the HBM bead planes of hard-sphere chains beyond
+ * the LDS limit (3 N doubles per resident block, at most 2048 blocks).
+ *
+ *   cfg     the configuration (validated as by rsaw_gen_chains).
+ *   out     the per-chain outputs the call will pass (NULL = none).
+ *   reduce  nonzero when the call reduces (a summary or a histogram).
+ *   bytes   receives the size (host).
+ *
+ * A pure query: no allocation and no device call.  A stream's workspace
+ * grows to the largest need seen (at least 1 MiB) and is then reused.
+ * Errors: those of rsaw_gen_chains's validation; RSAW_E_INVALID for a NULL
+ * `bytes`.
+ */
+rsaw_status rsaw_workspace_size(const rsaw_config *cfg, const rsaw_chain_out *out, int32_t reduce,
+                                size_t *bytes);
+
 /* Release the internal device workspace of every device and the timing
  * events (safe to call repeatedly; later calls re-create them on demand). */
 void rsaw_shutdown(void);

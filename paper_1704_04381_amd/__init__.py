@@ -67,7 +67,7 @@ EXPORTS = ["rsaw_gen_chains", "rsaw_gen_chains_sync", "rsaw_gen_batch", "rsaw_se
            "rsaw_server_submit", "rsaw_server_poll", "rsaw_server_wait", "rsaw_server_destroy",
            "rsaw_status_string",
            "rsaw_last_error", "rsaw_version", "rsaw_kernel_timing", "rsaw_kernel_time",
-           "rsaw_shutdown"]
+           "rsaw_workspace_size", "rsaw_shutdown"]
 
 _lib = None
 _lock = threading.Lock()
@@ -122,6 +122,9 @@ def load(path: str = LIB_PATH):
         lib.rsaw_kernel_time.restype = C.c_int
         lib.rsaw_shutdown.argtypes = []
         lib.rsaw_shutdown.restype = None
+        lib.rsaw_workspace_size.argtypes = [C.POINTER(rsaw_config), C.POINTER(rsaw_chain_out), C.c_int32,
+                                            C.POINTER(C.c_size_t)]
+        lib.rsaw_workspace_size.restype = C.c_int
         _lib = lib
         return lib
 
@@ -362,3 +365,12 @@ def kernel_time() -> tuple[float, int]:
 
 def shutdown():
     load().rsaw_shutdown()
+
+
+def workspace_size(cfg: rsaw_config, out: rsaw_chain_out | None = None, reduce: bool = True) -> int:
+    """Device workspace bytes an rsaw_gen_chains call with these arguments
+    needs (rsaw_workspace_size; a host-only query)."""
+    n = C.c_size_t(0)
+    _check(load().rsaw_workspace_size(C.byref(cfg), C.byref(out) if out is not None else None,
+                                      1 if reduce else 0, C.byref(n)))
+    return n.value

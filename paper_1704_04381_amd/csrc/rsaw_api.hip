@@ -674,6 +674,22 @@ rsaw_status rsaw_kernel_time(double *total_ms, uint64_t *launches)
     return st;
 }
 
+rsaw_status rsaw_workspace_size(const rsaw_config *cfg, const rsaw_chain_out *out, int32_t reduce,
+                                size_t *bytes)
+{
+    g_last_error.clear();
+    if (!bytes) return fail(RSAW_E_INVALID, "bytes is NULL");
+    const rsaw_status st = validate(cfg);
+    if (st != RSAW_OK) return st;
+    rsaw_chain_out in{};
+    if (out) in = *out;
+    EnsLayout L;
+    size_t off = 0;
+    layout_ensemble(cfg, in, reduce != 0, &off, &L);
+    *bytes = off;
+    return RSAW_OK;
+}
+
 void rsaw_shutdown(void)
 {
     {

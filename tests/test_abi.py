@@ -134,3 +134,30 @@ def test_product_package_never_touches_the_oracle():
                 txt = open(os.path.join(root, f)).read()
                 assert not re.search(r"^\s*(import|from)\s+oracle\b|rsaw_oracle|\boro_|"
                                      r"import_module\(.oracle", txt, re.M), f
+
+
+def test_workspace_size_query_on_host():
+    """rsaw_workspace_size is host-only: it needs no GPU and reports the
+    per-chain reduction arrays (26 B per chain) unless the caller supplies
+    them, the small fixed cells, and the HBM bead planes of long hard-sphere
+    chains (3 N doubles per resident block, at most 2048 blocks)."""
+    import ctypes as C
+
+    M = 10**7
+    cfg = rs.make_config("lattice", 64, 6, M, 1, coord="i16", hist_bins=256)
+    full = rs.workspace_size(cfg)
+    assert 26 * M <= full <= 26 * M + (1 << 20)
+    o = rs.rsaw_chain_out()
+    o.log_w = o.r2 = o.rg2 = o.n_grown = 1  # any non-NULL address: not dereferenced
+    supplied = rs.workspace_size(cfg, o)
+    assert supplied < (1 << 20) and full - supplied >= 26 * M
+    assert rs.workspace_size(cfg, None, reduce=False) < (1 << 18)  # fixed cells and block partials
+    real = rs.workspace_size(rs.make_config("real", 2000, 8, 5000, 1), None, reduce=False)
+    assert 2048 * 3 * 2000 * 8 <= real <= 2048 * 3 * 2000 * 8 + (1 << 18)
+    small = rs.workspace_size(rs.make_config("real", 1536, 8, 5000, 1), None, reduce=False)
+    assert small < (1 << 18)  # LDS planes up to N = 1536
+    with pytest.raises(rs.RsawError) as e:
+        rs.workspace_size(rs.make_config("lattice26", 16, 6, 10, 1))
+    assert e.value.status == 1
+    lib = rs.load()
+    assert lib.rsaw_workspace_size(C.byref(cfg), None, 1, None) == 1
