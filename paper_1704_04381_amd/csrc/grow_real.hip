@@ -432,7 +432,9 @@ uint32_t real_hbm_slots(int n_monomers, uint64_t n_chains)
 // lane), and enough that the chains whose planes fit in a CU's LDS still
 // fill about 8 waves (G >= 0.075 N); the extra lanes share the culling pass.
 // 256-thread blocks when the bead planes fit in half a CU's LDS, else one
-// wave per block (up to the whole 160 KiB).
+// wave per block (up to the whole 160 KiB).  G = 64 always runs one-wave
+// blocks: four one-chain waves sharing a block's padded planes were measured
+// 1.2-2.3x slower for 432 <= N <= 672 (k = 8) than four one-wave blocks.
 hipError_t real_variant(const GrowArgs &a, GrowVariant *v)
 {
     const int N = a.n_monomers;
@@ -456,7 +458,7 @@ hipError_t real_variant(const GrowArgs &a, GrowVariant *v)
     auto planes = [&](int threads) {
         return (size_t)3 * N * plane_row(threads / G, G) * sizeof(double);
     };
-    int threads = 256;
+    int threads = G == 64 ? 64 : 256;
     if (planes(threads) > 81920) threads = 64;
     if (planes(threads) + 65 * sizeof(double) > 163840) return hipErrorInvalidValue;
     v->family = 2;

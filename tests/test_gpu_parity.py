@@ -156,12 +156,12 @@ def test_real_parity(N, k, M, seed):
 
 
 @pytest.mark.parametrize("N,k,M,seed,sigma", [
-    # one wave per chain: 256-thread blocks up to N = 682, one-wave blocks
-    # (LDS planes beyond 64 KiB) up to the largest N
-    (300, 8, 64, 41, 1.0), (700, 8, 24, 42, 1.0), (700, 16, 12, 43, 0.8),
-    (2_048, 8, 6, 44, 0.5), (6_144, 8, 3, 45, 0.5),
+    # LDS planes: 32 lanes per chain in 256-thread blocks (N = 300), one
+    # wave per chain in one-wave blocks from N = 427 to the LDS limit 1536
+    (300, 8, 64, 41, 1.0), (460, 8, 40, 49, 1.0), (512, 16, 20, 50, 0.8),
+    (700, 8, 24, 42, 1.0), (700, 16, 12, 43, 0.8), (1_536, 8, 6, 51, 0.5),
     # HBM-resident planes beyond the LDS limit (persistent grid)
-    (6_145, 8, 3, 46, 0.5), (10_000, 8, 3, 47, 0.4), (16_384, 16, 2, 48, 0.4)])
+    (2_048, 8, 6, 44, 0.5), (6_144, 8, 3, 45, 0.5), (6_145, 8, 3, 46, 0.5), (10_000, 8, 3, 47, 0.4), (16_384, 16, 2, 48, 0.4)])
 def test_real_long_chains(N, k, M, seed, sigma):
     _, _, exact = _real_case(N, k, M, seed, sigma=sigma, bins=64)
     assert exact
