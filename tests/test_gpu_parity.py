@@ -149,7 +149,10 @@ def _real_case(N, k, M, seed, b=1.0, sigma=1.0, bins=0, offset=0, restart=False)
                                         # one-wave blocks (bead planes above 64 KiB at
                                         # 256 threads) up to the largest N
                                         (100, 8, 403, 11), (256, 8, 77, 12), (200, 16, 101, 13),
-                                        (150, 33, 65, 14), (256, 64, 21, 15)])
+                                        (150, 33, 65, 14), (256, 64, 21, 15),
+                                        # round-1 draws spread over spare lanes
+                                        # (G >= 4k), k not dividing G
+                                        (300, 5, 90, 16), (600, 7, 30, 17), (480, 3, 40, 18)])
 def test_real_parity(N, k, M, seed):
     _, _, exact = _real_case(N, k, M, seed, bins=128)
     assert exact
