@@ -230,6 +230,23 @@ def run_batch(torch, rs, reps, m_lo=3.0, m_span=3.0):
         t_p.append(a2.elapsed_time(b2))
         per.extend(x.elapsed_time(y) for x, y in evs)
     tb, tp = _percentile(t_b, 0.5), _percentile(t_p, 0.5)
+    # the same batch after the autotuner has picked the lane mapping of each
+    # (geometry, k, N bucket) of the workload
+    t0 = time.perf_counter()
+    tuning = tune_mixed(rs)
+    tune_s = time.perf_counter() - t0
+    batched()
+    torch.cuda.synchronize()
+    t_t = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        batched()
+        b.record(stream)
+        torch.cuda.synchronize()
+        t_t.append(a.elapsed_time(b))
+    rs.mapping_clear()
+    tt = _percentile(t_t, 0.5)
     return {
         "workload": f"mixed_256 (N = 8..128, lattice k = 6 / hard spheres k = 8, 16, "
                     f"10^{m_lo:g}..10^{m_lo + m_span:g} chains each)",
@@ -239,7 +256,29 @@ def run_batch(torch, rs, reps, m_lo=3.0, m_span=3.0):
         "unit": "monomer-steps/s", "speedup": tp / tb, "reps": reps,
         "plain_ensemble_p50_ms": _percentile(per, 0.5), "plain_ensemble_p99_ms": _percentile(per, 0.99),
         "batched_ensemble_latency_ms": tb,
+        "tuned_batched_ms": tt, "tuned_batched_value": steps / (tt / 1e3), "tuned_speedup": tp / tt,
+        "autotune_s": tune_s, "tuned_mappings": tuning,
     }
+
+
+# Buckets of the mixed workload (N = 8..128) that have a group kernel: the
+# lattice above N = 64, hard spheres at every N, each k separately.
+TUNE_BUCKETS = (("lattice", 6, (96, 128), 1 << 17),
+                ("real", 8, (32, 64, 96, 128), 1 << 15),
+                ("real", 16, (32, 64, 96, 128), 1 << 15))
+
+
+def tune_mixed(rs):
+    """Autotune the lane mapping for the mixed workload's buckets; returns
+    the chosen (geometry, k, N range, lanes, threads, ms) per bucket."""
+    out = []
+    for geo, k, edges, m in TUNE_BUCKETS:
+        lo = 65 if geo == "lattice" else 1
+        res = rs.autotune(geo, k, edges, m, reps=3)
+        for r in res:
+            out.append({"geometry": geo, "k": k, "n_lo": max(lo, r["n_lo"]), "n_hi": r["n_hi"],
+                        "lanes": r["lanes"], "threads": r["threads"], "ms": r["ms"]})
+    return out
 
 
 def run_serving(rs, rate, n, warmup, streams=2, max_batch=64, m_lo=4.0, m_span=3.0):
@@ -358,16 +397,24 @@ def main():
         out = {"metric": "serving: Poisson requests (N = 16..256, lattice / hard spheres, 10^4..10^7 "
                          "chains each), latency p50/p99 and throughput", "unit": "ms / monomer-steps/s",
                "runs": []}
-        for rate, n, warm in ((200.0, 2100, 100), (20.0, 300, 30), (5.0, 150, 15)):
+        rates = ((200.0, 2100, 100), (20.0, 300, 30), (5.0, 150, 15))
+        for rate, n, warm in rates:
             print(f"[serve] rate {rate}/s, {n} requests", file=sys.stderr, flush=True)
             out["runs"].append(run_serving(rs, rate, n, warm))
+        # the same traces served by per-request plain launches: one stream,
+        # one request per launch, in arrival order
+        out["plain_runs"] = []
+        for rate, n, warm in rates:
+            print(f"[serve] plain launches, rate {rate}/s, {n} requests", file=sys.stderr, flush=True)
+            out["plain_runs"].append(run_serving(rs, rate, n, warm, streams=1, max_batch=1))
         # the 200/s run is overloaded: its throughput is the capacity, and
         # rho = offered work / capacity for every run
         from paper_1704_04381_amd.workloads import serving_requests
 
         cap = out["runs"][0]["throughput_steps_per_s"]
-        for r in out["runs"]:
+        for r in out["runs"] + out["plain_runs"]:
             r["rho"] = r["offered_steps_per_s"] / cap
+        out["plain_capacity_steps_per_s"] = out["plain_runs"][0]["throughput_steps_per_s"]
         mean_work = sum(sp["n_chains"] * (sp["N"] - 1) for _, sp in serving_requests()) / 2100
         out["capacity_steps_per_s"] = cap
         out["max_sustainable_rate_per_s"] = cap / mean_work

@@ -327,6 +327,105 @@ rsaw_status rsaw_kernel_time(double *total_ms, uint64_t *launches);
 rsaw_status rsaw_workspace_size(const rsaw_config *cfg, const rsaw_chain_out *out, int32_t reduce,
                                 size_t *bytes);
 
+/*
+ * Lane mapping of the group kernels and its autotuner.
+ *
+ * Three growth kernels spread one chain over a group of lanes: the
+ * six-neighbour lattice for N > 64 (Sec. 3.3.2, Algorithm 1), hard spheres
+ * up to N = 1536 (Sec. 3.3.3, Algorithm 2) and the 26-neighbour lattice for
+ * N > 64.  Their mapping has two knobs: lanes per chain (4..64, a power of
+ * two; 64 / lanes chains share a wavefront, and the lanes split the scan of
+ * the chain's earlier monomers) and threads per block (64 or 256, which
+ * sets how many chains share a block's LDS and its tables).  A built-in
+ * rule picks both from N and k.  A process-wide tuning table can replace
+ * the rule per (geometry, k, range of N); it applies to rsaw_gen_chains,
+ * rsaw_gen_batch and the server alike.
+ *
+ * The mapping never changes a result: every legal mapping gives per-chain
+ * outputs and summaries bit-identical to the built-in rule's, because the
+ * random numbers are keyed by (seed, chain, step, slot), and the candidate
+ * tests and the reduction order do not depend on how the lanes split a
+ * chain's scan.
+ *
+ * Legal mappings:
+ *   RSAW_LATTICE_SC  lanes 4 (N <= 128 only), 8, 16, 32, 64;
+ *   RSAW_REAL_HS     lanes 8, 16, 32, 64 with lanes >= k; lanes 64 only
+ *                    with 64 threads; N <= 1536;
+ *   RSAW_LATTICE_26  lanes 4 (N <= 256 only), 8, 16, 32, 64;
+ * threads 64 or 256; and the block's LDS (lds_bytes) at most 160 KiB.
+ * Calls outside the group kernels' ranges (lattice N <= 64 or exact
+ * weights, hard spheres N > 1536) never consult the table.
+ */
+typedef struct {
+    int32_t geometry;   /* RSAW_LATTICE_SC, RSAW_REAL_HS or RSAW_LATTICE_26      */
+    int32_t k_trials;   /* k of the calls the entry applies to (6 or 26 on the    */
+                        /* lattices)                                              */
+    int32_t n_lo, n_hi; /* chain lengths N (monomers) covered, inclusive          */
+    int32_t lanes;      /* lanes per chain                                        */
+    int32_t threads;    /* threads per block                                      */
+    uint64_t lds_bytes; /* dynamic LDS per block; written by the library only     */
+} rsaw_mapping;
+
+/*
+ * rsaw_mapping_set — add an entry to the tuning table (host-only, no device
+ * call).  `m` is a host pointer; lds_bytes is ignored.  The entry must be
+ * legal at n_hi (then it is at every smaller N of its range, since the LDS
+ * need and the format limits grow with N).  A later entry takes precedence
+ * over earlier ones where their ranges overlap.  Thread-safe; calls already
+ * enqueued keep the mapping they were launched with.
+ * Errors: RSAW_E_INVALID for a NULL `m`, an unknown geometry, k out of
+ * range, n_lo < 1, n_hi < n_lo, or a mapping that is not legal at n_hi.
+ */
+rsaw_status rsaw_mapping_set(const rsaw_mapping *m);
+
+/* rsaw_mapping_clear — empty the tuning table (the built-in rule applies
+ * again to every later call).  Thread-safe. */
+void rsaw_mapping_clear(void);
+
+/*
+ * rsaw_mapping_query — the mapping a rsaw_gen_chains call with `cfg` would
+ * launch its growth kernel with, written to the host struct *m (n_lo =
+ * n_hi = cfg->n_monomers).  Host-only, no device call.  Kernels without a
+ * group mapping report lanes = 1 (one lane per chain: lattice N <= 64, exact
+ * weights) or lanes = 64 with lds_bytes = 0 (hard spheres beyond N = 1536,
+ * bead planes in HBM).
+ * Errors: those of rsaw_gen_chains's validation; RSAW_E_INVALID for a NULL m.
+ */
+rsaw_status rsaw_mapping_query(const rsaw_config *cfg, rsaw_mapping *m);
+
+/*
+ * rsaw_autotune — measure every legal mapping on the device and install the
+ * fastest per range of N.
+ *
+ *   base       the workload of a probe: geometry, k, n_chains, seed, b, sigma
+ *              and flags are taken from it (n_monomers is ignored).
+ *   n_edges    host array of n_buckets chain lengths, strictly increasing.
+ *              Bucket b covers N in [n_edges[b-1] + 1, n_edges[b]] (from
+ *              N = 1 for b = 0) and is probed at N = n_edges[b], its largest
+ *              (and most LDS-hungry) member.
+ *   n_buckets  1..64.
+ *   reps       timed calls per candidate (1..100), after one untimed call.
+ *   chosen     host array of n_buckets, or NULL: the winning mapping of each
+ *              bucket (the built-in one, unchanged, where N has no group
+ *              kernel).
+ *   best_ms    host array of n_buckets, or NULL: the winner's mean time per
+ *              call (growth and reduction, HIP events on `stream`).
+ *   stream     hipStream_t or NULL.
+ *
+ * Each probe is a full rsaw_gen_chains call (growth into the library's
+ * workspace and a reduction to its internal summary).  The candidates are
+ * timed one after another on `stream`, which this call synchronises; other
+ * threads' calls are unaffected while it runs and pick up the installed
+ * entries afterwards.  The winners go into the tuning table as by
+ * rsaw_mapping_set.
+ * Errors: RSAW_E_INVALID for a bad base config (as rsaw_gen_chains), NULL
+ * or non-increasing n_edges, n_buckets or reps out of range;
+ * RSAW_E_DEVICE / RSAW_E_NOMEM for runtime failures (entries of buckets
+ * already tuned stay installed).
+ */
+rsaw_status rsaw_autotune(const rsaw_config *base, const int32_t *n_edges, int32_t n_buckets,
+                          int32_t reps, rsaw_mapping *chosen, double *best_ms, void *stream);
+
 /* Release the internal device workspace of every device and the timing
  * events (safe to call repeatedly; later calls re-create them on demand). */
 void rsaw_shutdown(void);

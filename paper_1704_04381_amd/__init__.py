@@ -62,12 +62,18 @@ SUMMARY_BYTES = C.sizeof(rsaw_summary)
 class rsaw_server_params(C.Structure):
     _fields_ = [("bytes_per_stream", C.c_uint64), ("max_batch", C.c_int32), ("streams", C.c_int32)]
 
+class rsaw_mapping(C.Structure):
+    _fields_ = [("geometry", C.c_int32), ("k_trials", C.c_int32), ("n_lo", C.c_int32), ("n_hi", C.c_int32),
+                ("lanes", C.c_int32), ("threads", C.c_int32), ("lds_bytes", C.c_uint64)]
+
+
 # Every symbol include/rsaw.h declares.
 EXPORTS = ["rsaw_gen_chains", "rsaw_gen_chains_sync", "rsaw_gen_batch", "rsaw_server_create",
            "rsaw_server_submit", "rsaw_server_poll", "rsaw_server_wait", "rsaw_server_destroy",
            "rsaw_status_string",
            "rsaw_last_error", "rsaw_version", "rsaw_kernel_timing", "rsaw_kernel_time",
-           "rsaw_workspace_size", "rsaw_shutdown"]
+           "rsaw_workspace_size", "rsaw_mapping_set", "rsaw_mapping_clear", "rsaw_mapping_query",
+           "rsaw_autotune", "rsaw_shutdown"]
 
 _lib = None
 _lock = threading.Lock()
@@ -125,6 +131,15 @@ def load(path: str = LIB_PATH):
         lib.rsaw_workspace_size.argtypes = [C.POINTER(rsaw_config), C.POINTER(rsaw_chain_out), C.c_int32,
                                             C.POINTER(C.c_size_t)]
         lib.rsaw_workspace_size.restype = C.c_int
+        lib.rsaw_mapping_set.argtypes = [C.POINTER(rsaw_mapping)]
+        lib.rsaw_mapping_set.restype = C.c_int
+        lib.rsaw_mapping_clear.argtypes = []
+        lib.rsaw_mapping_clear.restype = None
+        lib.rsaw_mapping_query.argtypes = [C.POINTER(rsaw_config), C.POINTER(rsaw_mapping)]
+        lib.rsaw_mapping_query.restype = C.c_int
+        lib.rsaw_autotune.argtypes = [C.POINTER(rsaw_config), C.POINTER(C.c_int32), C.c_int32, C.c_int32,
+                                      C.POINTER(rsaw_mapping), C.POINTER(C.c_double), vp]
+        lib.rsaw_autotune.restype = C.c_int
         _lib = lib
         return lib
 
@@ -374,3 +389,45 @@ def workspace_size(cfg: rsaw_config, out: rsaw_chain_out | None = None, reduce: 
     _check(load().rsaw_workspace_size(C.byref(cfg), C.byref(out) if out is not None else None,
                                       1 if reduce else 0, C.byref(n)))
     return n.value
+
+
+def _mapping_dict(m: rsaw_mapping) -> dict:
+    return {name: getattr(m, name) for name, _ in rsaw_mapping._fields_}
+
+
+def mapping_set(geometry, k, n_lo, n_hi, lanes, threads) -> None:
+    """Install a lane mapping for (geometry, k, N in [n_lo, n_hi])
+    (rsaw_mapping_set; host-only)."""
+    geo = GEOMETRIES[geometry] if isinstance(geometry, str) else int(geometry)
+    m = rsaw_mapping(geo, int(k), int(n_lo), int(n_hi), int(lanes), int(threads), 0)
+    _check(load().rsaw_mapping_set(C.byref(m)))
+
+
+def mapping_clear() -> None:
+    """Empty the tuning table (rsaw_mapping_clear)."""
+    load().rsaw_mapping_clear()
+
+
+def mapping_query(cfg: rsaw_config) -> dict:
+    """The mapping a call with cfg would launch with (rsaw_mapping_query;
+    host-only)."""
+    m = rsaw_mapping()
+    _check(load().rsaw_mapping_query(C.byref(cfg), C.byref(m)))
+    return _mapping_dict(m)
+
+
+def autotune(geometry, k, n_edges, n_chains, *, seed=1, reps=3, stream=None, **cfg_kw) -> list[dict]:
+    """Time every legal lane mapping at each bucket edge and install the
+    fastest (rsaw_autotune).  Returns one dict per bucket: the chosen
+    mapping plus its mean time per call, `ms`."""
+    import torch
+
+    edges = [int(n) for n in n_edges]
+    cfg = make_config(geometry, edges[-1], k, n_chains, seed, **cfg_kw)
+    arr = (C.c_int32 * len(edges))(*edges)
+    chosen = (rsaw_mapping * len(edges))()
+    ms = (C.c_double * len(edges))()
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    _check(load().rsaw_autotune(C.byref(cfg), arr, len(edges), int(reps), chosen, ms, C.c_void_p(stream)))
+    return [dict(_mapping_dict(chosen[i]), ms=ms[i]) for i in range(len(edges))]

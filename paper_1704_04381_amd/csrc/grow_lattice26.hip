@@ -524,41 +524,64 @@ __global__ __launch_bounds__(kZ26LaneThreads) void grow_lattice26_lane_batch(con
 
 int lattice26_max_monomers() { return 16384; }
 
+// Shape of the group kernel for N monomers, G lanes per chain (4: 8-bit n_m
+// fields, N <= 256; 8..64: 16-bit fields) and `threads` per block (64 or
+// 256).  hipErrorInvalidValue when the combination is not legal or the
+// block's LDS exceeds the CU's 160 KiB.
+static hipError_t z26_shape(int N, bool i16, int G, int threads, GrowVariant *v)
+{
+    if (G != 4 && G != 8 && G != 16 && G != 32 && G != 64) return hipErrorInvalidValue;
+    if (threads != 64 && threads != 256) return hipErrorInvalidValue;
+    if (G == 4 && N > 256) return hipErrorInvalidValue;
+    const int H = (N + 4 * G - 1) / (4 * G) * (4 * G);
+    const size_t bytes = ((size_t)kZ26GroupHead + (size_t)(threads / G) * 2 * H) * sizeof(uint32_t);
+    if (bytes > 163840) return hipErrorInvalidValue;
+    v->family = 3;
+    v->p0 = G;
+    v->p1 = 0;
+    v->p2 = i16 ? 1 : 0;
+    v->threads = threads;
+    v->cpb = threads / G;
+    v->shmem = bytes;
+    v->H = H;
+    v->S = 0;
+    return hipSuccess;
+}
+
 // One lane per chain up to N = 64 (and for exact weights, N <= 14); above,
-// G lanes per chain, G growing with N so that the chains a CU's LDS holds
-// still fill the CU (measured best widths): 4 up to N = 160 (whose 8-bit
-// n_m fields need N <= 256), 8 up to 384, 16 up to 768, 32 up to 1536, 64
-// beyond; 256-thread blocks when the block's planes fit in half a
-// CU's LDS, else one wave.
+// G lanes per chain.  Built-in rule: G grows with N so that the chains a
+// CU's LDS holds still fill the CU (measured best widths): 4 up to N = 160
+// (whose 8-bit n_m fields need N <= 256), 8 up to 384, 16 up to 768, 32 up
+// to 1536, 64 beyond; 256-thread blocks when the block's planes fit in half
+// a CU's LDS, else one wave.  A legal mapping of the tuning table replaces
+// the rule for the group kernel.
 hipError_t lattice26_variant(const GrowArgs &a, bool exact, bool i16, GrowVariant *v)
 {
     const int N = a.n_monomers;
-    v->family = 3;
-    v->p1 = exact ? 1 : 0;
-    v->p2 = i16 ? 1 : 0;
-    v->S = 0;
     if (N <= kZ26LaneMax) {
+        v->family = 3;
         v->p0 = 1;
+        v->p1 = exact ? 1 : 0;
+        v->p2 = i16 ? 1 : 0;
         v->threads = kZ26LaneThreads;
         v->cpb = kZ26LaneThreads;
         v->shmem = z26_lane_shmem(N, kZ26LaneThreads);
         v->H = 0;
+        v->S = 0;
         return hipSuccess;
     }
     if (exact) return hipErrorInvalidValue;
+    int tl = 0, tt = 0;
+    if (tuned_mapping(2 /* 26-neighbour lattice */, N, a.k_trials, &tl, &tt) &&
+        z26_shape(N, i16, tl, tt, v) == hipSuccess)
+        return hipSuccess;
     const int G = N <= 160 ? 4 : (N <= 384 ? 8 : (N <= 768 ? 16 : (N <= 1536 ? 32 : 64)));
-    const int H = (N + 4 * G - 1) / (4 * G) * (4 * G);
-    auto bytes = [&](int threads) {
-        return ((size_t)kZ26GroupHead + (size_t)(threads / G) * 2 * H) * sizeof(uint32_t);
-    };
-    const int threads = bytes(256) <= 81920 ? 256 : 64;
-    if (bytes(threads) > 163840) return hipErrorInvalidValue;
-    v->p0 = G;
-    v->threads = threads;
-    v->cpb = threads / G;
-    v->shmem = bytes(threads);
-    v->H = H;
-    return hipSuccess;
+    GrowVariant half_cu;
+    if (z26_shape(N, i16, G, 256, &half_cu) == hipSuccess && half_cu.shmem <= 81920) {
+        *v = half_cu;
+        return hipSuccess;
+    }
+    return z26_shape(N, i16, G, 64, v);
 }
 
 template <bool EXACT, typename CT>

@@ -318,38 +318,53 @@ __global__ __launch_bounds__(256) void grow_lattice_lds_batch(const GrowEntry *t
 // Largest lattice chain of the LDS kernel (wide words: 128 KiB per chain).
 int lattice_lds_max_monomers() { return 16384; }
 
-// Variant for 64 < N <= 16384.  G grows with N so that one wave's chains take
-// at most ~17 KiB of LDS (8 waves per CU) up to N = 2048; four waves per
-// block share the move table when the block fits in half a CU's LDS.
-hipError_t lattice_lds_variant(const GrowArgs &a, bool i16, GrowVariant *v)
+// Shape of the LDS kernel for N monomers, G lanes per chain (4: byte words,
+// N <= 128; 8..64: wide words) and `threads` per block (64 or 256).
+// hipErrorInvalidValue when the combination is not legal or the block's
+// LDS exceeds the CU's 160 KiB.
+static hipError_t lds_shape(int N, bool i16, int G, int threads, GrowVariant *v)
 {
-    const int N = a.n_monomers;
-    int G, wide;
-    if (N <= 128) { G = 4; wide = 0; }
-    else if (N <= 256) { G = 8; wide = 1; }
-    else if (N <= 512) { G = 16; wide = 1; }
-    else if (N <= 1024) { G = 32; wide = 1; }
-    else { G = 64; wide = 1; }
+    if (G != 4 && G != 8 && G != 16 && G != 32 && G != 64) return hipErrorInvalidValue;
+    if (threads != 64 && threads != 256) return hipErrorInvalidValue;
+    const int wide = G == 4 ? 0 : 1;
+    if (!wide && N > 128) return hipErrorInvalidValue;
     const int WPM = wide ? 2 : 1;
     const int half = (N + 1) / 2;
     const int H = (half + 4 * G - 1) / (4 * G) * (4 * G);
     // chain stride: pad so that the chains of a wave start on different banks
     const int S = 2 * WPM * H + (4 * G < 64 ? 4 * G : 0);
-    auto bytes = [&](int threads) {
-        return ((size_t)WPM * kLutSize + (size_t)(threads / G) * S) * sizeof(uint32_t);
-    };
-    const int threads = bytes(256) <= 81920 ? 256 : 64;
-    if (bytes(threads) > 163840) return hipErrorInvalidValue;
+    const size_t bytes = ((size_t)WPM * kLutSize + (size_t)(threads / G) * S) * sizeof(uint32_t);
+    if (bytes > 163840) return hipErrorInvalidValue;
     v->family = 1;
     v->p0 = G;
     v->p1 = wide;
     v->p2 = i16 ? 1 : 0;
     v->threads = threads;
     v->cpb = threads / G;
-    v->shmem = bytes(threads);
+    v->shmem = bytes;
     v->H = H;
     v->S = S;
     return hipSuccess;
+}
+
+// Variant for 64 < N <= 16384.  Built-in rule: G grows with N so that one
+// wave's chains take at most ~17 KiB of LDS (8 waves per CU) up to N = 2048;
+// four waves per block share the move table when the block fits in half a
+// CU's LDS.  A legal mapping of the tuning table replaces the rule.
+hipError_t lattice_lds_variant(const GrowArgs &a, bool i16, GrowVariant *v)
+{
+    const int N = a.n_monomers;
+    int tl = 0, tt = 0;
+    if (tuned_mapping(0 /* simple cubic lattice */, N, a.k_trials, &tl, &tt) &&
+        lds_shape(N, i16, tl, tt, v) == hipSuccess)
+        return hipSuccess;
+    const int G = N <= 128 ? 4 : (N <= 256 ? 8 : (N <= 512 ? 16 : (N <= 1024 ? 32 : 64)));
+    GrowVariant half_cu;
+    if (lds_shape(N, i16, G, 256, &half_cu) == hipSuccess && half_cu.shmem <= 81920) {
+        *v = half_cu;
+        return hipSuccess;
+    }
+    return lds_shape(N, i16, G, 64, v);
 }
 
 template <int G, bool WIDE, typename CT>

@@ -460,13 +460,37 @@ uint32_t real_hbm_slots(int n_monomers, uint64_t n_chains)
     return (uint32_t)(n_chains < 2048 ? n_chains : 2048);
 }
 
-// Lanes per chain: at least the next power of two >= k (one trial per
-// lane), and enough that the chains whose planes fit in a CU's LDS still
-// fill about 8 waves (G >= 0.075 N); the extra lanes share the culling pass.
-// 256-thread blocks when the bead planes fit in half a CU's LDS, else one
-// wave per block (up to the whole 160 KiB).  G = 64 always runs one-wave
+// Shape of the LDS kernel for N beads, G lanes per chain (8..64, G >= k: one
+// trial per lane) and `threads` per block (64 or 256; G = 64 only in
+// one-wave blocks).  hipErrorInvalidValue when the combination is not legal
+// or the block's planes and logarithm table exceed the CU's 160 KiB.
+static hipError_t real_shape(int N, int k, int G, int threads, GrowVariant *v)
+{
+    if (G != 8 && G != 16 && G != 32 && G != 64) return hipErrorInvalidValue;
+    if (G < k) return hipErrorInvalidValue;
+    if (threads != 64 && (threads != 256 || G == 64)) return hipErrorInvalidValue;
+    const size_t planes = (size_t)3 * N * plane_row(threads / G, G) * sizeof(double);
+    if (planes + 65 * sizeof(double) > 163840) return hipErrorInvalidValue;
+    v->family = 2;
+    v->p0 = G;
+    v->p1 = 0;
+    v->p2 = 0;
+    v->threads = threads;
+    v->cpb = threads / G;
+    v->shmem = planes;
+    v->H = 0;
+    v->S = 0;
+    return hipSuccess;
+}
+
+// Built-in rule.  Lanes per chain: at least the next power of two >= k (one
+// trial per lane), and enough that the chains whose planes fit in a CU's LDS
+// still fill about 8 waves (G >= 0.075 N); the extra lanes share the culling
+// pass.  256-thread blocks when the bead planes fit in half a CU's LDS, else
+// one wave per block (up to the whole 160 KiB).  G = 64 always runs one-wave
 // blocks: four one-chain waves sharing a block's padded planes were measured
-// 1.2-2.3x slower for 432 <= N <= 672 (k = 8) than four one-wave blocks.
+// 1.2-2.3x slower for 432 <= N <= 672 (k = 8) than four one-wave blocks.  A
+// legal mapping of the tuning table replaces the rule.
 hipError_t real_variant(const GrowArgs &a, GrowVariant *v)
 {
     const int N = a.n_monomers;
@@ -483,26 +507,20 @@ hipError_t real_variant(const GrowArgs &a, GrowVariant *v)
         v->S = 0;
         return hipSuccess;
     }
+    int tl = 0, tt = 0;
+    if (tuned_mapping(1 /* hard spheres */, N, a.k_trials, &tl, &tt) &&
+        real_shape(N, a.k_trials, tl, tt, v) == hipSuccess)
+        return hipSuccess;
     int need = a.k_trials;
     const int occ = (3 * N + 39) / 40; // ceil(0.075 N)
     if (occ > need) need = occ;
     const int G = need <= 8 ? 8 : (need <= 16 ? 16 : (need <= 32 ? 32 : 64));
-    auto planes = [&](int threads) {
-        return (size_t)3 * N * plane_row(threads / G, G) * sizeof(double);
-    };
-    int threads = G == 64 ? 64 : 256;
-    if (planes(threads) > 81920) threads = 64;
-    if (planes(threads) + 65 * sizeof(double) > 163840) return hipErrorInvalidValue;
-    v->family = 2;
-    v->p0 = G;
-    v->p1 = 0;
-    v->p2 = 0;
-    v->threads = threads;
-    v->cpb = threads / G;
-    v->shmem = planes(threads);
-    v->H = 0;
-    v->S = 0;
-    return hipSuccess;
+    GrowVariant half_cu;
+    if (G != 64 && real_shape(N, a.k_trials, G, 256, &half_cu) == hipSuccess && half_cu.shmem <= 81920) {
+        *v = half_cu;
+        return hipSuccess;
+    }
+    return real_shape(N, a.k_trials, G, 64, v);
 }
 
 template <int G>

@@ -418,6 +418,24 @@ rsaw_status gen_impl(const rsaw_config *cfg, const rsaw_chain_out *out, rsaw_sum
     return RSAW_OK;
 }
 
+// Growth-kernel variant (kernel family, template parameters, block shape)
+// of one ensemble, as its launch would choose it.
+hipError_t ensemble_variant(const rsaw_config *cfg, const EnsLayout &L, rsaw::GrowVariant *v)
+{
+    rsaw::GrowArgs probe;
+    std::memset(&probe, 0, sizeof(probe));
+    probe.n_monomers = cfg->n_monomers;
+    probe.k_trials = cfg->k_trials;
+    const bool i16 = cfg->coord_type == RSAW_I16;
+    if (!L.lattice) return rsaw::real_variant(probe, v);
+    if (L.z26) return rsaw::lattice26_variant(probe, L.exact, i16, v);
+    if (L.exact || cfg->n_monomers <= 64) {
+        rsaw::lattice_reg_variant(probe, L.exact, i16, v);
+        return hipSuccess;
+    }
+    return rsaw::lattice_lds_variant(probe, i16, v);
+}
+
 // Batched body: every ensemble's growth shares one launch per kernel
 // variant, and the reductions three launches in all.
 rsaw_status batch_impl(const rsaw_config *cfgs, const rsaw_chain_out *outs, int32_t n,
@@ -450,21 +468,7 @@ rsaw_status batch_impl(const rsaw_config *cfgs, const rsaw_chain_out *outs, int3
         layout_ensemble(&cfgs[i], in[i], reduce, &off, &L[i]);
         max_bins = std::max(max_bins, L[i].bins);
         red_blocks += L[i].n_blocks;
-        rsaw::GrowArgs probe;
-        std::memset(&probe, 0, sizeof(probe));
-        probe.n_monomers = cfgs[i].n_monomers;
-        probe.k_trials = cfgs[i].k_trials;
-        const bool i16 = cfgs[i].coord_type == RSAW_I16;
-        if (!L[i].lattice) {
-            e = rsaw::real_variant(probe, &var[i]);
-        } else if (L[i].z26) {
-            e = rsaw::lattice26_variant(probe, L[i].exact, i16, &var[i]);
-        } else if (L[i].exact || cfgs[i].n_monomers <= 64) {
-            rsaw::lattice_reg_variant(probe, L[i].exact, i16, &var[i]);
-            e = hipSuccess;
-        } else {
-            e = rsaw::lattice_lds_variant(probe, i16, &var[i]);
-        }
+        e = ensemble_variant(&cfgs[i], L[i], &var[i]);
         if (e != hipSuccess) return fail(RSAW_E_UNSUPPORTED, "ensemble " + std::to_string(i) + ": no kernel variant");
     }
     // ensembles with chains, grouped by variant (stable: index order within a group)
@@ -582,6 +586,75 @@ rsaw_status batch_impl(const rsaw_config *cfgs, const rsaw_chain_out *outs, int3
 }
 
 } // namespace
+
+// ---- tuning table of the group kernels' lane mapping --------------------
+namespace {
+std::mutex g_map_lock;
+std::vector<rsaw_mapping> g_map; // newest last
+// The autotuner's candidate, forced on its own thread while it is timed.
+thread_local bool t_force = false;
+thread_local int t_force_lanes = 0, t_force_threads = 0;
+
+struct ForceMapping {
+    ForceMapping(int lanes, int threads)
+    {
+        t_force = true;
+        t_force_lanes = lanes;
+        t_force_threads = threads;
+    }
+    ~ForceMapping() { t_force = false; }
+};
+
+// Mapping a call with cfg launches its growth kernel with (host-only).
+rsaw_status query_mapping(const rsaw_config *cfg, rsaw_mapping *m)
+{
+    rsaw_chain_out none{};
+    EnsLayout L;
+    size_t off = 0;
+    layout_ensemble(cfg, none, false, &off, &L);
+    rsaw::GrowVariant v;
+    if (ensemble_variant(cfg, L, &v) != hipSuccess) return fail(RSAW_E_UNSUPPORTED, "no kernel variant");
+    m->geometry = cfg->geometry;
+    m->k_trials = cfg->k_trials;
+    m->n_lo = m->n_hi = cfg->n_monomers;
+    // register lattice (family 0) and 26-neighbour lane kernel: one lane per chain
+    m->lanes = v.family == 0 || (v.family == 3 && v.p0 == 1) ? 1 : v.p0;
+    m->threads = v.threads;
+    m->lds_bytes = v.shmem;
+    return RSAW_OK;
+}
+
+// True when (lanes, threads) is what a group kernel launches for cfg with
+// that mapping forced, i.e. the mapping is legal for cfg.
+bool mapping_legal(const rsaw_config *cfg, int lanes, int threads, rsaw_mapping *got)
+{
+    if (lanes < 2) return false; // one-lane kernels have no group mapping
+    ForceMapping f(lanes, threads);
+    if (query_mapping(cfg, got) != RSAW_OK) return false;
+    return got->lanes == lanes && got->threads == threads;
+}
+} // namespace
+
+namespace rsaw {
+bool tuned_mapping(int geometry, int n_monomers, int k_trials, int *lanes, int *threads)
+{
+    if (t_force) {
+        *lanes = t_force_lanes;
+        *threads = t_force_threads;
+        return true;
+    }
+    std::lock_guard<std::mutex> lk(g_map_lock);
+    for (auto it = g_map.rbegin(); it != g_map.rend(); ++it) {
+        if (it->geometry == geometry && it->k_trials == k_trials && it->n_lo <= n_monomers &&
+            n_monomers <= it->n_hi) {
+            *lanes = it->lanes;
+            *threads = it->threads;
+            return true;
+        }
+    }
+    return false;
+}
+} // namespace rsaw
 
 namespace rsaw {
 // The argument checks of rsaw_gen_chains, for the serving loop's submit.
@@ -715,6 +788,140 @@ void rsaw_shutdown(void)
         (void)hipSetDevice(cur);
     }
     g_ws.clear();
+}
+
+rsaw_status rsaw_mapping_set(const rsaw_mapping *m)
+{
+    g_last_error.clear();
+    if (!m) return fail(RSAW_E_INVALID, "mapping is NULL");
+    if (m->n_lo < 1 || m->n_hi < m->n_lo) return fail(RSAW_E_INVALID, "need 1 <= n_lo <= n_hi");
+    rsaw_config c;
+    std::memset(&c, 0, sizeof(c));
+    c.geometry = m->geometry;
+    c.n_monomers = m->n_hi;
+    c.k_trials = m->k_trials;
+    c.coord_type = m->geometry == RSAW_REAL_HS ? RSAW_F64 : RSAW_I32;
+    c.n_chains = 1;
+    c.bond_length = 1.0;
+    c.bead_diameter = 1.0;
+    rsaw_status st = validate(&c);
+    if (st != RSAW_OK) return st;
+    rsaw_mapping got;
+    if (!mapping_legal(&c, m->lanes, m->threads, &got))
+        return fail(RSAW_E_INVALID, "lanes " + std::to_string(m->lanes) + ", threads " +
+                                        std::to_string(m->threads) + " is not a legal mapping at N = " +
+                                        std::to_string(m->n_hi));
+    rsaw_mapping e = *m;
+    e.lds_bytes = 0;
+    std::lock_guard<std::mutex> lk(g_map_lock);
+    g_map.push_back(e);
+    return RSAW_OK;
+}
+
+void rsaw_mapping_clear(void)
+{
+    std::lock_guard<std::mutex> lk(g_map_lock);
+    g_map.clear();
+}
+
+rsaw_status rsaw_mapping_query(const rsaw_config *cfg, rsaw_mapping *m)
+{
+    g_last_error.clear();
+    if (!m) return fail(RSAW_E_INVALID, "m is NULL");
+    const rsaw_status st = validate(cfg);
+    if (st != RSAW_OK) return st;
+    return query_mapping(cfg, m);
+}
+
+rsaw_status rsaw_autotune(const rsaw_config *base, const int32_t *n_edges, int32_t n_buckets,
+                          int32_t reps, rsaw_mapping *chosen, double *best_ms, void *stream)
+{
+    g_last_error.clear();
+    if (!base) return fail(RSAW_E_INVALID, "base is NULL");
+    if (!n_edges || n_buckets < 1 || n_buckets > 64) return fail(RSAW_E_INVALID, "need 1..64 buckets");
+    if (reps < 1 || reps > 100) return fail(RSAW_E_INVALID, "reps must be 1..100");
+    for (int32_t b = 0; b < n_buckets; ++b) {
+        if (n_edges[b] < 1 || (b > 0 && n_edges[b] <= n_edges[b - 1]))
+            return fail(RSAW_E_INVALID, "n_edges must be positive and strictly increasing");
+        rsaw_config c = *base;
+        c.n_monomers = n_edges[b];
+        const rsaw_status st = validate(&c);
+        if (st != RSAW_OK) return fail(st, "bucket " + std::to_string(b) + ": " + g_last_error);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipError_t e = hipEventCreate(&ev0);
+    if (e == hipSuccess) e = hipEventCreate(&ev1);
+    if (e != hipSuccess) {
+        if (ev0) (void)hipEventDestroy(ev0);
+        return hip_fail(e, "hipEventCreate");
+    }
+    rsaw_status st = RSAW_OK;
+    // one untimed call, then reps calls between two events
+    auto time_calls = [&](const rsaw_config &c, double *ms) -> rsaw_status {
+        rsaw_status r = gen_impl(&c, nullptr, nullptr, nullptr, nullptr, stream, true, nullptr);
+        if (r != RSAW_OK) return r;
+        hipError_t he = hipEventRecord(ev0, s);
+        for (int32_t q = 0; q < reps && he == hipSuccess; ++q) {
+            r = gen_impl(&c, nullptr, nullptr, nullptr, nullptr, stream, true, nullptr);
+            if (r != RSAW_OK) return r;
+        }
+        if (he == hipSuccess) he = hipEventRecord(ev1, s);
+        if (he == hipSuccess) he = hipEventSynchronize(ev1);
+        float t = 0.f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&t, ev0, ev1);
+        if (he != hipSuccess) return hip_fail(he, "autotune timing");
+        *ms = (double)t / reps;
+        return RSAW_OK;
+    };
+    static const int kLanes[] = {4, 8, 16, 32, 64};
+    static const int kThreads[] = {64, 256};
+    for (int32_t b = 0; b < n_buckets && st == RSAW_OK; ++b) {
+        rsaw_config c = *base;
+        c.n_monomers = n_edges[b];
+        rsaw_mapping win;
+        st = query_mapping(&c, &win);
+        if (st != RSAW_OK) break;
+        double win_ms = -1.0;
+        bool tuned = false;
+        for (int lanes : kLanes) {
+            for (int threads : kThreads) {
+                rsaw_mapping got;
+                if (!mapping_legal(&c, lanes, threads, &got)) continue;
+                double ms = 0.0;
+                {
+                    ForceMapping f(lanes, threads);
+                    st = time_calls(c, &ms);
+                }
+                if (st != RSAW_OK) break;
+                if (win_ms < 0.0 || ms < win_ms) {
+                    win_ms = ms;
+                    win = got;
+                }
+                tuned = true;
+            }
+            if (st != RSAW_OK) break;
+        }
+        if (st != RSAW_OK) break;
+        if (!tuned) {
+            // no group kernel at this N: the built-in kernel, timed as is
+            st = time_calls(c, &win_ms);
+            if (st != RSAW_OK) break;
+        }
+        win.n_lo = b == 0 ? 1 : n_edges[b - 1] + 1;
+        win.n_hi = n_edges[b];
+        if (tuned) {
+            std::lock_guard<std::mutex> lk(g_map_lock);
+            rsaw_mapping ins = win;
+            ins.lds_bytes = 0;
+            g_map.push_back(ins);
+        }
+        if (chosen) chosen[b] = win;
+        if (best_ms) best_ms[b] = win_ms;
+    }
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    return st;
 }
 
 } // extern "C"

@@ -181,4 +181,12 @@ struct GrowVariant {
     int32_t H, S;       // LDS lattice plane length and chain stride
 };
 
+// Lane mapping (lanes per chain, threads per block) that the tuning table
+// holds for a group-kernel call of this geometry, N and k: the calling
+// thread's forced mapping while the autotuner times a candidate, else the
+// newest table entry covering N.  False when neither applies; the variant
+// functions then use their built-in rule, and they also fall back to it
+// when a mapping is not legal for the call.
+bool tuned_mapping(int geometry, int n_monomers, int k_trials, int *lanes, int *threads);
+
 } // namespace rsaw

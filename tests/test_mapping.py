@@ -1,0 +1,100 @@
+"""Tuning table of the group kernels' lane mapping: the host-only calls
+(rsaw_mapping_set / _query / _clear) of the HIP library, no device call.
+
+The mapping only decides how a chain's scan is spread over lanes; which
+mappings are legal follows from each group kernel's word formats and its
+LDS need (a CU holds 160 KiB).
+"""
+from __future__ import annotations
+
+import pytest
+
+import paper_1704_04381_amd as rs
+
+
+@pytest.fixture(autouse=True)
+def _clean_table():
+    if not __import__("os").path.exists(rs.LIB_PATH):
+        pytest.skip("librsaw.so not built")
+    rs.mapping_clear()
+    yield
+    rs.mapping_clear()
+
+
+def _q(geo, N, k):
+    return rs.mapping_query(rs.make_config(geo, N, k, 1000, 1))
+
+
+def test_builtin_rule():
+    # one lane per chain where there is no group kernel
+    assert _q("lattice", 64, 6)["lanes"] == 1
+    assert _q("lattice26", 64, 26)["lanes"] == 1
+    # group widths of the built-in rule
+    assert [_q("lattice", n, 6)["lanes"] for n in (65, 128, 129, 300, 600, 1024, 2048)] == [4, 4, 8, 16, 32, 32, 64]
+    assert [_q("lattice26", n, 26)["lanes"] for n in (65, 160, 161, 400, 800, 1600)] == [4, 4, 8, 16, 32, 64]
+    assert _q("real", 64, 8)["lanes"] == 8 and _q("real", 64, 16)["lanes"] == 16
+    assert _q("real", 300, 8)["lanes"] == 32  # 0.075 N = 22.5 -> 32
+    # beyond N = 1536 hard-sphere planes live in HBM
+    m = _q("real", 3000, 8)
+    assert m["lanes"] == 64 and m["threads"] == 64 and m["lds_bytes"] == 0
+    for geo, k in (("lattice", 6), ("real", 8), ("lattice26", 26)):
+        for n in (65, 200, 1000, 1536):
+            assert _q(geo, n, k)["lds_bytes"] <= 160 * 1024
+
+
+def test_set_overrides_inside_its_range_only():
+    base = _q("lattice", 100, 6)
+    rs.mapping_set("lattice", 6, 65, 128, 32, 64)
+    m = _q("lattice", 100, 6)
+    assert (m["lanes"], m["threads"]) == (32, 64)
+    assert _q("lattice", 129, 6)["lanes"] == 8       # outside the range
+    assert _q("lattice", 64, 6)["lanes"] == 1        # register kernel: never tuned
+    assert _q("lattice26", 100, 26)["lanes"] == 4    # other geometry
+    # a later entry wins where ranges overlap
+    rs.mapping_set("lattice", 6, 90, 110, 16, 256)
+    assert (_q("lattice", 100, 6)["lanes"], _q("lattice", 100, 6)["threads"]) == (16, 256)
+    assert _q("lattice", 80, 6)["lanes"] == 32
+    rs.mapping_clear()
+    assert _q("lattice", 100, 6) == base
+
+
+def test_hard_sphere_mapping_is_per_k():
+    rs.mapping_set("real", 8, 1, 200, 64, 64)
+    assert _q("real", 100, 8)["lanes"] == 64
+    assert _q("real", 100, 16)["lanes"] == 16
+
+
+@pytest.mark.parametrize("args", [
+    ("lattice", 6, 65, 200, 4, 64),      # byte words need N <= 128
+    ("lattice", 6, 65, 100, 2, 64),      # not a group width
+    ("lattice", 6, 65, 100, 8, 128),     # threads must be 64 or 256
+    ("lattice", 6, 10, 64, 8, 64),       # N <= 64: register kernel
+    ("real", 16, 10, 100, 8, 256),       # fewer lanes than trials
+    ("real", 8, 10, 100, 64, 256),       # 64 lanes only in one-wave blocks
+    ("real", 8, 10, 3000, 32, 64),       # beyond the LDS kernel
+    ("real", 8, 10, 1536, 8, 64),        # 8 chains' planes exceed 160 KiB
+    ("lattice26", 26, 65, 300, 4, 256),  # 8-bit n_m fields need N <= 256
+    ("lattice26", 26, 70, 60, 8, 64),    # empty range
+    ("lattice", 5, 65, 100, 8, 64),      # lattice k must be 6
+])
+def test_set_rejects_illegal_mappings(args):
+    geo, k = args[0], (args[1] if args[1] in (6, 8, 16, 26) else 6)
+    before = _q(geo, 100, k)
+    with pytest.raises(rs.RsawError) as e:
+        rs.mapping_set(*args)
+    assert e.value.status == 1  # RSAW_E_INVALID
+    assert _q(geo, 100, k) == before  # nothing installed
+
+
+def test_legal_mapping_at_n_hi_is_legal_below():
+    for geo, k in (("lattice", 6), ("real", 8), ("lattice26", 26)):
+        for lanes in (4, 8, 16, 32, 64):
+            for threads in (64, 256):
+                try:
+                    rs.mapping_set(geo, k, 65, 1000, lanes, threads)
+                except rs.RsawError:
+                    continue
+                for n in (65, 300, 999, 1000):
+                    m = _q(geo, n, k)
+                    assert (m["lanes"], m["threads"]) == (lanes, threads), (geo, n, lanes, threads)
+                rs.mapping_clear()
