@@ -204,9 +204,11 @@ rsaw_status rsaw_gen_chains_sync(const rsaw_config *cfg, const rsaw_chain_out *o
  * Every ensemble's per-chain outputs and summary are bit-identical to those
  * of a separate rsaw_gen_chains call with the same configuration.  The
  * ensembles share launches: one growth launch per kernel variant (geometry,
- * size class and block shape), whose blocks map to (ensemble, chunk) through
- * a prefix table, and three reduction launches for all of them, instead of
- * four launches per ensemble.  The descriptor tables travel in one copy from
+ * size class and block shape; an ensemble large enough to fill the GPU
+ * alone shares only with ensembles whose LDS need allows as many blocks per
+ * CU), whose blocks map to (ensemble, chunk) through a prefix table, and
+ * three reduction launches for all of them, instead of four launches per
+ * ensemble.  The descriptor tables travel in one copy from
  * a pinned host buffer of the library, reused per (device, stream): a call
  * waits for the previous call's table copy on the same stream (not for its
  * kernels).  Asynchronous otherwise.

@@ -471,13 +471,32 @@ rsaw_status batch_impl(const rsaw_config *cfgs, const rsaw_chain_out *outs, int3
         e = ensemble_variant(&cfgs[i], L[i], &var[i]);
         if (e != hipSuccess) return fail(RSAW_E_UNSUPPORTED, "ensemble " + std::to_string(i) + ": no kernel variant");
     }
-    // ensembles with chains, grouped by variant (stable: index order within a group)
+    // ensembles with chains, grouped by variant (stable: index order within a
+    // group).  A launch gives every block the largest LDS of its ensembles.
+    // An ensemble that fills the GPU by itself (at least one block per slot
+    // that its own LDS leaves on every CU: 160 KiB / shmem per CU, capped at
+    // the 32 waves a CU holds) shares a launch only with ensembles of the
+    // same blocks per CU, so it keeps its occupancy instead of running at
+    // that of the longest chains in the batch.  Smaller ensembles cannot
+    // fill the CUs alone and share one launch per variant, as few launches
+    // as possible.
+    int n_cu = 256;
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu < 1)
+        n_cu = 256;
     std::vector<int32_t> order;
-    for (int32_t i = 0; i < n; ++i)
-        if (cfgs[i].n_chains > 0) order.push_back(i);
+    std::vector<uint64_t> per_cu(n, 0);
+    for (int32_t i = 0; i < n; ++i) {
+        if (cfgs[i].n_chains == 0) continue;
+        order.push_back(i);
+        const rsaw::GrowVariant &v = var[i];
+        const uint64_t cap = 2048 / (uint64_t)v.threads;
+        const uint64_t slots = v.shmem ? std::min((uint64_t)(163840 / v.shmem), cap) : cap;
+        const uint64_t blocks = (cfgs[i].n_chains + v.cpb - 1) / v.cpb;
+        per_cu[i] = blocks >= slots * (uint64_t)n_cu ? slots : 0;
+    }
     auto key = [&](int32_t i) {
         const rsaw::GrowVariant &v = var[i];
-        return std::make_tuple(v.family, v.p0, v.p1, v.p2, v.threads);
+        return std::make_tuple(v.family, v.p0, v.p1, v.p2, v.threads, per_cu[i]);
     };
     std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return key(x) < key(y); });
     const int32_t ng = (int32_t)order.size();
