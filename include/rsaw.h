@@ -385,6 +385,18 @@ rsaw_status rsaw_mapping_set(const rsaw_mapping *m);
 void rsaw_mapping_clear(void);
 
 /*
+ * rsaw_mapping_list — copy the tuning table, oldest entry first, into the
+ * host array `out` of `capacity` entries (out may be NULL when capacity is
+ * 0); *count (host, required) receives the number of entries in the table,
+ * which may exceed capacity (then only the first `capacity` are copied).
+ * Re-adding the listed entries in order with rsaw_mapping_set rebuilds the
+ * same table, e.g. from a saved autotune cache.  Host-only, thread-safe.
+ * Errors: RSAW_E_INVALID for a NULL count, capacity < 0, or a NULL out with
+ * capacity > 0.
+ */
+rsaw_status rsaw_mapping_list(rsaw_mapping *out, int32_t capacity, int32_t *count);
+
+/*
  * rsaw_mapping_query — the mapping a rsaw_gen_chains call with `cfg` would
  * launch its growth kernel with, written to the host struct *m (n_lo =
  * n_hi = cfg->n_monomers).  Host-only, no device call.  Kernels without a

@@ -72,7 +72,7 @@ EXPORTS = ["rsaw_gen_chains", "rsaw_gen_chains_sync", "rsaw_gen_batch", "rsaw_se
            "rsaw_server_submit", "rsaw_server_poll", "rsaw_server_wait", "rsaw_server_destroy",
            "rsaw_status_string",
            "rsaw_last_error", "rsaw_version", "rsaw_kernel_timing", "rsaw_kernel_time",
-           "rsaw_workspace_size", "rsaw_mapping_set", "rsaw_mapping_clear", "rsaw_mapping_query",
+           "rsaw_workspace_size", "rsaw_mapping_set", "rsaw_mapping_clear", "rsaw_mapping_list", "rsaw_mapping_query",
            "rsaw_autotune", "rsaw_shutdown"]
 
 _lib = None
@@ -135,6 +135,8 @@ def load(path: str = LIB_PATH):
         lib.rsaw_mapping_set.restype = C.c_int
         lib.rsaw_mapping_clear.argtypes = []
         lib.rsaw_mapping_clear.restype = None
+        lib.rsaw_mapping_list.argtypes = [C.POINTER(rsaw_mapping), C.c_int32, C.POINTER(C.c_int32)]
+        lib.rsaw_mapping_list.restype = C.c_int
         lib.rsaw_mapping_query.argtypes = [C.POINTER(rsaw_config), C.POINTER(rsaw_mapping)]
         lib.rsaw_mapping_query.restype = C.c_int
         lib.rsaw_autotune.argtypes = [C.POINTER(rsaw_config), C.POINTER(C.c_int32), C.c_int32, C.c_int32,
@@ -406,6 +408,39 @@ def mapping_set(geometry, k, n_lo, n_hi, lanes, threads) -> None:
 def mapping_clear() -> None:
     """Empty the tuning table (rsaw_mapping_clear)."""
     load().rsaw_mapping_clear()
+
+
+def mapping_list() -> list[dict]:
+    """The tuning table, oldest entry first (rsaw_mapping_list)."""
+    lib = load()
+    n = C.c_int32(0)
+    _check(lib.rsaw_mapping_list(None, 0, C.byref(n)))
+    arr = (rsaw_mapping * max(n.value, 1))()
+    _check(lib.rsaw_mapping_list(arr, n.value, C.byref(n)))
+    return [_mapping_dict(arr[i]) for i in range(min(n.value, len(arr)))]
+
+
+def save_mappings(path) -> int:
+    """Write the tuning table to a JSON autotune cache; returns the number
+    of entries."""
+    import json
+
+    rows = [{k: v for k, v in m.items() if k != "lds_bytes"} for m in mapping_list()]
+    with open(path, "w") as f:
+        json.dump({"rsaw_mappings": rows, "version": version()}, f, indent=1)
+    return len(rows)
+
+
+def load_mappings(path) -> int:
+    """Add the entries of a JSON autotune cache to the tuning table, in their
+    saved order (each validated by rsaw_mapping_set); returns their number."""
+    import json
+
+    with open(path) as f:
+        rows = json.load(f)["rsaw_mappings"]
+    for r in rows:
+        mapping_set(r["geometry"], r["k_trials"], r["n_lo"], r["n_hi"], r["lanes"], r["threads"])
+    return len(rows)
 
 
 def mapping_query(cfg: rsaw_config) -> dict:

@@ -843,6 +843,18 @@ void rsaw_mapping_clear(void)
     g_map.clear();
 }
 
+rsaw_status rsaw_mapping_list(rsaw_mapping *out, int32_t capacity, int32_t *count)
+{
+    g_last_error.clear();
+    if (!count) return fail(RSAW_E_INVALID, "count is NULL");
+    if (capacity < 0 || (capacity > 0 && !out)) return fail(RSAW_E_INVALID, "bad output array");
+    std::lock_guard<std::mutex> lk(g_map_lock);
+    *count = (int32_t)g_map.size();
+    const size_t n = std::min(g_map.size(), (size_t)capacity);
+    for (size_t i = 0; i < n; ++i) out[i] = g_map[i];
+    return RSAW_OK;
+}
+
 rsaw_status rsaw_mapping_query(const rsaw_config *cfg, rsaw_mapping *m)
 {
     g_last_error.clear();

@@ -98,3 +98,21 @@ def test_legal_mapping_at_n_hi_is_legal_below():
                     m = _q(geo, n, k)
                     assert (m["lanes"], m["threads"]) == (lanes, threads), (geo, n, lanes, threads)
                 rs.mapping_clear()
+
+
+def test_list_save_and_load_round_trip(tmp_path):
+    assert rs.mapping_list() == []
+    rs.mapping_set("lattice", 6, 65, 128, 32, 64)
+    rs.mapping_set("real", 16, 1, 100, 32, 256)
+    rs.mapping_set("lattice26", 26, 65, 256, 4, 64)
+    rows = rs.mapping_list()
+    assert [(m["geometry"], m["lanes"], m["threads"]) for m in rows] == [(0, 32, 64), (1, 32, 256), (2, 4, 64)]
+    path = tmp_path / "mappings.json"
+    assert rs.save_mappings(path) == 3
+    probes = [("lattice", 100, 6), ("real", 50, 16), ("lattice26", 200, 26), ("lattice", 300, 6)]
+    before = [_q(*p) for p in probes]
+    rs.mapping_clear()
+    assert rs.mapping_list() == []
+    assert rs.load_mappings(path) == 3
+    assert rs.mapping_list() == rows
+    assert [_q(*p) for p in probes] == before
