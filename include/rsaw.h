@@ -227,9 +227,13 @@ rsaw_status rsaw_gen_batch(const rsaw_config *cfgs, const rsaw_chain_out *outs, 
  * device bytes (26 B per chain plus 160 KiB each) fit in bytes_per_stream
  * and the batch holds at most max_batch requests.  It launches each batch
  * with rsaw_gen_batch on a free stream, so a new batch starts while others
- * run.  A completion thread per stream retires the batch's tickets.  Each
- * result is bit-identical to a stand-alone rsaw_gen_chains call with the
- * same configuration, whatever the mix it was served in.
+ * run.  With size classes (large_ms), at most one large request is in
+ * flight and a batch holds at most one, while small requests skip past
+ * queued large ones; the size estimate is a per-chain cost model (N^2 scan
+ * work, per geometry and k) used for scheduling only.  A completion thread
+ * per stream retires the batch's tickets.  Each result is bit-identical to
+ * a stand-alone rsaw_gen_chains call with the same configuration, whatever
+ * the mix it was served in.
  */
 typedef struct rsaw_server rsaw_server;
 
@@ -237,6 +241,11 @@ typedef struct {
     uint64_t bytes_per_stream; /* admission budget of one batch (default 2 GiB) */
     int32_t max_batch;         /* requests per batch, 1..4096 (default 256)     */
     int32_t streams;           /* concurrent batches, 1..16 (default 2)         */
+    double large_ms;           /* size classes: a request whose estimated time  */
+                               /* alone exceeds this is large, and large ones   */
+                               /* run one at a time, in arrival order, while    */
+                               /* small ones skip past them; 0 = 2 ms, < 0 =    */
+                               /* no classes (strict arrival order)             */
 } rsaw_server_params;
 
 /*

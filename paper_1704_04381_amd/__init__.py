@@ -60,7 +60,8 @@ SUMMARY_BYTES = C.sizeof(rsaw_summary)
 
 
 class rsaw_server_params(C.Structure):
-    _fields_ = [("bytes_per_stream", C.c_uint64), ("max_batch", C.c_int32), ("streams", C.c_int32)]
+    _fields_ = [("bytes_per_stream", C.c_uint64), ("max_batch", C.c_int32), ("streams", C.c_int32),
+                ("large_ms", C.c_double)]
 
 class rsaw_mapping(C.Structure):
     _fields_ = [("geometry", C.c_int32), ("k_trials", C.c_int32), ("n_lo", C.c_int32), ("n_hi", C.c_int32),
@@ -313,10 +314,10 @@ class Server:
     """Serving loop of librsaw (rsaw_server_*): submit ensembles, take their
     summaries.  Each result equals a stand-alone gen_chains call."""
 
-    def __init__(self, bytes_per_stream=2 << 30, max_batch=256, streams=2, device=0):
+    def __init__(self, bytes_per_stream=2 << 30, max_batch=256, streams=2, device=0, large_ms=0.0):
         lib = load()
         self._lib = lib
-        p = rsaw_server_params(int(bytes_per_stream), int(max_batch), int(streams))
+        p = rsaw_server_params(int(bytes_per_stream), int(max_batch), int(streams), float(large_ms))
         h = C.c_void_p()
         _check(lib.rsaw_server_create(C.byref(p), int(device), C.byref(h)))
         self._h = h

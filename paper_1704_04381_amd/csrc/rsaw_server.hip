@@ -9,6 +9,14 @@
 // fixed share) stay within the per-stream budget and the batch holds at most
 // max_batch requests.  A new batch starts on any free stream while others
 // run, so short requests arriving during a long batch do not wait for it.
+//
+// Size classes: a request whose estimated service time alone exceeds
+// large_ms is "large".  At most one large request is in flight at a time
+// (and a batch holds at most one): large requests run one after another in
+// arrival order, each sharing the GPU only with batches of small requests,
+// which skip past queued large ones.  Two large requests run side by side
+// would each take about twice as long, so the tail latency is set by
+// serving them in series, while the small ones keep the concurrency.
 // Every result is that of a stand-alone rsaw_gen_chains call (batched
 // growth and reduction are bit-identical to single calls).
 #include <hip/hip_runtime.h>
@@ -42,6 +50,7 @@ struct Ticket {
 };
 
 struct Slot {
+    bool large = false;             // the batch holds a large request
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     rsaw_summary *d_summ = nullptr; // max_batch summaries (device)
@@ -59,6 +68,19 @@ size_t request_bytes(const rsaw_config &c)
     return (size_t)c.n_chains * (3 * sizeof(double) + sizeof(uint16_t)) + (size_t)160 * 1024;
 }
 
+// Estimated growth time of a request alone on the device, in ms, for the
+// size classes only (it never affects a result).  A chain's scan work grows
+// as N^2; the constants are per-chain times at N = 64 on one MI355X: 0.2 ns
+// (lattice, registers), 0.65 ns (26-neighbour lattice), 1 ns per trial
+// (hard spheres), and 3x on the lattices beyond N = 64 (group kernels).
+double estimate_ms(const rsaw_config &c)
+{
+    const double n = c.n_monomers / 64.0;
+    double ns = c.geometry == RSAW_REAL_HS ? 1.0 * c.k_trials : (c.geometry == RSAW_LATTICE_26 ? 0.65 : 0.2);
+    if (c.geometry != RSAW_REAL_HS && c.n_monomers > 64) ns *= 3.0;
+    return (double)c.n_chains * ns * n * n * 1e-6;
+}
+
 } // namespace
 
 struct rsaw_server {
@@ -74,6 +96,9 @@ struct rsaw_server {
     std::vector<Slot> slots;
     std::thread scheduler;
     std::string error;
+
+    bool is_large(const rsaw_config &c) const { return p.large_ms >= 0.0 && estimate_ms(c) > large_ms(); }
+    double large_ms() const { return p.large_ms > 0.0 ? p.large_ms : 2.0; }
 
     void fail_batch(Slot &sl, rsaw_status st)
     {
@@ -94,8 +119,15 @@ struct rsaw_server {
             cv_sched.wait(lk, [&] {
                 if (stopping) return true;
                 if (queue.empty()) return false;
-                for (Slot &sl : slots)
-                    if (sl.tickets.empty()) return true;
+                bool free = false, large_busy = false;
+                for (Slot &sl : slots) {
+                    free = free || sl.tickets.empty();
+                    large_busy = large_busy || (!sl.tickets.empty() && sl.large);
+                }
+                if (!free) return false;
+                if (!large_busy) return true;
+                for (uint64_t t : queue)
+                    if (!is_large(tickets[t].cfg)) return true; // a small request can start
                 return false;
             });
             if (stopping && queue.empty()) break;
@@ -118,17 +150,30 @@ struct rsaw_server {
                     break;
                 }
             if (!free_slot) continue;
-            // admission from the queue head
+            // admission in arrival order; a large request only while no
+            // other large one is in flight or in this batch (it stays queued
+            // in order otherwise)
+            bool large_busy = false;
+            for (Slot &sl : slots) large_busy = large_busy || (!sl.tickets.empty() && sl.large);
             std::vector<uint64_t> batch;
             size_t bytes = 0;
-            while (!queue.empty() && (int)batch.size() < p.max_batch) {
-                const Ticket &tk = tickets[queue.front()];
+            bool batch_large = false;
+            for (auto it = queue.begin(); it != queue.end() && (int)batch.size() < p.max_batch;) {
+                const Ticket &tk = tickets[*it];
+                const bool large = is_large(tk.cfg);
+                if (large && (large_busy || batch_large)) {
+                    ++it;
+                    continue;
+                }
                 const size_t need = request_bytes(tk.cfg);
                 if (!batch.empty() && bytes + need > p.bytes_per_stream) break;
                 bytes += need;
-                batch.push_back(queue.front());
-                queue.pop_front();
+                batch_large = batch_large || large;
+                batch.push_back(*it);
+                it = queue.erase(it);
             }
+            if (batch.empty()) continue;
+            free_slot->large = batch_large;
             std::vector<rsaw_config> cfgs;
             const Clock::time_point now = Clock::now();
             for (uint64_t t : batch) {
@@ -198,6 +243,7 @@ rsaw_status rsaw_server_create(const rsaw_server_params *params, int32_t device,
     p.bytes_per_stream = (size_t)2 << 30;
     p.max_batch = 256;
     p.streams = 2;
+    p.large_ms = 0.0;
     if (params) p = *params;
     if (p.streams < 1 || p.streams > 16 || p.max_batch < 1 || p.max_batch > 4096 || p.bytes_per_stream == 0)
         return RSAW_E_INVALID;

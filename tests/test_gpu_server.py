@@ -44,6 +44,32 @@ def test_served_results_equal_single_calls():
         _equal(s, _alone(sp))
 
 
+@pytest.mark.parametrize("large_ms", [-1.0, 0.0, 1e-6, 0.5])
+def test_size_classes_keep_results_and_finish_every_request(large_ms):
+    # -1: no classes; 0: default threshold; 1e-6: every request large (one
+    # at a time, in arrival order); 0.5 ms: a mix of large and small
+    specs = mixed_ensembles(n=40, meta_seed=11, m_lo=2.0, m_span=3.0)
+    print(f"[gpu] server size classes, large_ms={large_ms}", flush=True)
+    import time
+
+    with rs.Server(max_batch=8, streams=3, large_ms=large_ms) as srv:
+        tickets, t_sub = [], []
+        for sp in specs:
+            t_sub.append(time.perf_counter() * 1e6)
+            tickets.append(srv.submit(**sp))
+        served = [srv.wait(t) for t in tickets]
+    for sp, s in zip(specs, served):
+        _equal(s, _alone(sp))
+    if large_ms == 1e-6:
+        # all large: each starts after the previous one finished (host
+        # clock, microseconds; the submission stamps differ by the time of
+        # one submit call)
+        starts = [t + s["queue_us"] for t, s in zip(t_sub, served)]
+        ends = [t + s["latency_us"] for t, s in zip(t_sub, served)]
+        for i in range(1, len(served)):
+            assert starts[i] >= ends[i - 1] - 200.0, i
+
+
 def test_same_request_in_different_mixes():
     probe = dict(geometry="lattice", N=48, k=6, n_chains=5_000, seed=777, coord="i32", hist_bins=0)
     with rs.Server(max_batch=8, streams=2) as srv:
