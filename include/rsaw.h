@@ -221,6 +221,41 @@ rsaw_status rsaw_gen_batch(const rsaw_config *cfgs, const rsaw_chain_out *outs, 
                            uint64_t *const *d_hist_n, void *stream);
 
 /*
+ * Planned batch — the batch of rsaw_gen_batch prepared once and launched
+ * any number of times, with launches that only enqueue kernels, so that a
+ * caller can record them into a HIP graph (stream capture) and replay it.
+ *
+ * rsaw_batch_plan_create validates as rsaw_gen_batch, then, synchronously
+ * and on the current device: allocates the plan's own device workspace
+ * (the reduction cells and partials, the per-chain arrays the reduction
+ * needs where outs gives none, the HBM bead planes of long hard-sphere
+ * chains, and the descriptor tables) and copies the tables into it.  Arguments
+ * as rsaw_gen_batch; the output pointers (outs, d_summaries, d_hist_w,
+ * d_hist_n) are recorded in the plan and must stay valid while it is
+ * launched.  *plan receives the handle.  Call it outside any stream capture.
+ * Errors: as rsaw_gen_batch; RSAW_E_INVALID for a NULL plan; RSAW_E_NOMEM
+ * if the workspace cannot be allocated.
+ *
+ * rsaw_batch_plan_launch enqueues the batch on `stream` (hipStream_t or
+ * NULL): one accumulator-clearing launch, one growth launch per kernel
+ * variant and the segmented reduction; no allocation, copy or memset.
+ * Every launch gives outputs bit-identical to rsaw_gen_batch with the same
+ * arguments.  Launches of one plan share its workspace: at most one may be
+ * in flight at a time.  RSAW_E_INVALID for a NULL plan or a current device
+ * other than the plan's; RSAW_E_DEVICE for a failed launch.
+ *
+ * rsaw_batch_plan_destroy frees the plan (its workspace, on its device)
+ * once no launch of it is pending; NULL is ignored.
+ */
+typedef struct rsaw_batch_plan rsaw_batch_plan;
+
+rsaw_status rsaw_batch_plan_create(const rsaw_config *cfgs, const rsaw_chain_out *outs, int32_t n,
+                                   rsaw_summary *d_summaries, double *const *d_hist_w,
+                                   uint64_t *const *d_hist_n, rsaw_batch_plan **plan);
+rsaw_status rsaw_batch_plan_launch(const rsaw_batch_plan *plan, void *stream);
+void rsaw_batch_plan_destroy(rsaw_batch_plan *plan);
+
+/*
  * Serving loop.  A server owns S HIP streams on one device and a scheduler
  * thread.  Each request is one ensemble (an rsaw_config).  The scheduler
  * forms batches from the head of the arrival queue while the requests'

@@ -74,7 +74,8 @@ EXPORTS = ["rsaw_gen_chains", "rsaw_gen_chains_sync", "rsaw_gen_batch", "rsaw_se
            "rsaw_status_string",
            "rsaw_last_error", "rsaw_version", "rsaw_kernel_timing", "rsaw_kernel_time",
            "rsaw_workspace_size", "rsaw_mapping_set", "rsaw_mapping_clear", "rsaw_mapping_list", "rsaw_mapping_query",
-           "rsaw_autotune", "rsaw_shutdown"]
+           "rsaw_autotune", "rsaw_batch_plan_create", "rsaw_batch_plan_launch", "rsaw_batch_plan_destroy",
+           "rsaw_shutdown"]
 
 _lib = None
 _lock = threading.Lock()
@@ -143,6 +144,13 @@ def load(path: str = LIB_PATH):
         lib.rsaw_autotune.argtypes = [C.POINTER(rsaw_config), C.POINTER(C.c_int32), C.c_int32, C.c_int32,
                                       C.POINTER(rsaw_mapping), C.POINTER(C.c_double), vp]
         lib.rsaw_autotune.restype = C.c_int
+        lib.rsaw_batch_plan_create.argtypes = [C.POINTER(rsaw_config), C.POINTER(rsaw_chain_out), C.c_int32,
+                                               vp, vp, vp, C.POINTER(vp)]
+        lib.rsaw_batch_plan_create.restype = C.c_int
+        lib.rsaw_batch_plan_launch.argtypes = [vp, vp]
+        lib.rsaw_batch_plan_launch.restype = C.c_int
+        lib.rsaw_batch_plan_destroy.argtypes = [vp]
+        lib.rsaw_batch_plan_destroy.restype = None
         _lib = lib
         return lib
 
@@ -308,6 +316,67 @@ def gen_batch(specs, *, per_chain=True, device=None, stream=None, sync=True):
             raise RsawError(s["status"], f"ensemble {i}: device reported a rejection-cap hit")
         res.append((out, s))
     return res
+
+
+class BatchPlan:
+    """A batch prepared once (rsaw_batch_plan_create) and launched any number
+    of times with kernel launches only (rsaw_batch_plan_launch), e.g. inside
+    a torch.cuda.graph capture.  ``specs`` as for ``gen_batch``; the outputs
+    are allocated here and rewritten by every launch."""
+
+    def __init__(self, specs, *, per_chain=True, device=None):
+        import torch
+
+        dev = _device(device)
+        self._lib = load()
+        cfgs, outs, self.outputs = [], [], []
+        for sp in specs:
+            sp = dict(sp)
+            bins = int(sp.get("hist_bins", 0))
+            cfg = make_config(sp.pop("geometry"), sp.pop("N"), sp.pop("k"), sp.pop("n_chains"),
+                              sp.pop("seed"), **sp)
+            out, o = _alloc_outputs(cfg, dev, per_chain, bins)
+            cfgs.append(cfg)
+            outs.append(o)
+            self.outputs.append(out)
+        n = len(cfgs)
+        self.n = n
+        self.summaries = torch.empty(max(n, 1) * SUMMARY_BYTES, dtype=torch.uint8, device=dev)
+        carr = (rsaw_config * max(n, 1))(*cfgs)
+        oarr = (rsaw_chain_out * max(n, 1))(*outs)
+        hw = (C.c_void_p * max(n, 1))(*[a["hist_w"].data_ptr() if "hist_w" in a else None for a in self.outputs])
+        hn = (C.c_void_p * max(n, 1))(*[a["hist_n"].data_ptr() if "hist_n" in a else None for a in self.outputs])
+        self._h = C.c_void_p()
+        with torch.cuda.device(dev):
+            _check(self._lib.rsaw_batch_plan_create(carr, oarr, n, C.c_void_p(self.summaries.data_ptr()),
+                                                    C.cast(hw, C.c_void_p), C.cast(hn, C.c_void_p),
+                                                    C.byref(self._h)))
+        self.device = dev
+
+    def launch(self, stream=None):
+        import torch
+
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+        _check(self._lib.rsaw_batch_plan_launch(self._h, C.c_void_p(stream)))
+
+    def results(self):
+        """(out, summary) per ensemble, after the last launch has finished."""
+        res = []
+        for i, out in enumerate(self.outputs):
+            res.append((out, parse_summary(self.summaries[i * SUMMARY_BYTES:(i + 1) * SUMMARY_BYTES])))
+        return res
+
+    def close(self):
+        if self._h:
+            self._lib.rsaw_batch_plan_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

@@ -436,11 +436,80 @@ hipError_t ensemble_variant(const rsaw_config *cfg, const EnsLayout &L, rsaw::Gr
     return rsaw::lattice_lds_variant(probe, i16, v);
 }
 
+// Everything the launches of a batch need once its tables are on the device:
+// the growth groups and the reduction's segment tables.
+struct BatchGroup {
+    rsaw::GrowVariant v;
+    int32_t first, cnt;
+    uint64_t blocks;
+    size_t shmem;
+    std::vector<rsaw::GrowArgs> hbm; // hard spheres with HBM planes: one grid per ensemble
+};
+struct BatchLaunch {
+    std::vector<BatchGroup> groups;
+    const rsaw::GrowEntry *d_gtab = nullptr;
+    const uint64_t *d_gb0 = nullptr;
+    const rsaw::ReduceEntry *d_rtab = nullptr;
+    const uint64_t *d_rb0 = nullptr;
+    int32_t n = 0;
+    uint64_t rb = 0;
+    int max_bins = 0;
+    bool reduce = false;
+};
+
+// Enqueues the batch's launches on s: zero the accumulators, one growth
+// launch per group, the segmented reduction.  Kernel launches only.
+rsaw_status run_batch(const BatchLaunch &B, hipStream_t s)
+{
+    if (B.n == 0) return RSAW_OK;
+    hipError_t e = rsaw::launch_reduce_batch(B.d_rtab, B.d_rb0, B.n, 0, 0, s, true);
+    if (e != hipSuccess) return hip_fail(e, "batched reduce_init launch");
+    for (const BatchGroup &G : B.groups) {
+        const rsaw::GrowVariant &v = G.v;
+        EventPair tp;
+        bool timed = false;
+        rsaw_status st = timing_start(s, &tp, &timed);
+        if (st != RSAW_OK) return st;
+        if (v.family == 2 && v.p1) {
+            for (size_t q = 0; q < G.hbm.size() && e == hipSuccess; ++q) e = rsaw::launch_grow_real(G.hbm[q], s);
+        } else if (v.family == 0)
+            e = rsaw::launch_lattice_reg_batch(v, B.d_gtab + G.first, B.d_gb0 + G.first, G.cnt, G.blocks, s);
+        else if (v.family == 1)
+            e = rsaw::launch_lattice_lds_batch(v, B.d_gtab + G.first, B.d_gb0 + G.first, G.cnt, G.blocks, G.shmem,
+                                               s);
+        else if (v.family == 3)
+            e = rsaw::launch_lattice26_batch(v, B.d_gtab + G.first, B.d_gb0 + G.first, G.cnt, G.blocks, G.shmem, s);
+        else
+            e = rsaw::launch_real_batch(v, B.d_gtab + G.first, B.d_gb0 + G.first, G.cnt, G.blocks, G.shmem, s);
+        if (timed) {
+            st = timing_stop(s, tp);
+            if (st != RSAW_OK) return st;
+        }
+        if (e != hipSuccess) return hip_fail(e, "batched grow kernel launch");
+    }
+    if (B.reduce) {
+        e = rsaw::launch_reduce_batch(B.d_rtab, B.d_rb0, B.n, B.rb, B.max_bins, s, false);
+        if (e != hipSuccess) return hip_fail(e, "batched reduce kernel launch");
+    }
+    return RSAW_OK;
+}
+
+// A batch prepared once (own workspace, tables already on the device) and
+// launched any number of times, e.g. inside a HIP graph capture.
+struct PlannedBatch {
+    int dev = 0;
+    void *ws = nullptr;
+    BatchLaunch B;
+};
+
 // Batched body: every ensemble's growth shares one launch per kernel
 // variant, and the reductions three launches in all.
+// With `plan` set, nothing is enqueued: the workspace is the plan's own
+// allocation, the tables are copied synchronously, and the launch
+// description goes to *plan.
 rsaw_status batch_impl(const rsaw_config *cfgs, const rsaw_chain_out *outs, int32_t n,
                        rsaw_summary *d_summaries, double *const *d_hist_w, uint64_t *const *d_hist_n,
-                       void *stream)
+                       void *stream, PlannedBatch *plan = nullptr)
 {
     g_last_error.clear();
     if (n < 0) return fail(RSAW_E_INVALID, "n must be >= 0");
@@ -509,13 +578,24 @@ rsaw_status batch_impl(const rsaw_config *cfgs, const rsaw_chain_out *outs, int3
     const size_t off_end = align256(off_rb0 + (size_t)(n + 1) * sizeof(uint64_t));
     const size_t tab_bytes = off_end - off_gtab;
     void *wsv = nullptr;
-    rsaw_status st = workspace(dev, s, off_end, &wsv);
-    if (st != RSAW_OK) return st;
-    char *ws = (char *)wsv;
+    rsaw_status st = RSAW_OK;
+    std::vector<char> plan_stage;
     void *stv = nullptr;
     hipEvent_t stage_done = nullptr;
-    st = staging(dev, s, tab_bytes, &stv, &stage_done);
-    if (st != RSAW_OK) return st;
+    if (plan) {
+        e = hipMalloc(&wsv, off_end);
+        if (e != hipSuccess) return fail(RSAW_E_NOMEM, std::string("plan hipMalloc: ") + hipGetErrorString(e));
+        plan->dev = dev;
+        plan->ws = wsv;
+        plan_stage.resize(tab_bytes);
+        stv = plan_stage.data();
+    } else {
+        st = workspace(dev, s, off_end, &wsv);
+        if (st != RSAW_OK) return st;
+        st = staging(dev, s, tab_bytes, &stv, &stage_done);
+        if (st != RSAW_OK) return st;
+    }
+    char *ws = (char *)wsv;
     char *stage = (char *)stv;
     rsaw::GrowEntry *gtab = (rsaw::GrowEntry *)(stage + (off_gtab - off_gtab));
     uint64_t *gb0 = (uint64_t *)(stage + (off_gb0 - off_gtab));
@@ -561,47 +641,45 @@ rsaw_status batch_impl(const rsaw_config *cfgs, const rsaw_chain_out *outs, int3
     }
     rb0[n] = rb;
 
-    e = hipMemcpyAsync(ws + off_gtab, stage, tab_bytes, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return hip_fail(e, "batch table copy");
-    e = hipEventRecord(stage_done, s);
-    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    if (plan) {
+        e = hipMemcpy(ws + off_gtab, stage, tab_bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "plan table copy");
+    } else {
+        e = hipMemcpyAsync(ws + off_gtab, stage, tab_bytes, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "batch table copy");
+        e = hipEventRecord(stage_done, s);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    }
     const rsaw::GrowEntry *d_gtab = (const rsaw::GrowEntry *)(ws + off_gtab);
     const uint64_t *d_gb0 = (const uint64_t *)(ws + off_gb0);
     const rsaw::ReduceEntry *d_rtab = (const rsaw::ReduceEntry *)(ws + off_rtab);
     const uint64_t *d_rb0 = (const uint64_t *)(ws + off_rb0);
 
-    e = rsaw::launch_reduce_batch(d_rtab, d_rb0, n, 0, 0, s, true);
-    if (e != hipSuccess) return hip_fail(e, "batched reduce_init launch");
+    BatchLaunch B;
+    B.d_gtab = d_gtab;
+    B.d_gb0 = d_gb0;
+    B.d_rtab = d_rtab;
+    B.d_rb0 = d_rb0;
+    B.n = n;
+    B.rb = rb;
+    B.max_bins = max_bins;
+    B.reduce = reduce;
     for (const Group &G : groups) {
-        const rsaw::GrowVariant &v = var[order[G.first]];
-        const int32_t cnt = G.last - G.first;
-        EventPair tp;
-        bool timed = false;
-        st = timing_start(s, &tp, &timed);
-        if (st != RSAW_OK) return st;
-        if (v.family == 2 && v.p1) {
-            // HBM planes: each ensemble runs its own persistent grid
-            for (int32_t q = G.first; q < G.last && e == hipSuccess; ++q)
-                e = rsaw::launch_grow_real(gtab[q].a, s);
-        } else if (v.family == 0)
-            e = rsaw::launch_lattice_reg_batch(v, d_gtab + G.first, d_gb0 + G.first, cnt, G.blocks, s);
-        else if (v.family == 1)
-            e = rsaw::launch_lattice_lds_batch(v, d_gtab + G.first, d_gb0 + G.first, cnt, G.blocks, G.shmem, s);
-        else if (v.family == 3)
-            e = rsaw::launch_lattice26_batch(v, d_gtab + G.first, d_gb0 + G.first, cnt, G.blocks, G.shmem, s);
-        else
-            e = rsaw::launch_real_batch(v, d_gtab + G.first, d_gb0 + G.first, cnt, G.blocks, G.shmem, s);
-        if (timed) {
-            st = timing_stop(s, tp);
-            if (st != RSAW_OK) return st;
-        }
-        if (e != hipSuccess) return hip_fail(e, "batched grow kernel launch");
+        BatchGroup g;
+        g.v = var[order[G.first]];
+        g.first = G.first;
+        g.cnt = G.last - G.first;
+        g.blocks = G.blocks;
+        g.shmem = G.shmem;
+        if (g.v.family == 2 && g.v.p1)
+            for (int32_t q = G.first; q < G.last; ++q) g.hbm.push_back(gtab[q].a);
+        B.groups.push_back(std::move(g));
     }
-    if (reduce) {
-        e = rsaw::launch_reduce_batch(d_rtab, d_rb0, n, rb, max_bins, s, false);
-        if (e != hipSuccess) return hip_fail(e, "batched reduce kernel launch");
+    if (plan) {
+        plan->B = std::move(B);
+        return RSAW_OK;
     }
-    return RSAW_OK;
+    return run_batch(B, s);
 }
 
 } // namespace
@@ -716,6 +794,54 @@ rsaw_status rsaw_gen_batch(const rsaw_config *cfgs, const rsaw_chain_out *outs, 
                            uint64_t *const *d_hist_n, void *stream)
 {
     return batch_impl(cfgs, outs, n, d_summaries, d_hist_w, d_hist_n, stream);
+}
+
+struct rsaw_batch_plan {
+    PlannedBatch p;
+};
+
+rsaw_status rsaw_batch_plan_create(const rsaw_config *cfgs, const rsaw_chain_out *outs, int32_t n,
+                                   rsaw_summary *d_summaries, double *const *d_hist_w,
+                                   uint64_t *const *d_hist_n, rsaw_batch_plan **plan)
+{
+    g_last_error.clear();
+    if (!plan) return fail(RSAW_E_INVALID, "plan is NULL");
+    *plan = nullptr;
+    rsaw_batch_plan *pl = new rsaw_batch_plan();
+    const rsaw_status st = batch_impl(cfgs, outs, n, d_summaries, d_hist_w, d_hist_n, nullptr, &pl->p);
+    if (st != RSAW_OK) {
+        if (pl->p.ws) (void)hipFree(pl->p.ws);
+        delete pl;
+        return st;
+    }
+    if (!pl->p.ws) (void)hipGetDevice(&pl->p.dev); // n = 0: nothing to launch
+    *plan = pl;
+    return RSAW_OK;
+}
+
+rsaw_status rsaw_batch_plan_launch(const rsaw_batch_plan *plan, void *stream)
+{
+    g_last_error.clear();
+    if (!plan) return fail(RSAW_E_INVALID, "plan is NULL");
+    int dev = 0;
+    const hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != plan->p.dev)
+        return fail(RSAW_E_INVALID, "the plan was created on device " + std::to_string(plan->p.dev));
+    return run_batch(plan->p.B, (hipStream_t)stream);
+}
+
+void rsaw_batch_plan_destroy(rsaw_batch_plan *plan)
+{
+    if (!plan) return;
+    if (plan->p.ws) {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(plan->p.dev);
+        (void)hipFree(plan->p.ws);
+        (void)hipSetDevice(cur);
+    }
+    delete plan;
 }
 
 const char *rsaw_status_string(rsaw_status s)

@@ -78,3 +78,70 @@ def test_captured_calls_replay_bit_identically():
                 np.testing.assert_array_equal(o_got[k], o_ref[k], err_msg=f"replay {rep} call {i} {k}")
             np.testing.assert_array_equal(s_got, s_ref, err_msg=f"replay {rep} call {i} summary")
     del g
+
+
+BATCH = [dict(geometry="lattice", N=16, k=6, n_chains=30_000, seed=11, coord="i32", exact_w=True, hist_bins=8),
+         dict(geometry="lattice", N=100, k=6, n_chains=20_000, seed=12, coord="i16", hist_bins=64),
+         dict(geometry="real", N=64, k=8, n_chains=10_000, seed=13, hist_bins=16),
+         dict(geometry="real", N=1800, k=8, n_chains=40, seed=14),
+         dict(geometry="lattice26", N=200, k=26, n_chains=5_000, seed=15, coord="i32"),
+         dict(geometry="lattice", N=33, k=6, n_chains=0, seed=16, coord="i32", hist_bins=4)]
+
+
+def _plan_snapshot(plan):
+    return [({k: v.cpu().numpy().copy() for k, v in out.items()}, plan.summaries.cpu().numpy().copy())
+            for out in plan.outputs]
+
+
+def test_batch_plan_equals_gen_batch_and_replays_in_a_graph():
+    dev = torch.device("cuda", 0)
+    print("[gpu] batch plan: eager gen_batch reference", flush=True)
+    ref = rs.gen_batch(BATCH)
+    torch.cuda.synchronize()
+    ref = [({k: v.cpu().numpy() for k, v in out.items()}, s) for out, s in ref]
+    plan = rs.BatchPlan(BATCH)
+    side = torch.cuda.Stream(device=dev)
+
+    def check(tag):
+        for i, ((o_ref, s_ref), (o_got, s_got)) in enumerate(zip(ref, plan.results())):
+            for k in o_ref:
+                np.testing.assert_array_equal(o_got[k].cpu().numpy(), o_ref[k], err_msg=f"{tag} ensemble {i} {k}")
+            for k, v in s_ref.items():
+                w = s_got[k]
+                assert w == v or (v != v and w != w), (tag, i, k, v, w)
+
+    print("[gpu] batch plan: eager launches", flush=True)
+    for rep in range(2):
+        with torch.cuda.stream(side):
+            plan.launch(side.cuda_stream)
+        torch.cuda.synchronize()
+        check(f"eager {rep}")
+
+    g = torch.cuda.CUDAGraph()
+    print("[gpu] batch plan: capture", flush=True)
+    with torch.cuda.graph(g, stream=side):
+        plan.launch(side.cuda_stream)
+    torch.cuda.synchronize()
+    other = _prepare(dev)
+    for rep in range(3):
+        for out in plan.outputs:
+            for v in out.values():
+                v.zero_()
+        plan.summaries.zero_()
+        _launch(other, torch.cuda.current_stream(dev).cuda_stream)  # eager work between replays
+        torch.cuda.synchronize()
+        print(f"[gpu] batch plan: replay {rep}", flush=True)
+        g.replay()
+        torch.cuda.synchronize()
+        check(f"replay {rep}")
+    del g
+    plan.close()
+
+
+def test_batch_plan_argument_errors():
+    with pytest.raises(rs.RsawError):
+        rs.BatchPlan([dict(geometry="lattice", N=70000, k=6, n_chains=10, seed=1)])
+    empty = rs.BatchPlan([])
+    empty.launch()
+    torch.cuda.synchronize()
+    empty.close()
