@@ -80,6 +80,31 @@ def lattice_alg_ops_per_chain(N: int) -> int:
     return sum(4 * (i // 2) + 8 + 10 for i in range(1, N))
 
 
+# LDS bandwidth of the chip: 128 bytes per clock per CU, 256 CUs, 2.4 GHz.
+LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12
+
+
+def real_lds_bytes_per_chain(N: int) -> int:
+    """Algorithmic LDS bytes of one hard-sphere chain (beads as three
+    binary64 planes).  Per step i the culling pass reads beads 0..i-4 once
+    (24 B each), the two beads next to the tip are read once (their loads
+    are broadcast to the trial lanes) and the new bead is written (24 B)."""
+    return sum(24 * max(i - 3, 0) + 24 * min(max(i - 1, 0), 2) + 24 for i in range(1, N))
+
+
+def lattice26_lds_bytes_per_chain(N: int) -> int:
+    """Algorithmic LDS bytes of one 26-neighbour chain (one 4-byte word per
+    monomer): per step i every earlier monomer but the predecessor is read
+    once and the new monomer is written."""
+    return sum(4 * max(i - 1, 0) + 4 for i in range(1, N))
+
+
+def lds_object(bytes_per_launch: float, kernel_ms: float, note: str) -> dict:
+    ach = bytes_per_launch / (kernel_ms / 1e3) / 1e12
+    return {"bytes_per_launch": bytes_per_launch, "achieved": ach, "peak": LDS_PEAK_TBS, "unit": "TB/s",
+            "frac": ach / LDS_PEAK_TBS, "model": note}
+
+
 def real_alg_ops_per_chain(N: int, k: int) -> float:
     """Algorithmic VALU lane-operations to grow one hard-sphere chain.
 
@@ -469,6 +494,9 @@ def main():
                                  measured_traffic("grow_real_tp", "grow_real.hip", args.workload)),
                      "kernel": "grow_lattice_reg" if w["geometry"] == "lattice" else "grow_real_tp",
                      "kernel_ms": r["grow_ms"], "alg_ops_per_launch": alg_ops},
+        "lds": (lds_object(0.0, r["grow_ms"], "chain history in VGPRs: no LDS traffic")
+                if lattice else
+                lds_object(real_lds_bytes_per_chain(N) * M, r["grow_ms"], "beads read once per step")),
         "physics": {k: r["summary"][k] for k in ("n_alive", "log_c_est", "r2_mean", "r2_err",
                                                  "rg2_mean", "rg2_err", "ess")},
     }
@@ -491,6 +519,10 @@ def main():
                                      if w2["geometry"] == "lattice" else
                                      measured_traffic("grow_real_tp", "grow_real.hip", args.secondary)),
                          "kernel_ms": r2["grow_ms"], "alg_ops_per_launch": ops2},
+            "lds": (lds_object(0.0, r2["grow_ms"], "chain history in VGPRs: no LDS traffic")
+                    if w2["geometry"] == "lattice" else
+                    lds_object(real_lds_bytes_per_chain(w2["N"]) * w2["n_chains"], r2["grow_ms"],
+                               "beads read once per step")),
             "physics": {k: r2["summary"][k] for k in ("n_alive", "log_c_est", "r2_mean",
                                                       "r2_err", "rg2_mean", "rg2_err")},
         }
@@ -513,6 +545,8 @@ def main():
                                                      args.variant),
                          "kernel": "grow_lattice26_lane",
                          "kernel_ms": r3["grow_ms"], "alg_ops_per_launch": ops3},
+            "lds": lds_object(lattice26_lds_bytes_per_chain(w3["N"]) * w3["n_chains"], r3["grow_ms"],
+                              "monomer words read once per step"),
             "physics": {k: r3["summary"][k] for k in ("n_alive", "log_c_est", "r2_mean",
                                                       "r2_err", "rg2_mean", "rg2_err")},
         }

@@ -63,3 +63,19 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_lds_models():
+    import bench
+    # hard spheres: steps 1, 2, 3 move 24, 48 and 72 bytes (write; one near
+    # bead; two near beads), step 4 also culls bead 0
+    assert bench.real_lds_bytes_per_chain(2) == 24
+    assert bench.real_lds_bytes_per_chain(4) == 24 + 48 + 72
+    assert bench.real_lds_bytes_per_chain(5) == 24 + 48 + 72 + 96
+    # 26-neighbour lattice: (i - 1) words read and one written per step
+    assert bench.lattice26_lds_bytes_per_chain(4) == 4 + 8 + 12
+    N = 64
+    assert bench.lattice26_lds_bytes_per_chain(N) == 4 * (N - 1) * N // 2
+    assert abs(bench.LDS_PEAK_TBS - 78.6432) < 1e-9
+    o = bench.lds_object(1e12, 1000.0, "x")
+    assert abs(o["achieved"] - 1.0) < 1e-12 and abs(o["frac"] - 1.0 / bench.LDS_PEAK_TBS) < 1e-12
