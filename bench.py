@@ -196,8 +196,24 @@ def run_gpu(w, steps, warmup, torch, rs):
     summary = rs.parse_summary(summ)
     if summary["status"] != 0:
         raise RuntimeError(f"device status {summary['status']}")
+    # end to end on the host clock: enqueue, then the summary's copy to the
+    # host and the wait for it (outside the timed region above)
+    e2e = []
+    for _ in range(3):
+        t1 = time.perf_counter()
+        step()
+        summ.cpu()
+        e2e.append((time.perf_counter() - t1) * 1e3)
 
-    return dict(wall=wall, lat=lat, summary=summary, grow_ms=k_ms / k_n)
+    return dict(wall=wall, lat=lat, summary=summary, grow_ms=k_ms / k_n, e2e_ms=_percentile(e2e, 0.5))
+
+
+def device_info(torch) -> dict:
+    """Name, architecture, CU count and memory of device 0 as HIP reports
+    them."""
+    p = torch.cuda.get_device_properties(0)
+    return {"name": p.name, "arch": getattr(p, "gcnArchName", ""), "cus": p.multi_processor_count,
+            "hbm_bytes": p.total_memory, "l2_bytes": getattr(p, "L2_cache_size", None)}
 
 
 def run_batch(torch, rs, reps, m_lo=3.0, m_span=3.0):
@@ -477,6 +493,7 @@ def main():
         "ms_per_step": T * 1e3 / args.steps,
         "p50_ms": _percentile(r["lat"], 0.5),
         "p99_ms": _percentile(r["lat"], 0.99),
+        "end_to_end_ms": r["e2e_ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -499,6 +516,7 @@ def main():
                 lds_object(real_lds_bytes_per_chain(N) * M, r["grow_ms"], "beads read once per step")),
         "physics": {k: r["summary"][k] for k in ("n_alive", "log_c_est", "r2_mean", "r2_err",
                                                  "rg2_mean", "rg2_err", "ess")},
+        "device": device_info(torch),
     }
     if args.secondary:
         w2 = WORKLOADS[args.secondary]
