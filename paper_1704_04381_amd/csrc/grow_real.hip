@@ -515,6 +515,16 @@ hipError_t real_variant(const GrowArgs &a, GrowVariant *v)
     const int occ = (3 * N + 39) / 40; // ceil(0.075 N)
     if (occ > need) need = occ;
     const int G = need <= 8 ? 8 : (need <= 16 ? 16 : (need <= 32 ? 32 : 64));
+    // k = 8 with 16 lanes in 256-thread blocks whose planes leave fewer than
+    // 3 blocks per CU: 32 lanes in one-wave blocks are faster (the extra
+    // lanes also carry the round-1 Marsaglia attempts); measured on MI355X
+    // for 144 <= N <= 208, 1.18-1.22x.
+    GrowVariant wide, at256;
+    if (a.k_trials == 8 && G == 16 && real_shape(N, 8, 16, 256, &at256) == hipSuccess &&
+        at256.shmem > 163840 / 3 && real_shape(N, 8, 32, 64, &wide) == hipSuccess) {
+        *v = wide;
+        return hipSuccess;
+    }
     GrowVariant half_cu;
     if (G != 64 && real_shape(N, a.k_trials, G, 256, &half_cu) == hipSuccess && half_cu.shmem <= 81920) {
         *v = half_cu;

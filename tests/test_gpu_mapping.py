@@ -155,3 +155,15 @@ def test_autotune_argument_errors():
         with pytest.raises(rs.RsawError):
             rs.autotune("lattice", 6, edges, 100, reps=reps)
     assert rs.mapping_query(rs.make_config("lattice", 100, 6, 100, 1))["lanes"] == 4  # nothing installed
+
+
+def test_hard_sphere_rule_window_matches_the_oracle():
+    # k = 8, 144 <= N <= 213: the built-in rule takes 32 lanes in one-wave blocks
+    for N, M, seed in ((150, 300, 51), (213, 200, 52)):
+        m = rs.mapping_query(rs.make_config("real", N, 8, M, seed))
+        assert (m["lanes"], m["threads"]) == (32, 64)
+        print(f"[gpu] hard-sphere rule window N={N}", flush=True)
+        out, _ = _run("real", N, 8, M, seed)
+        ref = oracle.gen_real(seed, N, 8, M)
+        for key in ("log_w", "r2", "rg2", "n_grown"):
+            np.testing.assert_array_equal(out[key], ref[key], err_msg=f"N={N} {key}")

@@ -34,6 +34,12 @@ def test_builtin_rule():
     assert [_q("lattice26", n, 26)["lanes"] for n in (65, 160, 161, 400, 800, 1600)] == [4, 4, 8, 16, 32, 64]
     assert _q("real", 64, 8)["lanes"] == 8 and _q("real", 64, 16)["lanes"] == 16
     assert _q("real", 300, 8)["lanes"] == 32  # 0.075 N = 22.5 -> 32
+    # k = 8: 16 lanes while a 256-thread block leaves 3 blocks per CU, then
+    # 32 lanes in one-wave blocks
+    assert (_q("real", 128, 8)["lanes"], _q("real", 128, 8)["threads"]) == (16, 256)
+    for n in (144, 192, 213):
+        assert (_q("real", n, 8)["lanes"], _q("real", n, 8)["threads"]) == (32, 64), n
+    assert (_q("real", 192, 16)["lanes"], _q("real", 192, 16)["threads"]) == (16, 256)
     # beyond N = 1536 hard-sphere planes live in HBM
     m = _q("real", 3000, 8)
     assert m["lanes"] == 64 and m["threads"] == 64 and m["lds_bytes"] == 0
