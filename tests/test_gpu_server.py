@@ -62,12 +62,12 @@ def test_size_classes_keep_results_and_finish_every_request(large_ms):
         _equal(s, _alone(sp))
     if large_ms == 1e-6:
         # all large: each starts after the previous one finished (host
-        # clock, microseconds; the submission stamps differ by the time of
-        # one submit call)
+        # clock, microseconds; the Python and library submission stamps
+        # differ by the time of one submit call, hence the slack)
         starts = [t + s["queue_us"] for t, s in zip(t_sub, served)]
         ends = [t + s["latency_us"] for t, s in zip(t_sub, served)]
         for i in range(1, len(served)):
-            assert starts[i] >= ends[i - 1] - 200.0, i
+            assert starts[i] >= ends[i - 1] - 1000.0, i
 
 
 def test_same_request_in_different_mixes():
