@@ -515,13 +515,15 @@ hipError_t real_variant(const GrowArgs &a, GrowVariant *v)
     const int occ = (3 * N + 39) / 40; // ceil(0.075 N)
     if (occ > need) need = occ;
     const int G = need <= 8 ? 8 : (need <= 16 ? 16 : (need <= 32 ? 32 : 64));
-    // k = 8 with 16 lanes in 256-thread blocks whose planes leave fewer than
-    // 3 blocks per CU: 32 lanes in one-wave blocks are faster (the extra
-    // lanes also carry the round-1 Marsaglia attempts); measured on MI355X
-    // for 144 <= N <= 208, 1.18-1.22x.
+    // k = 8 or 16 with 2k lanes in 256-thread blocks whose planes leave
+    // fewer than 3 blocks per CU: 4k lanes in one-wave blocks are faster
+    // (the extra lanes also carry the round-1 Marsaglia attempts); measured
+    // on MI355X: k = 8, 144 <= N <= 208, 1.18-1.22x; k = 16, 320 <= N <= 416,
+    // 1.13-1.20x.
+    const int k = a.k_trials;
     GrowVariant wide, at256;
-    if (a.k_trials == 8 && G == 16 && real_shape(N, 8, 16, 256, &at256) == hipSuccess &&
-        at256.shmem > 163840 / 3 && real_shape(N, 8, 32, 64, &wide) == hipSuccess) {
+    if ((k == 8 || k == 16) && G == 2 * k && real_shape(N, k, G, 256, &at256) == hipSuccess &&
+        at256.shmem > 163840 / 3 && real_shape(N, k, 4 * k, 64, &wide) == hipSuccess) {
         *v = wide;
         return hipSuccess;
     }

@@ -159,11 +159,12 @@ def test_autotune_argument_errors():
 
 def test_hard_sphere_rule_window_matches_the_oracle():
     # k = 8, 144 <= N <= 213: the built-in rule takes 32 lanes in one-wave blocks
-    for N, M, seed in ((150, 300, 51), (213, 200, 52)):
-        m = rs.mapping_query(rs.make_config("real", N, 8, M, seed))
-        assert (m["lanes"], m["threads"]) == (32, 64)
-        print(f"[gpu] hard-sphere rule window N={N}", flush=True)
-        out, _ = _run("real", N, 8, M, seed)
-        ref = oracle.gen_real(seed, N, 8, M)
+    # k = 16, 285 <= N <= 426: 64 lanes in one-wave blocks
+    for N, k, M, seed, lanes in ((150, 8, 300, 51, 32), (213, 8, 200, 52, 32), (300, 16, 60, 53, 64)):
+        m = rs.mapping_query(rs.make_config("real", N, k, M, seed))
+        assert (m["lanes"], m["threads"]) == (lanes, 64)
+        print(f"[gpu] hard-sphere rule window N={N} k={k}", flush=True)
+        out, _ = _run("real", N, k, M, seed)
+        ref = oracle.gen_real(seed, N, k, M)
         for key in ("log_w", "r2", "rg2", "n_grown"):
             np.testing.assert_array_equal(out[key], ref[key], err_msg=f"N={N} {key}")

@@ -40,6 +40,12 @@ def test_builtin_rule():
     for n in (144, 192, 213):
         assert (_q("real", n, 8)["lanes"], _q("real", n, 8)["threads"]) == (32, 64), n
     assert (_q("real", 192, 16)["lanes"], _q("real", 192, 16)["threads"]) == (16, 256)
+    # k = 16: 32 lanes in 256-thread blocks up to N = 284, then 64 lanes
+    # in one-wave blocks while the occupancy term asks for 32
+    assert (_q("real", 256, 16)["lanes"], _q("real", 256, 16)["threads"]) == (32, 256)
+    for n in (285, 384, 426):
+        assert (_q("real", n, 16)["lanes"], _q("real", n, 16)["threads"]) == (64, 64), n
+    assert (_q("real", 106, 4)["lanes"], _q("real", 106, 4)["threads"]) == (8, 256)  # k = 4 unchanged
     # beyond N = 1536 hard-sphere planes live in HBM
     m = _q("real", 3000, 8)
     assert m["lanes"] == 64 and m["threads"] == 64 and m["lds_bytes"] == 0
