@@ -161,3 +161,20 @@ def test_workspace_size_query_on_host():
     assert e.value.status == 1
     lib = rs.load()
     assert lib.rsaw_workspace_size(C.byref(cfg), None, 1, None) == 1
+
+
+def test_header_is_plain_c99(tmp_path):
+    """include/rsaw.h compiles as strict C99 (no C++ or torch types leak into
+    the boundary)."""
+    import shutil
+    import subprocess
+
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    src = tmp_path / "use_header.c"
+    src.write_text('#include "rsaw.h"\nint main(void) { rsaw_config c; rsaw_mapping m; (void)c; (void)m; return 0; }\n')
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    r = subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-fsyntax-only", "-I", inc,
+                        str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
