@@ -170,6 +170,34 @@ def test_real_long_chains(N, k, M, seed, sigma):
     assert exact
 
 
+@pytest.mark.parametrize("N,k,M,seed,offset,sigma", [
+    # chain index g = offset + c keys every Philox counter (Sec. 3.2: one
+    # independent stream per chain).  G = 8 lanes for k = 8: the wave-wide
+    # helper round of the Marsaglia draws (lanes serving other chains'
+    # failed trials) runs at most steps and recomputes the owner's g
+    (64, 8, 1_500, 61, (1 << 32) + 5, 1.0), (64, 8, 700, 62, 4_321, 1.0),
+    (33, 16, 400, 63, (1 << 40) + 3, 1.0),
+    # G = 32 with round-1 attempts spread over spare lanes (k = 5)
+    (300, 5, 90, 64, (1 << 32) + 5, 1.0), (300, 5, 90, 65, 4_321, 1.0),
+    # one chain per wave (G = 64), and HBM-resident bead planes
+    (700, 8, 20, 66, (1 << 32) + 5, 1.0), (2_048, 8, 5, 67, (1 << 32) + 5, 0.5)])
+def test_real_chain_offset_bit_exact(N, k, M, seed, offset, sigma):
+    _, _, exact = _real_case(N, k, M, seed, sigma=sigma, bins=32, offset=offset)
+    assert exact
+
+
+def test_real_split_ranges_equal_one_launch():
+    """Hard spheres: two calls over [0, a) and [a, M) (chain_offset = a)
+    give the chains of one call over [0, M), bit for bit."""
+    M, a = 3_000, 1_234
+    full, _ = _gpu("real", 64, 8, M, 23)
+    x, _ = _gpu("real", 64, 8, a, 23)
+    y, _ = _gpu("real", 64, 8, M - a, 23, chain_offset=a)
+    for key in ("log_w", "r2", "rg2", "n_grown"):
+        np.testing.assert_array_equal(np.concatenate([x[key], y[key]]), full[key])
+    np.testing.assert_array_equal(np.concatenate([x["r_end"], y["r_end"]], axis=1), full["r_end"])
+
+
 @pytest.mark.parametrize("N,M,seed,coord,exact", [(64, 20_000, 31, "i16", False), (28, 5_000, 32, "i32", True),
                                                   (200, 500, 33, "i32", False), (2_049, 40, 34, "i16", False)])
 def test_lattice_restart_bit_exact(N, M, seed, coord, exact):
@@ -268,6 +296,10 @@ def test_headline_lattice_n64_sampled():
 
 
 def test_headline_real_n64_sampled():
+    """Full-size hard-sphere workload: sampled chains against the oracle
+    chain by chain, bit for bit (log W, R^2, Rg^2, end vector, monomers
+    placed), and the full reduction against the oracle's reduction of the
+    same per-chain outputs."""
     w = WORKLOADS["real_n64"]
     out, s = _gpu(w["geometry"], w["N"], w["k"], w["n_chains"], w["seed"],
                   bond_length=w["bond_length"], bead_diameter=w["bead_diameter"],
@@ -276,17 +308,16 @@ def test_headline_real_n64_sampled():
     idx = _sampled_indices(M, 400, 98)
     for c in idx:
         ch = oracle.real_chain(w["seed"], int(c), N, k)
-        assert int(out["n_grown"].view(np.uint16)[c]) == ch["n_grown"]
-        if math.isfinite(ch["log_w"]):
-            assert abs(out["log_w"][c] - ch["log_w"]) <= RTOL_REAL * ch["log_w"]
-        else:
-            assert out["log_w"][c] == -math.inf
-        assert abs(out["r2"][c] - ch["r2"]) <= RTOL_REAL * ch["r2"]
-        assert abs(out["rg2"][c] - ch["rg2"]) <= RTOL_REAL * ch["rg2"]
+        assert int(out["n_grown"].view(np.uint16)[c]) == ch["n_grown"], c
+        assert out["log_w"][c] == ch["log_w"], c
+        assert out["r2"][c] == ch["r2"], c
+        assert out["rg2"][c] == ch["rg2"], c
+        assert tuple(float(v) for v in out["r_end"][:, c]) == tuple(float(v) for v in ch["end"]), c
     red = oracle.reduce(N, out["log_w"], out["r2"], out["rg2"],
                         out["n_grown"].view(np.uint16).astype(np.int32), bins=w["hist_bins"])
     _check_summary(s, red, M)
     np.testing.assert_array_equal(out["hist_n"], red["hist_n"])
+    np.testing.assert_allclose(out["hist_w"], red["hist_w"], rtol=RTOL_SUM, atol=0)
 
 
 def test_headline_lattice_n16_full():
@@ -294,20 +325,25 @@ def test_headline_lattice_n16_full():
     _lattice_case(w["N"], w["n_chains"], w["seed"], coord=w["coord"], exact_w=True)
 
 
-def test_ensemble_averages_agree_within_3_sigma():
-    """Independent seeds: GPU and oracle ensembles are statistically equal."""
-    _, g = _gpu("real", 32, 8, 200_000, 31)
-    ref = oracle.gen_real(32, 32, 8, 40_000)
-    r = oracle.reduce(32, ref["log_w"], ref["r2"], ref["rg2"], ref["n_grown"])
-    for key in ("r2", "rg2"):
+def _within_3_sigma(g, r, keys=("r2", "rg2")):
+    for key in keys:
         d = g[f"{key}_mean"] - r[f"{key}_mean"]
         se = math.hypot(g[f"{key}_err"], r[f"{key}_err"])
         assert abs(d) < 3 * se, (key, d, se)
+    d = g["log_c_est"] - r["log_c_est"]
+    assert abs(d) < 3 * math.hypot(g["c_rel_err"], r["c_rel_err"]), ("log_c_est", d)
+
+
+def test_ensemble_averages_agree_within_3_sigma():
+    """Independent seeds: GPU and oracle ensembles are statistically equal
+    (weighted <R^2>, <Rg^2> of Eq. 2 and the c estimate of Eq. 6), at the
+    headline shapes: hard spheres N = 64, k = 8 and the lattice N = 64."""
+    w = WORKLOADS["real_n64"]
+    _, g = _gpu("real", w["N"], w["k"], w["n_chains"], 31)
+    ref = oracle.gen_real(32, w["N"], w["k"], 60_000)
+    r = oracle.reduce(w["N"], ref["log_w"], ref["r2"], ref["rg2"], ref["n_grown"])
+    _within_3_sigma(g, r)
     _, g = _gpu("lattice", 64, 6, 1_000_000, 33, coord="i16")
     ref = oracle.gen_lattice(34, 64, 100_000)
     r = oracle.reduce(64, ref["log_w"], ref["r2"], ref["rg2"], ref["n_grown"])
-    for key in ("r2", "rg2"):
-        d = g[f"{key}_mean"] - r[f"{key}_mean"]
-        se = math.hypot(g[f"{key}_err"], r[f"{key}_err"])
-        assert abs(d) < 3 * se, (key, d, se)
-    assert abs(g["log_c_est"] - r["log_c_est"]) < 3 * math.hypot(g["c_rel_err"], r["c_rel_err"])
+    _within_3_sigma(g, r)
