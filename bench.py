@@ -254,7 +254,7 @@ def run_batch(torch, rs, reps, m_lo=3.0, m_span=3.0):
     batched()
     plain()
     torch.cuda.synchronize()
-    t_b, t_p, per = [], [], []
+    t_b, t_p, per, done = [], [], [], []
     for _ in range(reps):
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(stream)
@@ -270,6 +270,9 @@ def run_batch(torch, rs, reps, m_lo=3.0, m_span=3.0):
         torch.cuda.synchronize()
         t_p.append(a2.elapsed_time(b2))
         per.extend(x.elapsed_time(y) for x, y in evs)
+        # completion of ensemble i from the common submission at a2: the
+        # plain launches finish one after another
+        done.extend(a2.elapsed_time(y) for _, y in evs)
     tb, tp = _percentile(t_b, 0.5), _percentile(t_p, 0.5)
     # the same batch after the autotuner has picked the lane mapping of each
     # (geometry, k, N bucket) of the workload
@@ -296,6 +299,11 @@ def run_batch(torch, rs, reps, m_lo=3.0, m_span=3.0):
         "plain_ms": tp, "plain_value": steps / (tp / 1e3),
         "unit": "monomer-steps/s", "speedup": tp / tb, "reps": reps,
         "plain_ensemble_p50_ms": _percentile(per, 0.5), "plain_ensemble_p99_ms": _percentile(per, 0.99),
+        # like for like: each ensemble's completion time from the common
+        # submission of all of them.  In a batch every summary is written by
+        # its last launch, so each ensemble completes when the batch does.
+        "completion_ms": {"batched_p50": _percentile(t_b, 0.5), "batched_p99": _percentile(t_b, 0.99),
+                          "plain_p50": _percentile(done, 0.5), "plain_p99": _percentile(done, 0.99)},
         "batched_ensemble_latency_ms": tb,
         "tuned_batched_ms": tt, "tuned_batched_value": steps / (tt / 1e3), "tuned_speedup": tp / tt,
         "autotune_s": tune_s, "tuned_mappings": tuning,
@@ -368,17 +376,60 @@ def run_serving(rs, rate, n, warmup, streams=2, max_batch=64, m_lo=4.0, m_span=3
     }
 
 
-def cpu_baseline(w, sample_chains, threads):
-    """The oracle, untuned, on the host cores: a bounded sample of the same
-    workload (its first `sample_chains` chains), split over threads."""
+def serving_leg(rs):
+    """Bounded serving measurement for the default run (about a minute): the
+    serving workload's request stream at 20/s (300 requests) and 40/s (300),
+    and its first 300 requests at 200/s, each served by the server and by
+    per-request plain launches (one stream, one request per launch, arrival
+    order).  The 200/s run is overloaded, so its throughput is the capacity,
+    and rho = offered work / that capacity."""
+    runs, plain = [], []
+    for rate, n, warm in ((20.0, 300, 30), (40.0, 300, 30), (200.0, 300, 30)):
+        print(f"[serve] rate {rate}/s, {n} requests", file=sys.stderr, flush=True)
+        runs.append(run_serving(rs, rate, n, warm))
+        print(f"[serve] plain launches, rate {rate}/s", file=sys.stderr, flush=True)
+        plain.append(run_serving(rs, rate, n, warm, streams=1, max_batch=1))
+    cap = runs[-1]["throughput_steps_per_s"]
+    for r in runs + plain:
+        r["rho"] = r["offered_steps_per_s"] / cap
+    return {"workload": "serving_requests (Poisson arrivals; N in {16, 32, 64, 128, 256}; lattice k = 6 or "
+                        "hard spheres k = 8; 10^4..10^7 chains each)",
+            "unit": "ms / monomer-steps/s", "served": runs, "plain": plain,
+            "capacity_steps_per_s": cap, "plain_capacity_steps_per_s": plain[-1]["throughput_steps_per_s"]}
+
+
+def host_cpu() -> dict:
+    """The host's CPU model (/proc/cpuinfo), its logical CPU count (nproc),
+    the CPUs this process may run on (affinity) and the thread share the job
+    is given (OMP_NUM_THREADS, when set)."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count() or 1
+    share = os.environ.get("OMP_NUM_THREADS")
+    return {"model": model, "nproc": os.cpu_count(), "affinity": affinity,
+            "job_share": int(share) if share and share.isdigit() else None}
+
+
+def _oracle_rate(w, n, threads):
+    """Oracle growth + reduction of the workload's first n chains on
+    `threads` threads (chain ranges; the oracle's C calls release the GIL);
+    returns (monomer-steps/s, seconds)."""
     from concurrent.futures import ThreadPoolExecutor
 
     import numpy as np
 
     import oracle
 
-    oracle.build()
-    n = sample_chains
     parts = [(i * n // threads, (i + 1) * n // threads) for i in range(threads)]
 
     def work(rng):
@@ -394,10 +445,32 @@ def cpu_baseline(w, sample_chains, threads):
     cat = {k: np.concatenate([r[k] for r in res]) for k in ("log_w", "r2", "rg2", "n_grown")}
     oracle.reduce(w["N"], cat["log_w"], cat["r2"], cat["rg2"], cat["n_grown"], bins=w["hist_bins"])
     dt = time.perf_counter() - t0
-    return dict(value=n * (w["N"] - 1) / dt, unit="monomer-steps/s", cores=threads,
-                kind="oracle",
-                sample=f"first {n} chains of the workload (seed {w['seed']}), growth + reduction, "
-                       f"{threads} threads, {dt:.2f} s wall")
+    return n * (w["N"] - 1) / dt, dt
+
+
+def cpu_baseline(w, single_chains, all_chains):
+    """The oracle, untuned, on the host: a bounded sample of the same
+    workload (its first chains, growth and reduction) on one thread and on
+    every core the job may use (the affinity set, within the job's thread
+    share when one is set).  The oracle's throughput is linear in the chain
+    count, so a sample gives the full workload's rate."""
+    import oracle
+
+    oracle.build()
+    cpu = host_cpu()
+    threads = cpu["affinity"]
+    if cpu["job_share"]:
+        threads = min(threads, cpu["job_share"])
+    one, dt1 = _oracle_rate(w, single_chains, 1)
+    allc, dta = _oracle_rate(w, all_chains, threads)
+    return dict(value=allc, unit="monomer-steps/s", cores=threads, kind="oracle",
+                sample=f"first {all_chains} chains of the workload (seed {w['seed']}), growth + reduction, "
+                       f"{threads} threads, {dta:.2f} s wall",
+                single_thread={"value": one, "cores": 1,
+                               "sample": f"first {single_chains} chains, growth + reduction, 1 thread, "
+                                         f"{dt1:.2f} s"},
+                parallel_efficiency=allc / (one * threads),
+                host_cpu=cpu)
 
 
 def main():
@@ -414,7 +487,12 @@ def main():
                     help="only run the serving benchmark (open-loop Poisson requests; about 2 minutes)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the mixed 256-ensemble batched-launch measurement")
-    ap.add_argument("--cpu-sample", type=int, default=0)
+    ap.add_argument("--cpu-scale", type=float, default=1.0,
+                    help="scale of the oracle samples of the CPU baseline (1 = about 10 s of CPU "
+                         "work per leg)")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the bounded serving leg (20/s, 40/s and a shortened 200/s trace, "
+                         "served and by plain launches)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (3 times), to scale "
                          "the FETCH_SIZE / WRITE_SIZE counters of a profiler run")
@@ -571,10 +649,22 @@ def main():
     if not args.no_batch:
         line["batch"] = {"full": run_batch(torch, rs, 3),
                          "small": run_batch(torch, rs, 5, m_lo=2.0, m_span=2.0)}
+    if not args.no_serve:
+        print("[bench] serving leg", file=sys.stderr, flush=True)
+        line["serving"] = serving_leg(rs)
     if not args.no_cpu_baseline:
-        threads = min(16, os.cpu_count() or 1)
-        sample = args.cpu_sample or (1_000_000 if w["geometry"] == "lattice" else 300_000)
-        line["cpu_baseline"] = cpu_baseline(w, sample, threads)
+        print("[bench] CPU baseline (oracle)", file=sys.stderr, flush=True)
+        scale = max(args.cpu_scale, 0.01)
+        if w["geometry"] == "lattice":
+            line["cpu_baseline"] = cpu_baseline(w, int(200_000 * scale), int(1_000_000 * scale))
+        else:
+            line["cpu_baseline"] = cpu_baseline(w, int(60_000 * scale), int(300_000 * scale))
+        if args.secondary and "secondary" in line:
+            w2 = WORKLOADS[args.secondary]
+            if w2["geometry"] == "lattice":
+                line["secondary"]["cpu_baseline"] = cpu_baseline(w2, int(200_000 * scale), int(1_000_000 * scale))
+            else:
+                line["secondary"]["cpu_baseline"] = cpu_baseline(w2, int(60_000 * scale), int(300_000 * scale))
     print(json.dumps(line), flush=True)
 
 

@@ -30,10 +30,10 @@
  *     human-readable message for the last failure on the calling thread is
  *     available from rsaw_last_error().
  *   - Thread safety: calls on different streams may run concurrently; the
- *     library keeps one internal workspace per (device, stream), so calls
- *     on the same stream are ordered by that stream.  Calls on one stream
- *     must come from one host thread at a time (they share that workspace
- *     and its staging buffer).
+ *     library keeps one workspace per (device, stream) (internal, or the
+ *     caller's after rsaw_set_workspace), so calls on the same stream are
+ *     ordered by that stream.  Calls on one stream must come from one host
+ *     thread at a time (they share that workspace and its staging buffer).
  */
 #ifndef RSAW_H
 #define RSAW_H
@@ -102,7 +102,10 @@ typedef struct {
  * monomers placed, and the observables of its placed prefix.
  */
 typedef struct {
-    double *log_w;     /* sum_i log m_i, in step order (Eq. 3)                        */
+    double *log_w;     /* log W (Eq. 3) grouped by value: sum over m = 1..k, ascending */
+                       /* m, of n_m ln m, n_m = steps with m free candidates; each     */
+                       /* product and each sum rounded once in binary64, ln m          */
+                       /* correctly rounded                                            */
     uint64_t *w_exact; /* lattice with RSAW_EXACT_W: prod_i m_i                       */
     void *r_end;       /* 3 planes (x, y, z) of n_chains, coord_type; r_0 = origin    */
     double *r2;        /* squared end-to-end distance                                */
@@ -257,12 +260,17 @@ void rsaw_batch_plan_destroy(rsaw_batch_plan *plan);
 
 /*
  * Serving loop.  A server owns S HIP streams on one device and a scheduler
- * thread.  Each request is one ensemble (an rsaw_config).  The scheduler
- * forms batches from the head of the arrival queue while the requests'
- * device bytes (26 B per chain plus 160 KiB each) fit in bytes_per_stream
- * and the batch holds at most max_batch requests.  It launches each batch
- * with rsaw_gen_batch on a free stream, so a new batch starts while others
- * run.  With size classes (large_ms), at most one large request is in
+ * thread.  Each stream has a device workspace of bytes_per_stream (capped
+ * at creation so that the S of them fit in 90 % of the device's free
+ * memory) and a pinned staging buffer for max_batch requests, allocated
+ * once when the server is created; serving then allocates nothing.  Each
+ * request is one ensemble (an rsaw_config).  The scheduler forms batches
+ * from the head of the arrival queue while the requests' workspace bytes
+ * (what rsaw_workspace_size reports for the configuration with a reduction
+ * and no per-chain outputs, plus its descriptor-table entries, under 1 KiB)
+ * fit in a stream's workspace and the batch holds at most max_batch
+ * requests.  It launches each batch with rsaw_gen_batch on a free stream,
+ * so a new batch starts while others run.  With size classes (large_ms), at most one large request is in
  * flight and a batch holds at most one, while small requests skip past
  * queued large ones; the size estimate is a per-chain cost model (N^2 scan
  * work, per geometry and k) used for scheduling only.  A completion thread
@@ -273,7 +281,8 @@ void rsaw_batch_plan_destroy(rsaw_batch_plan *plan);
 typedef struct rsaw_server rsaw_server;
 
 typedef struct {
-    uint64_t bytes_per_stream; /* admission budget of one batch (default 2 GiB) */
+    uint64_t bytes_per_stream; /* device workspace of one stream, the admission */
+                               /* budget of a batch (default 2 GiB)             */
     int32_t max_batch;         /* requests per batch, 1..4096 (default 256)     */
     int32_t streams;           /* concurrent batches, 1..16 (default 2)         */
     double large_ms;           /* size classes: a request whose estimated time  */
@@ -294,8 +303,8 @@ rsaw_status rsaw_server_create(const rsaw_server_params *params, int32_t device,
 /*
  * rsaw_server_submit — queue one request; *ticket identifies it.  The
  * configuration is checked as by rsaw_gen_chains (same statuses).  A
- * request whose bytes exceed bytes_per_stream is refused with
- * RSAW_E_NOMEM.  Thread-safe.
+ * request whose workspace bytes do not fit in a stream's workspace is
+ * refused with RSAW_E_NOMEM.  Thread-safe.
  */
 rsaw_status rsaw_server_submit(rsaw_server *s, const rsaw_config *cfg, uint64_t *ticket);
 
@@ -372,6 +381,52 @@ rsaw_status rsaw_kernel_time(double *total_ms, uint64_t *launches);
  */
 rsaw_status rsaw_workspace_size(const rsaw_config *cfg, const rsaw_chain_out *out, int32_t reduce,
                                 size_t *bytes);
+
+/*
+ * rsaw_set_workspace — bind a caller-owned device buffer as the workspace of
+ * (current device, stream), the buffer that rsaw_workspace_size describes.
+ *
+ *   d_ws    device memory of the current device, 256-byte aligned, owned by
+ *           the caller (the library never frees it); NULL unbinds it, and
+ *           the next call on the stream allocates an internal workspace again.
+ *   bytes   its size; at least the bytes of an empty reducing call (a few
+ *           hundred bytes).
+ *   stream  hipStream_t or NULL (the default stream).
+ *
+ * While bound, rsaw_gen_chains, rsaw_gen_chains_sync and rsaw_gen_batch on
+ * `stream` place their workspace in d_ws and allocate no device memory; a
+ * call that needs more than `bytes` (rsaw_workspace_size; for a batch, the
+ * sum over its ensembles plus its descriptor tables) fails with
+ * RSAW_E_NOMEM before enqueueing anything.  A bound stream's calls
+ * therefore only enqueue kernel launches (rsaw_gen_batch also copies its
+ * tables from a pinned host buffer), so a caller can capture
+ * rsaw_gen_chains into a HIP graph with no earlier warm-up call.  The buffer
+ * must stay valid, and must not be used by anything else, while work
+ * enqueued with it may run.  Binding releases an internal workspace of the
+ * stream after waiting for the stream's queued work (call it outside any
+ * capture).  Host-side, per (device, stream).
+ * Errors: RSAW_E_INVALID for a misaligned pointer, a size below the minimum,
+ * or memory that is not device memory of the current device;
+ * RSAW_E_DEVICE for a failed HIP call.
+ */
+rsaw_status rsaw_set_workspace(void *d_ws, size_t bytes, void *stream);
+
+/*
+ * rsaw_fp64_check — evaluate binary64 square roots and quotients on the
+ * device with the compiler settings of the growth kernels (no contraction,
+ * the same target), for checking that they are correctly rounded: the
+ * hard-sphere kernels take sqrt in the Marsaglia step (Sec. 3.3.3,
+ * q = 2 sqrt(1 - s)) and divisions in the centre of mass and Rg^2.
+ *
+ *   d_a, d_b        device arrays of n doubles (inputs).
+ *   d_sqrt, d_div   device arrays of n doubles: sqrt(a_i) and a_i / b_i.
+ *   n               element count (0 does nothing).
+ *   stream          hipStream_t or NULL.  Asynchronous.
+ * Errors: RSAW_E_INVALID for a NULL array with n > 0; RSAW_E_DEVICE for a
+ * failed launch.
+ */
+rsaw_status rsaw_fp64_check(const double *d_a, const double *d_b, double *d_sqrt, double *d_div, uint64_t n,
+                            void *stream);
 
 /*
  * Lane mapping of the group kernels and its autotuner.

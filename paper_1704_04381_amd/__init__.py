@@ -75,7 +75,7 @@ EXPORTS = ["rsaw_gen_chains", "rsaw_gen_chains_sync", "rsaw_gen_batch", "rsaw_se
            "rsaw_last_error", "rsaw_version", "rsaw_kernel_timing", "rsaw_kernel_time",
            "rsaw_workspace_size", "rsaw_mapping_set", "rsaw_mapping_clear", "rsaw_mapping_list", "rsaw_mapping_query",
            "rsaw_autotune", "rsaw_batch_plan_create", "rsaw_batch_plan_launch", "rsaw_batch_plan_destroy",
-           "rsaw_shutdown"]
+           "rsaw_set_workspace", "rsaw_fp64_check", "rsaw_shutdown"]
 
 _lib = None
 _lock = threading.Lock()
@@ -151,6 +151,10 @@ def load(path: str = LIB_PATH):
         lib.rsaw_batch_plan_launch.restype = C.c_int
         lib.rsaw_batch_plan_destroy.argtypes = [vp]
         lib.rsaw_batch_plan_destroy.restype = None
+        lib.rsaw_set_workspace.argtypes = [vp, C.c_size_t, vp]
+        lib.rsaw_set_workspace.restype = C.c_int
+        lib.rsaw_fp64_check.argtypes = [vp, vp, vp, vp, C.c_uint64, vp]
+        lib.rsaw_fp64_check.restype = C.c_int
         _lib = lib
         return lib
 
@@ -461,6 +465,32 @@ def workspace_size(cfg: rsaw_config, out: rsaw_chain_out | None = None, reduce: 
     _check(load().rsaw_workspace_size(C.byref(cfg), C.byref(out) if out is not None else None,
                                       1 if reduce else 0, C.byref(n)))
     return n.value
+
+
+def set_workspace(ptr: int, nbytes: int, stream: int = 0) -> None:
+    """Bind caller-owned device memory (address ``ptr``, ``nbytes``; 0
+    unbinds) as the workspace of (current device, stream)
+    (rsaw_set_workspace)."""
+    _check(load().rsaw_set_workspace(ptr or None, int(nbytes), stream or None))
+
+
+def fp64_check(a, b, stream=None):
+    """Device sqrt(a) and a / b (rsaw_fp64_check) for float64 device tensors
+    of equal length; returns (sqrt, quotient) tensors."""
+    import torch
+
+    a = a.contiguous()
+    b = b.contiguous()
+    if a.dtype != torch.float64 or b.dtype != torch.float64 or a.numel() != b.numel():
+        raise RsawError(1, "fp64_check needs two float64 tensors of equal length")
+    sq = torch.empty_like(a)
+    dv = torch.empty_like(a)
+    if stream is None:
+        stream = torch.cuda.current_stream(a.device).cuda_stream
+    with torch.cuda.device(a.device):
+        _check(load().rsaw_fp64_check(a.data_ptr(), b.data_ptr(), sq.data_ptr(), dv.data_ptr(),
+                                      a.numel(), stream or None))
+    return sq, dv
 
 
 def _mapping_dict(m: rsaw_mapping) -> dict:

@@ -17,7 +17,7 @@ INCLUDE = os.path.join(REPO, "include")
 LIB = os.path.join(PKG, "librsaw.so")
 SOURCES = ["rsaw_api.hip", "rsaw_server.hip", "grow_lattice.hip", "grow_lattice_lds.hip", "grow_lattice26.hip",
            "grow_real.hip",
-           "reduce.hip"]
+           "reduce.hip", "fp64_check.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

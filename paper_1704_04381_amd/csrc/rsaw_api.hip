@@ -57,22 +57,41 @@ rsaw_status hip_fail(hipError_t e, const char *what)
 }
 
 // Device buffers reused across calls on one (device, stream).  Grown on
-// demand; released by rsaw_shutdown().
+// demand; released by rsaw_shutdown().  A caller-owned buffer bound by
+// rsaw_set_workspace replaces the internal one and is never grown or freed.
 struct Workspace {
     void *base = nullptr;
     size_t bytes = 0;
+    bool external = false;      // base is the caller's buffer (rsaw_set_workspace)
     void *stage = nullptr;      // pinned host staging of batch descriptor tables
     size_t stage_bytes = 0;
     hipEvent_t stage_done = nullptr; // recorded after the last copy out of `stage`
 };
 
+// Entries are created under g_ws_lock and never move (std::map); an entry is
+// then used without the lock by the one host thread that drives its stream
+// (the ABI's rule for calls on one stream), so a synchronising call on one
+// stream's entry never blocks calls on other streams.
 std::mutex g_ws_lock;
 std::map<std::pair<int, void *>, Workspace> g_ws;
 
-rsaw_status workspace(int dev, hipStream_t s, size_t need, void **out)
+Workspace &ws_entry(int dev, hipStream_t s)
 {
     std::lock_guard<std::mutex> lk(g_ws_lock);
-    Workspace &w = g_ws[{dev, (void *)s}];
+    return g_ws[{dev, (void *)s}];
+}
+
+rsaw_status workspace(int dev, hipStream_t s, size_t need, void **out)
+{
+    Workspace &w = ws_entry(dev, s);
+    if (w.external) {
+        if (w.bytes < need)
+            return fail(RSAW_E_NOMEM, "the caller's workspace holds " + std::to_string(w.bytes) +
+                                          " bytes; this call needs " + std::to_string(need) +
+                                          " (rsaw_workspace_size)");
+        *out = w.base;
+        return RSAW_OK;
+    }
     if (w.bytes < need) {
         if (w.base) {
             hipError_t e = hipStreamSynchronize(s);
@@ -98,8 +117,7 @@ rsaw_status workspace(int dev, hipStream_t s, size_t need, void **out)
 // (dev, s), free for writing: waits for the previous copy out of it.
 rsaw_status staging(int dev, hipStream_t s, size_t need, void **out, hipEvent_t *done)
 {
-    std::lock_guard<std::mutex> lk(g_ws_lock);
-    Workspace &w = g_ws[{dev, (void *)s}];
+    Workspace &w = ws_entry(dev, s);
     if (w.stage_done) {
         hipError_t e = hipEventSynchronize(w.stage_done);
         if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
@@ -190,6 +208,8 @@ const double *logm_table()
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t min_workspace_bytes();
 
 rsaw_status validate(const rsaw_config *cfg)
 {
@@ -289,6 +309,23 @@ void layout_ensemble(const rsaw_config *cfg, const rsaw_chain_out &o, bool reduc
     L->off_slots = x;
     x = align256(x + (size_t)L->n_slots * 3 * (size_t)cfg->n_monomers * sizeof(double));
     *off = x;
+}
+
+// Workspace bytes that every call needs: those of an empty ensemble with a
+// reduction (its cells and summary).
+size_t min_workspace_bytes()
+{
+    rsaw_config c;
+    std::memset(&c, 0, sizeof(c));
+    c.geometry = RSAW_LATTICE_SC;
+    c.n_monomers = 1;
+    c.k_trials = 6;
+    c.coord_type = RSAW_I32;
+    rsaw_chain_out none{};
+    EnsLayout L;
+    size_t off = 0;
+    layout_ensemble(&c, none, true, &off, &L);
+    return off;
 }
 
 // The per-chain arrays the kernels write: the caller's, completed with
@@ -760,6 +797,63 @@ rsaw_status check_config(const rsaw_config *cfg)
     g_last_error.clear();
     return validate(cfg);
 }
+
+// Device workspace bytes one ensemble holds in an rsaw_gen_batch call with no
+// per-chain outputs and a reduction: its regions (the layout that
+// rsaw_workspace_size reports) and its entries of the descriptor tables.  A
+// batch needs at most the sum over its ensembles plus kBatchFixedBytes (the
+// alignment of its four tables and their two end entries).
+size_t batch_entry_bytes(const rsaw_config *cfg)
+{
+    rsaw_chain_out none{};
+    EnsLayout L;
+    size_t off = 0;
+    layout_ensemble(cfg, none, true, &off, &L);
+    return off + sizeof(GrowEntry) + sizeof(ReduceEntry) + 2 * sizeof(uint64_t);
+}
+
+// Pinned staging of the batch tables of (current device, s), grown to at
+// least `bytes` now rather than on a later call (which would free and
+// reallocate it while batches run).
+rsaw_status reserve_staging(hipStream_t s, size_t bytes)
+{
+    int dev = 0;
+    const hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    void *stage = nullptr;
+    hipEvent_t done = nullptr;
+    return staging(dev, s, bytes, &stage, &done);
+}
+
+// Forget the (current device, s) entry: free its internal workspace, its
+// staging buffer and event (a caller workspace stays the caller's).  For a
+// stream about to be destroyed; waits for its queued work first.
+rsaw_status release_stream(hipStream_t s)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    Workspace w;
+    {
+        std::lock_guard<std::mutex> lk(g_ws_lock);
+        auto it = g_ws.find({dev, (void *)s});
+        if (it == g_ws.end()) return RSAW_OK;
+        w = it->second;
+        g_ws.erase(it);
+    }
+    if (w.base && !w.external) (void)hipFree(w.base);
+    if (w.stage) (void)hipHostFree(w.stage);
+    if (w.stage_done) (void)hipEventDestroy(w.stage_done);
+    return RSAW_OK;
+}
+
+// Staging bytes of the tables of a batch of n ensembles.
+size_t batch_stage_bytes(int n)
+{
+    return (size_t)n * (sizeof(GrowEntry) + sizeof(ReduceEntry) + 2 * sizeof(uint64_t)) + kBatchFixedBytes;
+}
 } // namespace rsaw
 
 extern "C" {
@@ -908,6 +1002,44 @@ rsaw_status rsaw_workspace_size(const rsaw_config *cfg, const rsaw_chain_out *ou
     return RSAW_OK;
 }
 
+rsaw_status rsaw_set_workspace(void *d_ws, size_t bytes, void *stream)
+{
+    g_last_error.clear();
+    hipStream_t s = (hipStream_t)stream;
+    if (d_ws) {
+        if ((uintptr_t)d_ws & 255) return fail(RSAW_E_INVALID, "d_ws must be 256-byte aligned");
+        const size_t least = min_workspace_bytes();
+        if (bytes < least)
+            return fail(RSAW_E_INVALID, "a workspace needs at least " + std::to_string(least) + " bytes");
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (d_ws) {
+        hipPointerAttribute_t at;
+        std::memset(&at, 0, sizeof(at));
+        e = hipPointerGetAttributes(&at, d_ws);
+        if (e != hipSuccess) {
+            (void)hipGetLastError(); // an unknown pointer is an argument error, not a device fault
+            return fail(RSAW_E_INVALID, "d_ws is not device memory known to HIP");
+        }
+        if ((at.type != hipMemoryTypeDevice && !at.isManaged) || at.device != dev)
+            return fail(RSAW_E_INVALID, "d_ws must be device memory of the current device " + std::to_string(dev));
+    }
+    Workspace &w = ws_entry(dev, s);
+    if (!w.external && w.base) {
+        // the internal buffer may still be in use by work queued on the stream
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        e = hipFree(w.base);
+        if (e != hipSuccess) return hip_fail(e, "hipFree");
+    }
+    w.base = d_ws;
+    w.bytes = d_ws ? bytes : 0;
+    w.external = d_ws != nullptr;
+    return RSAW_OK;
+}
+
 void rsaw_shutdown(void)
 {
     {
@@ -927,7 +1059,7 @@ void rsaw_shutdown(void)
         (void)hipGetDevice(&cur);
         (void)hipSetDevice(kv.first.first);
         (void)hipDeviceSynchronize();
-        if (kv.second.base) (void)hipFree(kv.second.base);
+        if (kv.second.base && !kv.second.external) (void)hipFree(kv.second.base);
         if (kv.second.stage) (void)hipHostFree(kv.second.stage);
         if (kv.second.stage_done) (void)hipEventDestroy(kv.second.stage_done);
         (void)hipSetDevice(cur);

@@ -52,6 +52,15 @@ struct ReduceEntry {
 hipError_t launch_reduce_batch(const ReduceEntry *tab, const uint64_t *block0, int n, uint64_t total_blocks,
                                int max_bins, hipStream_t s, bool init_only);
 
+// Serving-loop admission: device workspace of one ensemble in a batch (its
+// regions and table entries), the fixed bytes a batch adds, the staging
+// bytes of a batch of n, and an early reservation of a stream's staging.
+size_t batch_entry_bytes(const rsaw_config *cfg);
+constexpr size_t kBatchFixedBytes = 2048;
+size_t batch_stage_bytes(int n);
+rsaw_status reserve_staging(hipStream_t s, size_t bytes);
+rsaw_status release_stream(hipStream_t s);
+
 hipError_t launch_reduce_init(unsigned long long *lmax_bits, int32_t *status,
                               unsigned long long *hist_acc, int n_acc, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs &a, uint32_t n_blocks, rsaw_summary *out,

@@ -4,11 +4,16 @@
 // of S streams, and a completion thread per stream waits for the batch's
 // event, copies the summaries out and retires the tickets.
 //
-// Admission: a batch takes requests in arrival order while the device bytes
-// they need (the per-chain arrays of the reduction, 26 B per chain, plus a
-// fixed share) stay within the per-stream budget and the batch holds at most
-// max_batch requests.  A new batch starts on any free stream while others
-// run, so short requests arriving during a long batch do not wait for it.
+// Admission by device memory: each stream owns a device workspace of
+// bytes_per_stream (capped at creation so that all of them fit in 90 % of
+// the device's free memory), bound with rsaw_set_workspace, and a pinned
+// staging buffer sized for max_batch requests, both allocated once at
+// creation: serving allocates and frees nothing.  A batch takes requests
+// while the workspace bytes they need (the layout of rsaw_workspace_size
+// plus their descriptor-table entries) fit in the stream's workspace and
+// the batch holds at most max_batch requests.  A new batch starts on any
+// free stream while others run, so short requests arriving during a long
+// batch do not wait for it.
 //
 // Size classes: a request whose estimated service time alone exceeds
 // large_ms is "large".  At most one large request is in flight at a time
@@ -21,6 +26,7 @@
 // growth and reduction are bit-identical to single calls).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -32,6 +38,7 @@
 #include <vector>
 
 #include "rsaw.h"
+#include "rsaw_reduce.hpp"
 
 namespace rsaw {
 rsaw_status check_config(const rsaw_config *cfg); // the checks of rsaw_gen_chains
@@ -52,6 +59,7 @@ struct Ticket {
 struct Slot {
     bool large = false;             // the batch holds a large request
     hipStream_t stream = nullptr;
+    void *ws = nullptr;             // the stream's device workspace (budget bytes)
     hipEvent_t done = nullptr;
     rsaw_summary *d_summ = nullptr; // max_batch summaries (device)
     rsaw_summary *h_summ = nullptr; // pinned copy
@@ -61,12 +69,8 @@ struct Slot {
     std::condition_variable cv;     // a batch was launched on this slot
 };
 
-// Device bytes a request holds while in flight (the reduction's per-chain
-// arrays in the library workspace, and its cells and partials).
-size_t request_bytes(const rsaw_config &c)
-{
-    return (size_t)c.n_chains * (3 * sizeof(double) + sizeof(uint16_t)) + (size_t)160 * 1024;
-}
+// Device workspace bytes a request holds while its batch runs.
+size_t request_bytes(const rsaw_config &c) { return rsaw::batch_entry_bytes(&c); }
 
 // Estimated growth time of a request alone on the device, in ms, for the
 // size classes only (it never affects a result).  A chain's scan work grows
@@ -96,6 +100,7 @@ struct rsaw_server {
     std::vector<Slot> slots;
     std::thread scheduler;
     std::string error;
+    size_t budget = 0; // workspace bytes of each stream
 
     bool is_large(const rsaw_config &c) const { return p.large_ms >= 0.0 && estimate_ms(c) > large_ms(); }
     double large_ms() const { return p.large_ms > 0.0 ? p.large_ms : 2.0; }
@@ -166,7 +171,7 @@ struct rsaw_server {
                     continue;
                 }
                 const size_t need = request_bytes(tk.cfg);
-                if (!batch.empty() && bytes + need > p.bytes_per_stream) break;
+                if (bytes + need + rsaw::kBatchFixedBytes > budget) break;
                 bytes += need;
                 batch_large = batch_large || large;
                 batch.push_back(*it);
@@ -256,26 +261,40 @@ rsaw_status rsaw_server_create(const rsaw_server_params *params, int32_t device,
     s->p = p;
     s->device = device;
     s->slots = std::vector<Slot>(p.streams);
-    bool ok = true;
+    // each stream's workspace: bytes_per_stream, within 90 % of free memory
+    size_t free_b = 0, total_b = 0;
+    bool ok = hipMemGetInfo(&free_b, &total_b) == hipSuccess;
+    s->budget = (size_t)p.bytes_per_stream;
+    if (ok) s->budget = std::min(s->budget, (size_t)((double)free_b * 0.9 / p.streams));
+    s->budget &= ~(size_t)255;
     for (Slot &sl : s->slots) {
         ok = ok && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess;
         ok = ok && hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess;
         ok = ok && hipMalloc(&sl.d_summ, (size_t)p.max_batch * sizeof(rsaw_summary)) == hipSuccess;
         ok = ok && hipHostMalloc(&sl.h_summ, (size_t)p.max_batch * sizeof(rsaw_summary), hipHostMallocDefault) ==
                        hipSuccess;
+        ok = ok && hipMalloc(&sl.ws, s->budget) == hipSuccess;
+        ok = ok && rsaw_set_workspace(sl.ws, s->budget, sl.stream) == RSAW_OK;
+        ok = ok && rsaw::reserve_staging(sl.stream, rsaw::batch_stage_bytes(p.max_batch)) == RSAW_OK;
         if (!ok) break;
     }
-    (void)hipSetDevice(prev);
     if (!ok) {
         for (Slot &sl : s->slots) {
+            if (sl.stream) {
+                (void)rsaw_set_workspace(nullptr, 0, sl.stream);
+                (void)rsaw::release_stream(sl.stream);
+            }
+            if (sl.ws) (void)hipFree(sl.ws);
             if (sl.d_summ) (void)hipFree(sl.d_summ);
             if (sl.h_summ) (void)hipHostFree(sl.h_summ);
             if (sl.done) (void)hipEventDestroy(sl.done);
             if (sl.stream) (void)hipStreamDestroy(sl.stream);
         }
+        (void)hipSetDevice(prev);
         delete s;
         return RSAW_E_NOMEM;
     }
+    (void)hipSetDevice(prev);
     for (Slot &sl : s->slots) sl.waiter = std::thread(&rsaw_server::wait_loop, s, &sl);
     s->scheduler = std::thread(&rsaw_server::schedule_loop, s);
     *out = s;
@@ -287,7 +306,7 @@ rsaw_status rsaw_server_submit(rsaw_server *s, const rsaw_config *cfg, uint64_t 
     if (!s || !cfg || !ticket) return RSAW_E_INVALID;
     rsaw_status st = rsaw::check_config(cfg);
     if (st != RSAW_OK) return st;
-    if (request_bytes(*cfg) > s->p.bytes_per_stream) return RSAW_E_NOMEM;
+    if (request_bytes(*cfg) + rsaw::kBatchFixedBytes > s->budget) return RSAW_E_NOMEM;
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stopping) return RSAW_E_INVALID;
     const uint64_t t = s->next_ticket++;
@@ -357,6 +376,9 @@ void rsaw_server_destroy(rsaw_server *s)
     (void)hipSetDevice(s->device);
     for (Slot &sl : s->slots) {
         (void)hipStreamSynchronize(sl.stream);
+        (void)rsaw_set_workspace(nullptr, 0, sl.stream);
+        (void)rsaw::release_stream(sl.stream);
+        (void)hipFree(sl.ws);
         (void)hipFree(sl.d_summ);
         (void)hipHostFree(sl.h_summ);
         (void)hipEventDestroy(sl.done);

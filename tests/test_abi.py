@@ -178,3 +178,22 @@ def test_header_is_plain_c99(tmp_path):
     r = subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-fsyntax-only", "-I", inc,
                         str(src)], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+def test_set_workspace_argument_errors():
+    """rsaw_set_workspace checks alignment and the minimum size on the host
+    before any device call; NULL unbinds."""
+    lib = _lib()
+    assert lib.rsaw_set_workspace(C.c_void_p(0x1001), 1 << 20, None) == 1
+    assert "aligned" in lib.rsaw_last_error().decode()
+    assert lib.rsaw_set_workspace(C.c_void_p(0x100000), 64, None) == 1
+    assert "at least" in lib.rsaw_last_error().decode()
+    # the smallest workspace is that of an empty reducing call
+    least = rs.workspace_size(rs.make_config("lattice", 1, 6, 0, 1))
+    assert 0 < least <= 4096
+
+
+def test_fp64_check_argument_errors():
+    lib = _lib()
+    assert lib.rsaw_fp64_check(None, None, None, None, 0, None) == 0
+    assert lib.rsaw_fp64_check(None, None, None, None, 5, None) == 1

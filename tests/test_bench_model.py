@@ -79,3 +79,17 @@ def test_lds_models():
     assert abs(bench.LDS_PEAK_TBS - 78.6432) < 1e-9
     o = bench.lds_object(1e12, 1000.0, "x")
     assert abs(o["achieved"] - 1.0) < 1e-12 and abs(o["frac"] - 1.0 / bench.LDS_PEAK_TBS) < 1e-12
+
+
+def test_cpu_baseline_reports_one_thread_and_all_cores():
+    """The CPU baseline times the oracle on one thread and on every core the
+    job may use, and states the host's CPU model and counts."""
+    from paper_1704_04381_amd.workloads import WORKLOADS
+
+    cb = bench.cpu_baseline(WORKLOADS["real_n64"], 200, 800)
+    assert cb["kind"] == "oracle" and cb["unit"] == "monomer-steps/s"
+    assert cb["value"] > 0 and cb["single_thread"]["value"] > 0 and cb["single_thread"]["cores"] == 1
+    cpu = cb["host_cpu"]
+    assert cpu["nproc"] == os.cpu_count() and cpu["affinity"] >= 1
+    assert cb["cores"] == min(cpu["affinity"], cpu["job_share"] or cpu["affinity"])
+    assert isinstance(cpu["model"], str)

@@ -145,3 +145,61 @@ def test_batch_plan_argument_errors():
     empty.launch()
     torch.cuda.synchronize()
     empty.close()
+
+
+def test_caller_workspace_allows_capture_without_warm_up():
+    """rsaw_set_workspace: a fresh stream bound to a caller-owned buffer is
+    captured into a graph with no earlier call on it; every replay equals the
+    eager calls on another stream bit for bit.  A call needing more than the
+    buffer fails with RSAW_E_NOMEM and enqueues nothing."""
+    dev = torch.device("cuda", 0)
+    calls = _prepare(dev)
+    print("[gpu] caller workspace: eager reference on the current stream", flush=True)
+    _launch(calls, torch.cuda.current_stream(dev).cuda_stream)
+    torch.cuda.synchronize()
+    ref = _snapshot(calls)
+    need = max(rs.workspace_size(cfg, o) for cfg, o, _, _ in calls)
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    fresh = torch.cuda.Stream(device=dev)
+    with torch.cuda.device(dev):
+        rs.set_workspace(ws.data_ptr(), need, fresh.cuda_stream)
+    try:
+        g = torch.cuda.CUDAGraph()
+        print("[gpu] caller workspace: capture on a fresh stream", flush=True)
+        with torch.cuda.graph(g, stream=fresh):
+            _launch(calls, fresh.cuda_stream)
+        torch.cuda.synchronize()
+        other = _prepare(dev)
+        for rep in range(3):
+            for _, _, out, summ in calls:
+                for v in out.values():
+                    v.zero_()
+                summ.zero_()
+            _launch(other, torch.cuda.current_stream(dev).cuda_stream)
+            torch.cuda.synchronize()
+            print(f"[gpu] caller workspace: replay {rep}", flush=True)
+            g.replay()
+            torch.cuda.synchronize()
+            got = _snapshot(calls)
+            for i, ((o_ref, s_ref), (o_got, s_got)) in enumerate(zip(ref, got)):
+                for k in o_ref:
+                    np.testing.assert_array_equal(o_got[k], o_ref[k], err_msg=f"replay {rep} call {i} {k}")
+                np.testing.assert_array_equal(s_got, s_ref, err_msg=f"replay {rep} call {i} summary")
+        del g
+        # too small for a call without per-chain outputs: refused, nothing enqueued
+        big = rs.make_config("lattice", 64, 6, 10 * need, 1, coord="i16")
+        summ = torch.zeros(rs.SUMMARY_BYTES, dtype=torch.uint8, device=dev)
+        with pytest.raises(rs.RsawError) as e:
+            rs.gen_chains_raw(big, None, summ.data_ptr(), 0, 0, fresh.cuda_stream)
+        assert e.value.status == 4
+        torch.cuda.synchronize()
+        assert int(summ.sum()) == 0
+    finally:
+        with torch.cuda.device(dev):
+            rs.set_workspace(0, 0, fresh.cuda_stream)
+    # unbound: the stream allocates its own workspace again
+    cfg, o, out, summ = calls[0]
+    rs.gen_chains_raw(cfg, o, summ.data_ptr(), out["hist_w"].data_ptr(), out["hist_n"].data_ptr(),
+                      fresh.cuda_stream)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(summ.cpu().numpy(), ref[0][1])
