@@ -190,6 +190,34 @@ rsaw_status rsaw_gen_chains_sync(const rsaw_config *cfg, const rsaw_chain_out *o
                                  uint64_t *d_hist_n, void *stream);
 
 /*
+ * rsaw_gen_chains_static — rsaw_gen_chains for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc).  Same arguments, results and errors as
+ * rsaw_gen_chains; the workspace is a file-scope device array of
+ * RSAW_STATIC_SCRATCH_BYTES in the library, one copy per GPU, held until the
+ * process ends.  The call allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine) and records no kernel-timing events.
+ *
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents (the call clears what must start at zero with a kernel): calls
+ * that may overlap on one GPU (other streams, other threads, another call
+ * before the previous one has finished reading its results from the
+ * workspace) race and must be serialised by the caller.  Results the caller
+ * needs must be in `out`, `d_summary` and the histograms, which the caller
+ * owns.
+ * Errors: as rsaw_gen_chains; RSAW_E_NOMEM when the call needs more
+ * workspace than the array holds (rsaw_workspace_size > the limit: e.g.
+ * more than about 1.2 million chains without per-chain outputs, or
+ * hard-sphere chains beyond 1536 beads, whose HBM bead planes need 48 N KiB
+ * per resident block), checked before anything is enqueued;
+ * RSAW_E_UNSUPPORTED for a device index above 63.
+ */
+#define RSAW_STATIC_SCRATCH_BYTES ((size_t)32 << 20)
+rsaw_status rsaw_gen_chains_static(const rsaw_config *cfg, const rsaw_chain_out *out,
+                                   rsaw_summary *d_summary, double *d_hist_w,
+                                   uint64_t *d_hist_n, void *stream);
+
+/*
  * rsaw_gen_batch — grow and reduce n ensembles at once (the same method as
  * rsaw_gen_chains, Sec. 3.3.2-3.3.3, Eqs. 2, 3 and 6, for each ensemble).
  *

@@ -75,7 +75,7 @@ EXPORTS = ["rsaw_gen_chains", "rsaw_gen_chains_sync", "rsaw_gen_batch", "rsaw_se
            "rsaw_last_error", "rsaw_version", "rsaw_kernel_timing", "rsaw_kernel_time",
            "rsaw_workspace_size", "rsaw_mapping_set", "rsaw_mapping_clear", "rsaw_mapping_list", "rsaw_mapping_query",
            "rsaw_autotune", "rsaw_batch_plan_create", "rsaw_batch_plan_launch", "rsaw_batch_plan_destroy",
-           "rsaw_set_workspace", "rsaw_fp64_check", "rsaw_shutdown"]
+           "rsaw_set_workspace", "rsaw_fp64_check", "rsaw_gen_chains_static", "rsaw_shutdown"]
 
 _lib = None
 _lock = threading.Lock()
@@ -101,6 +101,9 @@ def load(path: str = LIB_PATH):
         lib.rsaw_gen_chains.argtypes = [C.POINTER(rsaw_config), C.POINTER(rsaw_chain_out),
                                         vp, vp, vp, vp]
         lib.rsaw_gen_chains.restype = C.c_int
+        lib.rsaw_gen_chains_static.argtypes = [C.POINTER(rsaw_config), C.POINTER(rsaw_chain_out),
+                                               vp, vp, vp, vp]
+        lib.rsaw_gen_chains_static.restype = C.c_int
         lib.rsaw_gen_chains_sync.argtypes = [C.POINTER(rsaw_config), C.POINTER(rsaw_chain_out),
                                              C.POINTER(rsaw_summary), vp, vp, vp]
         lib.rsaw_gen_chains_sync.restype = C.c_int
@@ -198,6 +201,20 @@ def gen_chains_raw(cfg: rsaw_config, out: rsaw_chain_out | None, d_summary: int,
     _check(lib.rsaw_gen_chains(C.byref(cfg), C.byref(out) if out is not None else None,
                                d_summary or None, d_hist_w or None, d_hist_n or None,
                                stream or None))
+
+
+STATIC_SCRATCH_BYTES = 32 << 20
+
+
+def gen_chains_static_raw(cfg: rsaw_config, out: rsaw_chain_out | None, d_summary: int,
+                          d_hist_w: int, d_hist_n: int, stream: int):
+    """Direct call of rsaw_gen_chains_static (the allocation-free variant of
+    rsaw_gen_chains, workspace in the library's static device scratch) with
+    raw device addresses (0 = NULL)."""
+    lib = load()
+    _check(lib.rsaw_gen_chains_static(C.byref(cfg), C.byref(out) if out is not None else None,
+                                      d_summary or None, d_hist_w or None, d_hist_n or None,
+                                      stream or None))
 
 
 def _alloc_outputs(cfg: rsaw_config, dev, per_chain: bool, hist_bins: int):

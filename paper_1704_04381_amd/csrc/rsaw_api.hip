@@ -399,9 +399,11 @@ rsaw::ReduceArgs reduce_args(const rsaw_config *cfg, const rsaw_chain_out &o, co
 // summary goes to the workspace when the caller gives no device summary;
 // *used_summary receives the device address the summary was written to (or
 // NULL).
+// With fixed_ws set, the call uses that buffer of fixed_bytes instead of the
+// stream's workspace, allocates nothing and records no timing events.
 rsaw_status gen_impl(const rsaw_config *cfg, const rsaw_chain_out *out, rsaw_summary *d_summary,
                      double *d_hist_w, uint64_t *d_hist_n, void *stream, bool force_reduce,
-                     rsaw_summary **used_summary)
+                     rsaw_summary **used_summary, void *fixed_ws = nullptr, size_t fixed_bytes = 0)
 {
     g_last_error.clear();
     if (used_summary) *used_summary = nullptr;
@@ -419,8 +421,16 @@ rsaw_status gen_impl(const rsaw_config *cfg, const rsaw_chain_out *out, rsaw_sum
     size_t off = 0;
     layout_ensemble(cfg, in, reduce, &off, &L);
     void *wsv = nullptr;
-    st = workspace(dev, s, off, &wsv);
-    if (st != RSAW_OK) return st;
+    if (fixed_ws) {
+        if (off > fixed_bytes)
+            return fail(RSAW_E_NOMEM, "this call needs " + std::to_string(off) +
+                                          " bytes of workspace (rsaw_workspace_size); the static scratch holds " +
+                                          std::to_string(fixed_bytes));
+        wsv = fixed_ws;
+    } else {
+        st = workspace(dev, s, off, &wsv);
+        if (st != RSAW_OK) return st;
+    }
     char *ws = (char *)wsv;
     const rsaw_chain_out o = bind_outputs(in, L, ws);
 
@@ -432,8 +442,10 @@ rsaw_status gen_impl(const rsaw_config *cfg, const rsaw_chain_out *out, rsaw_sum
         const rsaw::GrowArgs a = grow_args(cfg, o, L, ws);
         EventPair tp;
         bool timed = false;
-        st = timing_start(s, &tp, &timed);
-        if (st != RSAW_OK) return st;
+        if (!fixed_ws) {
+            st = timing_start(s, &tp, &timed);
+            if (st != RSAW_OK) return st;
+        }
         const bool i16 = cfg->coord_type == RSAW_I16;
         e = L.z26       ? rsaw::launch_grow_lattice26(a, L.exact, i16, s)
             : L.lattice ? rsaw::launch_grow_lattice(a, L.exact, i16, s)
@@ -849,6 +861,32 @@ rsaw_status release_stream(hipStream_t s)
     return RSAW_OK;
 }
 
+// Scratch of rsaw_gen_chains_static: a file-scope device array, one copy per
+// GPU, held until the process ends.  Host code never passes `scratch`
+// itself to a kernel (on the host it is a stand-in, not a device address);
+// it uses the address hipGetSymbolAddress returns for the current device.
+constexpr size_t kStaticScratchBytes = (size_t)32 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+std::mutex g_scratch_lock;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev (current), looked up on the
+// first call there.
+rsaw_status static_scratch(int dev, void **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(RSAW_E_UNSUPPORTED, "device index beyond 63");
+    std::lock_guard<std::mutex> lk(g_scratch_lock);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return RSAW_OK;
+}
+
 // Staging bytes of the tables of a batch of n ensembles.
 size_t batch_stage_bytes(int n)
 {
@@ -863,6 +901,22 @@ rsaw_status rsaw_gen_chains(const rsaw_config *cfg, const rsaw_chain_out *out,
                             void *stream)
 {
     return gen_impl(cfg, out, d_summary, d_hist_w, d_hist_n, stream, false, nullptr);
+}
+
+rsaw_status rsaw_gen_chains_static(const rsaw_config *cfg, const rsaw_chain_out *out,
+                                   rsaw_summary *d_summary, double *d_hist_w, uint64_t *d_hist_n,
+                                   void *stream)
+{
+    g_last_error.clear();
+    rsaw_status st = validate(cfg);
+    if (st != RSAW_OK) return st;
+    int dev = 0;
+    const hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    void *ws = nullptr;
+    st = rsaw::static_scratch(dev, &ws);
+    if (st != RSAW_OK) return st;
+    return gen_impl(cfg, out, d_summary, d_hist_w, d_hist_n, stream, false, nullptr, ws, rsaw::kStaticScratchBytes);
 }
 
 rsaw_status rsaw_gen_chains_sync(const rsaw_config *cfg, const rsaw_chain_out *out,
