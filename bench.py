@@ -132,6 +132,65 @@ def lattice26_alg_ops_per_chain(N: int) -> int:
     return sum(7 * max(i - 1, 0) + 8 + 20 for i in range(1, N))
 
 
+def path_model(w) -> dict:
+    """Growth kernel of a workload, its algorithmic VALU lane-operations and
+    LDS bytes per launch, and the VALU peak it is priced against."""
+    geo, N, M = w["geometry"], w["N"], w["n_chains"]
+    if geo == "lattice":
+        reg = N <= 64 or w.get("exact_w", False)
+        return dict(kernel="grow_lattice_reg" if reg else "grow_lattice_lds",
+                    kernel_file="grow_lattice.hip" if reg else "grow_lattice_lds.hip",
+                    ops=lattice_alg_ops_per_chain(N) * M, peak=VALU_PEAK_INT32_TOPS, int_path=True,
+                    lds_bytes=0.0 if reg else lattice_lds_bytes_per_chain(N) * M,
+                    lds_note=("chain history in VGPRs: no LDS traffic" if reg else
+                              "parity-plane words of the neighbour candidates read once per step"))
+    if geo == "lattice26":
+        lane = N <= 64
+        return dict(kernel="grow_lattice26_lane" if lane else "grow_lattice26",
+                    kernel_file="grow_lattice26.hip",
+                    ops=lattice26_alg_ops_per_chain(N) * M, peak=VALU_PEAK_INT32_TOPS, int_path=True,
+                    lds_bytes=lattice26_lds_bytes_per_chain(N) * M * (1 if lane else 2),
+                    lds_note="monomer words read once per step")
+    hbm = N > 1536
+    return dict(kernel="grow_real_hbm" if hbm else "grow_real_tp", kernel_file="grow_real.hip",
+                ops=real_alg_ops_per_chain(N, w["k"]) * M, peak=VALU_PEAK_FP64_TOPS, int_path=False,
+                lds_bytes=0.0 if hbm else real_lds_bytes_per_chain(N) * M,
+                lds_note="beads in HBM planes" if hbm else "beads read once per step")
+
+
+def lattice_lds_bytes_per_chain(N: int) -> int:
+    """Algorithmic LDS bytes of one long lattice chain (two 4-byte words per
+    monomer): per step i the floor(i/2) monomers of the tip's opposite
+    parity are read once, and the new monomer is written."""
+    return sum(8 * (i // 2) + 8 for i in range(1, N))
+
+
+def roofline_object(pm: dict, kernel_ms: float, workload: str) -> dict:
+    """Roofline of a growth kernel: algorithmic lane-operations per launch
+    over the kernel's mean duration, against the VALU peak."""
+    ach = pm["ops"] / (kernel_ms / 1e3) / 1e12
+    out = {"bound": "alu", "achieved": ach, "peak": pm["peak"], "unit": "Tops/s", "frac": ach / pm["peak"]}
+    if pm["int_path"]:
+        out.update(attainable_peak=ATTAINABLE_INT_PATH_TOPS, frac_attainable=ach / ATTAINABLE_INT_PATH_TOPS)
+    out.update(traffic=measured_traffic(pm["kernel"], pm["kernel_file"], workload), kernel=pm["kernel"],
+               kernel_ms=kernel_ms, alg_ops_per_launch=pm["ops"])
+    return out
+
+
+def side_leg(w, name, steps, torch, rs) -> dict:
+    """Throughput, latency, roofline and LDS objects of one more workload."""
+    r = run_gpu(w, steps, 1, torch, rs)
+    T = sum(r["lat"]) / 1e3
+    pm = path_model(w)
+    return {"workload": name, "value": w["n_chains"] * (w["N"] - 1) * steps / T,
+            "unit": "monomer-steps/s", "steps": steps, "ms_per_step": T * 1e3 / steps,
+            "p50_ms": _percentile(r["lat"], 0.5), "p99_ms": _percentile(r["lat"], 0.99),
+            "roofline": roofline_object(pm, r["grow_ms"], name),
+            "lds": lds_object(pm["lds_bytes"], r["grow_ms"], pm["lds_note"]),
+            "physics": {k: r["summary"][k] for k in ("n_alive", "log_c_est", "r2_mean",
+                                                      "r2_err", "rg2_mean", "rg2_err")}}
+
+
 def _percentile(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -482,6 +541,8 @@ def main():
     ap.add_argument("--secondary", default="real_n64")
     ap.add_argument("--variant", default="lattice26_n64",
                     help="26-neighbour lattice workload reported under \"variant\" ('' to skip)")
+    ap.add_argument("--long", default="lattice_n256,lattice26_n256",
+                    help="comma-separated long-chain workloads reported under \"long_chains\" ('' to skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", action="store_true",
                     help="only run the serving benchmark (open-loop Poisson requests; about 2 minutes)")
@@ -554,13 +615,7 @@ def main():
     r = run_gpu(w, args.steps, args.warmup, torch, rs)
     T = sum(r["lat"]) / 1e3
     value = M * (N - 1) * args.steps / T
-    if w["geometry"] == "lattice":
-        alg_ops = lattice_alg_ops_per_chain(N) * M
-    else:
-        alg_ops = real_alg_ops_per_chain(N, w["k"]) * M
-    achieved = alg_ops / (r["grow_ms"] / 1e3) / 1e12
-    lattice = w["geometry"] != "real"
-    peak = VALU_PEAK_INT32_TOPS if lattice else VALU_PEAK_FP64_TOPS
+    pm = path_model(w)
     line = {
         "metric": "monomer-steps/s at N=64 lattice + hard-sphere; p50/p99 ensemble latency",
         "value": value,
@@ -575,77 +630,22 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int32+f64" if w["geometry"] == "lattice" else "f64",
+        "dtype": "int32+f64" if w["geometry"] != "real" else "f64",
         "data": "synthetic (counter-based Philox draws inside the method)",
         "config": {"workload": args.workload, "geometry": w["geometry"], "N": N, "k": w["k"],
                    "n_chains": M, "seed": w["seed"], "coord": w["coord"],
                    "hist_bins": w["hist_bins"]},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
-                     "unit": "Tops/s", "frac": achieved / peak,
-                     **({"attainable_peak": ATTAINABLE_INT_PATH_TOPS,
-                         "frac_attainable": achieved / ATTAINABLE_INT_PATH_TOPS} if lattice else {}),
-                     "traffic": (measured_traffic("grow_lattice_reg", "grow_lattice.hip", args.workload)
-                                 if w["geometry"] == "lattice" else
-                                 measured_traffic("grow_real_tp", "grow_real.hip", args.workload)),
-                     "kernel": "grow_lattice_reg" if w["geometry"] == "lattice" else "grow_real_tp",
-                     "kernel_ms": r["grow_ms"], "alg_ops_per_launch": alg_ops},
-        "lds": (lds_object(0.0, r["grow_ms"], "chain history in VGPRs: no LDS traffic")
-                if lattice else
-                lds_object(real_lds_bytes_per_chain(N) * M, r["grow_ms"], "beads read once per step")),
+        "roofline": roofline_object(pm, r["grow_ms"], args.workload),
+        "lds": lds_object(pm["lds_bytes"], r["grow_ms"], pm["lds_note"]),
         "physics": {k: r["summary"][k] for k in ("n_alive", "log_c_est", "r2_mean", "r2_err",
                                                  "rg2_mean", "rg2_err", "ess")},
         "device": device_info(torch),
     }
-    if args.secondary:
-        w2 = WORKLOADS[args.secondary]
-        steps2 = max(3, args.steps // 4)
-        r2 = run_gpu(w2, steps2, 1, torch, rs)
-        T2 = sum(r2["lat"]) / 1e3
-        ops2 = (lattice_alg_ops_per_chain(w2["N"]) if w2["geometry"] == "lattice"
-                else real_alg_ops_per_chain(w2["N"], w2["k"])) * w2["n_chains"]
-        ach2 = ops2 / (r2["grow_ms"] / 1e3) / 1e12
-        peak2 = VALU_PEAK_INT32_TOPS if w2["geometry"] != "real" else VALU_PEAK_FP64_TOPS
-        line["secondary"] = {
-            "workload": args.secondary, "value": w2["n_chains"] * (w2["N"] - 1) * steps2 / T2,
-            "unit": "monomer-steps/s", "steps": steps2, "ms_per_step": T2 * 1e3 / steps2,
-            "p50_ms": _percentile(r2["lat"], 0.5), "p99_ms": _percentile(r2["lat"], 0.99),
-            "roofline": {"bound": "alu", "achieved": ach2, "peak": peak2,
-                         "unit": "Tops/s", "frac": ach2 / peak2,
-                         "traffic": (measured_traffic("grow_lattice_reg", "grow_lattice.hip", args.secondary)
-                                     if w2["geometry"] == "lattice" else
-                                     measured_traffic("grow_real_tp", "grow_real.hip", args.secondary)),
-                         "kernel_ms": r2["grow_ms"], "alg_ops_per_launch": ops2},
-            "lds": (lds_object(0.0, r2["grow_ms"], "chain history in VGPRs: no LDS traffic")
-                    if w2["geometry"] == "lattice" else
-                    lds_object(real_lds_bytes_per_chain(w2["N"]) * w2["n_chains"], r2["grow_ms"],
-                               "beads read once per step")),
-            "physics": {k: r2["summary"][k] for k in ("n_alive", "log_c_est", "r2_mean",
-                                                      "r2_err", "rg2_mean", "rg2_err")},
-        }
-    if args.variant:
-        w3 = WORKLOADS[args.variant]
-        steps3 = max(3, args.steps // 4)
-        r3 = run_gpu(w3, steps3, 1, torch, rs)
-        T3 = sum(r3["lat"]) / 1e3
-        ops3 = lattice26_alg_ops_per_chain(w3["N"]) * w3["n_chains"]
-        ach3 = ops3 / (r3["grow_ms"] / 1e3) / 1e12
-        line["variant"] = {
-            "workload": args.variant, "value": w3["n_chains"] * (w3["N"] - 1) * steps3 / T3,
-            "unit": "monomer-steps/s", "steps": steps3, "ms_per_step": T3 * 1e3 / steps3,
-            "p50_ms": _percentile(r3["lat"], 0.5), "p99_ms": _percentile(r3["lat"], 0.99),
-            "roofline": {"bound": "alu", "achieved": ach3, "peak": VALU_PEAK_INT32_TOPS,
-                         "unit": "Tops/s", "frac": ach3 / VALU_PEAK_INT32_TOPS,
-                         "attainable_peak": ATTAINABLE_INT_PATH_TOPS,
-                         "frac_attainable": ach3 / ATTAINABLE_INT_PATH_TOPS,
-                         "traffic": measured_traffic("grow_lattice26_lane", "grow_lattice26.hip",
-                                                     args.variant),
-                         "kernel": "grow_lattice26_lane",
-                         "kernel_ms": r3["grow_ms"], "alg_ops_per_launch": ops3},
-            "lds": lds_object(lattice26_lds_bytes_per_chain(w3["N"]) * w3["n_chains"], r3["grow_ms"],
-                              "monomer words read once per step"),
-            "physics": {k: r3["summary"][k] for k in ("n_alive", "log_c_est", "r2_mean",
-                                                      "r2_err", "rg2_mean", "rg2_err")},
-        }
+    for key, name in (("secondary", args.secondary), ("variant", args.variant)):
+        if name:
+            line[key] = side_leg(WORKLOADS[name], name, max(3, args.steps // 4), torch, rs)
+    if args.long:
+        line["long_chains"] = [side_leg(WORKLOADS[n], n, 3, torch, rs) for n in args.long.split(",")]
     if not args.no_batch:
         line["batch"] = {"full": run_batch(torch, rs, 3),
                          "small": run_batch(torch, rs, 5, m_lo=2.0, m_span=2.0)}

@@ -536,7 +536,9 @@ rsaw_status rsaw_mapping_query(const rsaw_config *cfg, rsaw_mapping *m);
 
 /*
  * rsaw_autotune — measure every legal mapping on the device and install the
- * fastest per range of N.
+ * fastest per range of N when it beats the mapping in force (the built-in
+ * rule or an earlier entry) by at least 3 %; otherwise the mapping in force
+ * stays and nothing is installed for that range.
  *
  *   base       the workload of a probe: geometry, k, n_chains, seed, b, sigma
  *              and flags are taken from it (n_monomers is ignored).
@@ -546,9 +548,9 @@ rsaw_status rsaw_mapping_query(const rsaw_config *cfg, rsaw_mapping *m);
  *              (and most LDS-hungry) member.
  *   n_buckets  1..64.
  *   reps       timed calls per candidate (1..100), after one untimed call.
- *   chosen     host array of n_buckets, or NULL: the winning mapping of each
- *              bucket (the built-in one, unchanged, where N has no group
- *              kernel).
+ *   chosen     host array of n_buckets, or NULL: the mapping each bucket
+ *              runs with afterwards (the winner, or the mapping in force; the
+ *              built-in one, unchanged, where N has no group kernel).
  *   best_ms    host array of n_buckets, or NULL: the winner's mean time per
  *              call (growth and reduction, HIP events on `stream`).
  *   stream     hipStream_t or NULL.

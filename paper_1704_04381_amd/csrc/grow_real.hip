@@ -1,14 +1,19 @@
 // Hard-sphere chain growth in continuous space (Sec. 3.3.3, Algorithm 2;
 // weight of Eq. 3).  Trial-parallel mapping: a group of G lanes (G = 8 or the
 // next power of two >= k) serves one chain, lane t of the group owns trial t.
-// Bead coordinates (binary64) live in LDS as three planes X, Y, Z, each laid
-// out [bead][chain of block] with an XOR swizzle of the chain index (see
+// Bead coordinates (binary64) live in LDS as (x, y, z) triples laid out
+// [bead][chain of block] with an XOR swizzle of the chain index (see
 // plane_row).
 //
 // Per step i:
 //   1. lane t obtains the Marsaglia direction of trial t (Philox slot t, the
-//      first accepted attempt; rejected trials are retried by all lanes of
-//      the wave at once) and forms the candidate c_t = tip + b e;
+//      first accepted attempt) and forms the candidate c_t = tip + b e.
+//      Each trial lane keeps a short queue of the accepted pairs of its own
+//      trial for the coming steps, drawn ahead in rounds in which every lane
+//      with room tries its next attempt; a step only waits for a new round
+//      when some lane's queue is empty.  (With one chain per wave and
+//      G >= 4 k, the spare lanes instead try later attempts of the same
+//      step at once, see `spread`.);
 //   2. culling: beads i-2 and i-3 are always tested; the G lanes of the
 //      chain split beads 0 .. i-4 (lane t takes every G-th bead) and flag
 //      those whose squared tip distance is below (b + sigma)^2 (1 + 2^-30);
@@ -56,20 +61,6 @@ __device__ __forceinline__ double uniform53(uint32_t a, uint32_t b)
     return __hiloint2double((int)hi, (int)lo) - __hiloint2double((int)chi, 0);
 }
 
-// One Marsaglia attempt from a Philox block: two 53-bit uniforms on [-1, 1)
-// and acceptance of the pair strictly inside the unit disc, off its centre.
-__device__ __forceinline__ bool marsaglia_try(const Philox4 q, double &v1, double &v2, double &s)
-{
-    const double u1 = uniform53(q.x0, q.x1);
-    const double u2 = uniform53(q.x2, q.x3);
-    const double ss = u1 * u1 + u2 * u2;
-    if (ss < 1.0 && ss != 0.0) {
-        v1 = u1; v2 = u2; s = ss;
-        return true;
-    }
-    return false;
-}
-
 // OR of the G-bit groups of a wave-wide ballot: bit q is set when lane q of
 // any group of G lanes had its predicate set.
 template <int G>
@@ -88,19 +79,58 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Row length (in doubles) of the bead planes for cpb chains per block.
-// Bead j of chain c sits at j row + (c ^ ((j H) mod cpb)), H = 32 / G.  A
-// wave reads binary64 words half a wave at a time over 64 four-byte banks;
-// the culling pass has lane t of chain c read bead b0 + t (b0 a multiple of
-// G), and with cpb = 32 (G = 8, 256 threads) the 32 (t, c) pairs of a half
-// wave then fall on distinct bank pairs, as do the other accesses, where
-// all chains of a wave read the same bead index.  Smaller cpb leaves at
-// most 2-way conflicts.  G = 64 (one chain per wave, t < 32 per half wave)
-// uses an odd row and no swizzle instead.
+// One Marsaglia attempt from a Philox block: the two 53-bit uniforms on
+// [-1, 1) (always set) and whether the pair lies strictly inside the unit
+// disc, off its centre.
+__device__ __forceinline__ bool marsaglia_pair(const Philox4 q, double &u1, double &u2)
+{
+    u1 = uniform53(q.x0, q.x1);
+    u2 = uniform53(q.x2, q.x3);
+    const double ss = u1 * u1 + u2 * u2;
+    return ss < 1.0 && ss != 0.0;
+}
+
+// Row length (in elements) of the bead array for cpb chains per block.
+// Bead j of chain c is element j row + (c ^ ((j H) mod cpb)), H = 32 / G,
+// an (x, y, z) triple of 24 bytes.  A wave reads binary64 words half a wave
+// at a time over 64 four-byte banks; the culling pass has lane t of chain c
+// read bead b0 + t (b0 a multiple of G), and with cpb = 32 (G = 8, 256
+// threads) the 32 (t, c) pairs of a half wave then fall on distinct
+// elements modulo 32, whose 24-byte strides cover distinct bank pairs, as
+// do the other accesses, where all chains of a wave read the same bead
+// index.  Smaller cpb leaves at most 2-way conflicts (4-way for G = 32 in
+// 256-thread blocks).  G = 64 (one chain per wave) uses an odd row and no
+// swizzle instead.
 __host__ __device__ inline int plane_row(int cpb, int G) { return G == 64 ? (cpb | 1) : cpb; }
 
-// Orders the plane accesses of the lanes of one wave: LDS planes need the
-// wavefront scope, planes in global memory (one wave per block) the
+// Bead e of an (x, y, z) triple array.  LDS serves 8-byte reads over 32
+// banks of 8 bytes, 32 lanes per pass; the swizzle of plane_row puts the
+// lanes of a pass on distinct banks for each 8-byte read, but a 16-byte read
+// of the x, y pair (which the compiler would otherwise merge the first two
+// into) spans two banks per lane and meets 2-way conflicts.  The empty asm
+// statements keep the three reads apart.
+template <bool HBM>
+__device__ __forceinline__ void load_bead(const double *P, int e, double &x, double &y, double &z)
+{
+    if constexpr (HBM) {
+        const double *q = P + 3 * e;
+        x = q[0]; y = q[1]; z = q[2];
+    } else {
+        typedef const double __attribute__((address_space(3))) *lds_ptr;
+        lds_ptr q = (lds_ptr)(P + 3 * e);
+        x = q[0];
+        asm volatile("" : "+v"(q));
+        y = q[1];
+        asm volatile("" : "+v"(q));
+        z = q[2];
+    }
+}
+
+// Accepted Marsaglia pairs a trial lane keeps ahead of the current step.
+constexpr int kQueue = 4;
+
+// Orders the bead accesses of the lanes of one wave: beads in LDS need the
+// wavefront scope, beads in global memory (one wave per block) the
 // workgroup scope, which waits for the stores before later loads.
 template <bool HBM>
 __device__ __forceinline__ void plane_sync()
@@ -114,14 +144,12 @@ __device__ __forceinline__ void plane_sync()
     }
 }
 
-// HBM: the planes of chain `bid` live in global memory, in the region of
+// HBM: the beads of chain `bid` live in global memory, in the region of
 // resident block `slot` (one 64-lane chain per block, row 1, no swizzle).
 template <int G, bool HBM>
 __device__ __forceinline__ void grow_real_body(const GrowArgs &a, uint64_t bid, uint32_t slot = 0)
 {
-    extern __shared__ double lds[]; // X, Y, Z planes of [N][row], swizzled
-    __shared__ double logm[65];
-    for (int t = threadIdx.x; t < 65; t += blockDim.x) logm[t] = a.logm[t];
+    extern __shared__ double lds[]; // [N][row] (x, y, z) bead triples, swizzled
 
     const int cpb = blockDim.x / G;
     // wave-uniform: bead offsets of uniform bead indices stay scalar
@@ -129,20 +157,18 @@ __device__ __forceinline__ void grow_real_body(const GrowArgs &a, uint64_t bid, 
     const int swz_mul = G == 64 ? 0 : 32 / G;
     const int swz_mask = cpb - 1;
     const int N = a.n_monomers;
-    double *planes = HBM ? a.bead_slots + (size_t)slot * 3 * N : lds;
-    double *X = planes;
-    double *Y = planes + (size_t)N * row;
-    double *Z = planes + (size_t)2 * N * row;
+    double *P = HBM ? a.bead_slots + (size_t)slot * 3 * N : lds;
     const int t = threadIdx.x & (G - 1);
     const int chb = threadIdx.x / G;
     const int lane = threadIdx.x & 63;
     const int gbase = lane & ~(G - 1);
-    // element of bead j of this chain in a plane; at_t(b0) is at(b0 + t) for
-    // a wave-uniform b0 (b0 row scalar, t row computed once)
+    // element of bead j of this chain
     const auto at = [&](int j) { return j * row + (chb ^ ((j * swz_mul) & swz_mask)); };
-    int trow = t * row;
-    asm volatile("" : "+v"(trow)); // keeps b0 row + t row from being re-fused into a vector multiply
-    const auto at_t = [&](int b0) { return b0 * row + trow + (chb ^ (((b0 + t) * swz_mul) & swz_mask)); };
+    // bead b0 + t for b0 a multiple of G: (b0 H) mod cpb = 0 (32 divides b0 H
+    // and cpb <= 32), so its element is b0 row + at(t); elements past the
+    // last one are clamped to it (their results are discarded)
+    const int at_lane = at(t);
+    const int last_el = N * row - 1;
     const uint64_t gmask_bits = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
     const uint64_t c = bid * cpb + chb;
     const bool valid = c < a.n_chains;
@@ -153,8 +179,7 @@ __device__ __forceinline__ void grow_real_body(const GrowArgs &a, uint64_t bid, 
     // trials over the G lanes of the chain: lane t tries attempt t / k of
     // trial t mod k (G >= k).  Used when reps >= 4, where a second round is
     // rarely needed (measured 1.08-1.36x faster for k = 8, 256 <= N <= 1536);
-    // with fewer spare lanes the gather costs more than it saves, and each
-    // trial lane tries attempt 0 only.
+    // otherwise each trial lane draws its own trial ahead through its queue.
     const int reps = G / k;
     bool spread = false;
     if constexpr (G >= 32) spread = reps >= 4;
@@ -174,7 +199,8 @@ __device__ __forceinline__ void grow_real_body(const GrowArgs &a, uint64_t bid, 
     const double cull2 = a.cull2;
 
     if (t == 0) {
-        X[at(0)] = 0.0; Y[at(0)] = 0.0; Z[at(0)] = 0.0;
+        const int o = 3 * at(0);
+        P[o] = 0.0; P[o + 1] = 0.0; P[o + 2] = 0.0;
     }
     if constexpr (HBM) plane_sync<true>();
     __syncthreads();
@@ -185,6 +211,13 @@ __device__ __forceinline__ void grow_real_body(const GrowArgs &a, uint64_t bid, 
     uint32_t n_mine = 0; // steps with m = t + 1 (lane t counts one value of m)
     bool rng_fail = false;
     Philox4 sel{0, 0, 0, 0};
+    // this lane's queue: q1[0..lvl), q2[0..lvl) hold the accepted pairs of
+    // trial t for steps i, i + 1, ...; the next draw is step nstep, attempt natt
+    double q1[kQueue], q2[kQueue];
+#pragma unroll
+    for (int q = 0; q < kQueue; ++q) { q1[q] = 0.0; q2[q] = 0.0; }
+    int lvl = 0;
+    uint32_t nstep = 1, natt = 0;
     // the attempt that ends the chain: the first complete one, or the last
     // allowed one (one attempt without restarts); bead 0 stays at the origin
     bool res_alive = false;
@@ -195,85 +228,121 @@ __device__ __forceinline__ void grow_real_body(const GrowArgs &a, uint64_t bid, 
         if (pending) {
             tx = 0.0; ty = 0.0; tz = 0.0;
             n_mine = 0;
+            lvl = 0; nstep = 1; natt = 0;
         }
         alive = pending;
         grown = 1;
         const uint32_t hi = rd << 16; // attempt in the high half of the step word
+        // One production round of the trial queues: each lane with room
+        // tries its next attempt; an accepted pair joins the queue and the
+        // lane moves on to the next step (a lane reaching the attempt cap
+        // queues its last pair and reports the failure).  Every step runs one
+        // round while its first bead reads are in flight, and more at its end
+        // until every lane that grows a trial at the next step holds its pair.
+        const auto round = [&]() {
+            const bool room = alive && has_trial && lvl < kQueue && nstep < (uint32_t)N;
+            double u1, u2;
+            const bool ok = marsaglia_pair(draw(a.seed, g, nstep | hi, (uint32_t)t, natt), u1, u2);
+            const bool capped = !ok && natt + 1u == kMaxAttempt;
+            const bool put = room && (ok || capped);
+            rng_fail = rng_fail || (room && capped);
+#pragma unroll
+            for (int q = 0; q < kQueue; ++q) {
+                const bool here = put && lvl == q;
+                q1[q] = here ? u1 : q1[q];
+                q2[q] = here ? u2 : q2[q];
+            }
+            lvl += put ? 1 : 0;
+            nstep += put ? 1u : 0u;
+            natt = put ? 0u : natt + (room ? 1u : 0u);
+        };
+        // a lane starves when its queue is empty and the step it needs next
+        // (nstep, when the queue is empty) exists; a starving lane always has
+        // room, so every round moves it on (an acceptance, or its attempt cap)
+        const auto starving = [&]() { return alive && has_trial && lvl == 0 && nstep < (uint32_t)N; };
+        if (!spread)
+            while (__ballot(starving()) != 0) round();
 
         for (int i = 1; i < N; ++i) {
             // 1. Marsaglia direction of trial t: the first accepted attempt.
-            // Round 1: the chain's G lanes try attempts 0 .. reps-1 of its k
-            // trials (lane u: trial u mod k, attempt u / k) and each trial takes
-            // its smallest accepted one.  Round 2 (when a trial failed all of
-            // them): the 64 lanes of the wave serve the failed trials, lane l
-            // taking the failed trial of rank q = l mod nF at attempt
-            // reps + l / nF; each failed trial then takes its first accepting
-            // helper in lane order, which is its smallest accepted attempt.  Values move through the
-            // cross-lane permute network (no LDS storage).  A trial whose helpers
-            // all rejected continues alone after its last helped attempt.
             double v1 = 0.0, v2 = 0.0, s = 0.5;
             const bool need = alive && has_trial;
-            bool acc;
             if (!spread) {
-                acc = marsaglia_try(draw(a.seed, g, (uint32_t)i | hi, (uint32_t)t, 0), v1, v2, s);
+                v1 = q1[0]; v2 = q2[0];
+#pragma unroll
+                for (int q = 0; q + 1 < kQueue; ++q) { q1[q] = q1[q + 1]; q2[q] = q2[q + 1]; }
+                if (need) --lvl;
+                s = v1 * v1 + v2 * v2;
             } else {
-                // each trial takes its smallest accepted attempt among its lanes
-                double w1 = 0.0, w2 = 0.0, ws = 0.5;
-                const bool wok = marsaglia_try(draw(a.seed, g, (uint32_t)i | hi, r1_trial, r1_att), w1, w2, ws) &
+                // Round 1: the chain's G lanes try attempts 0 .. reps-1 of its
+                // k trials (lane u: trial u mod k, attempt u / k) and each
+                // trial takes its smallest accepted one.  Round 2 (when a
+                // trial failed all of them): the 64 lanes of the wave serve
+                // the failed trials, lane l taking the failed trial of rank
+                // q = l mod nF at attempt reps + l / nF; each failed trial then
+                // takes its first accepting helper in lane order, which is its
+                // smallest accepted attempt.  Values move through the
+                // cross-lane permute network (no LDS storage).  A trial whose
+                // helpers all rejected continues alone after its last helped
+                // attempt.
+                double w1 = 0.0, w2 = 0.0;
+                const bool wok = marsaglia_pair(draw(a.seed, g, (uint32_t)i | hi, r1_trial, r1_att), w1, w2) &
                                  r1_lane;
                 const uint64_t B = (__ballot(wok) >> gbase) & gmask_bits;
                 const uint64_t cand = has_trial ? ((B >> t) & r1_pattern) : 0ull;
                 const int src = cand ? gbase + t + __builtin_ctzll(cand) : lane;
                 v1 = pull_from(src, w1);
                 v2 = pull_from(src, w2);
-                s = pull_from(src, ws);
-                acc = cand != 0;
-            }
-            uint32_t att = spread ? (uint32_t)reps : 1u; // the next attempt of a trial still failing
-            const uint64_t F = __ballot(need && !acc);
-            if (F != 0) {
-                const uint32_t nF = (uint32_t)__popcll(F);
-                const bool failing = need && !acc;
-                const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(F >> 32),
-                                      __builtin_amdgcn_mbcnt_lo((uint32_t)F, 0u));
-                // lane q < nF learns the lane of the failed trial of rank q
-                const int owner_of_q = __builtin_amdgcn_ds_permute((int)((failing ? rank : 63u) * 4u), lane);
-                // l / nF and l mod nF (l < 64: the float quotient is never within
-                // rounding of an integer boundary)
-                const uint32_t jh = (uint32_t)(((float)lane + 0.5f) * __builtin_amdgcn_rcpf((float)nF));
-                const uint32_t q = (uint32_t)lane - jh * nF;
-                const int owner = __builtin_amdgcn_ds_bpermute((int)(q * 4u), owner_of_q);
-                const uint64_t og = a.chain_offset + bid * cpb +
-                                    (uint64_t)(((threadIdx.x & ~63) + (owner & ~(G - 1))) / G);
-                double h1 = 0.0, h2 = 0.0, hs = 0.5;
-                const bool hok = marsaglia_try(draw(a.seed, og, (uint32_t)i | hi, (uint32_t)(owner & (G - 1)),
-                                                    att + jh),
-                                               h1, h2, hs);
-                const uint64_t H = __ballot(hok);
-                // helpers of rank r are lanes r, r + nF, r + 2 nF, ...
-                uint64_t pattern = 0;
-                for (uint32_t l = 0; l < 64u; l += nF) pattern |= 1ull << l;
-                const uint64_t mine = failing ? (H & (pattern << rank)) : 0ull;
-                const int src = mine ? __builtin_ctzll(mine) : lane;
-                const double n1 = pull_from(src, h1), n2 = pull_from(src, h2), ns = pull_from(src, hs);
-                if (failing) {
-                    if (mine) {
-                        v1 = n1; v2 = n2; s = ns;
-                        acc = true;
-                    } else {
-                        att = att + (64u - rank + nF - 1u) / nF;
+                bool acc = cand != 0;
+                uint32_t att = (uint32_t)reps; // the next attempt of a trial still failing
+                const uint64_t F = __ballot(need && !acc);
+                if (F != 0) {
+                    const uint32_t nF = (uint32_t)__popcll(F);
+                    const bool failing = need && !acc;
+                    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(F >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)F, 0u));
+                    // lane q < nF learns the lane of the failed trial of rank q
+                    const int owner_of_q = __builtin_amdgcn_ds_permute((int)((failing ? rank : 63u) * 4u), lane);
+                    // l / nF and l mod nF (l < 64: the float quotient is never
+                    // within rounding of an integer boundary)
+                    const uint32_t jh = (uint32_t)(((float)lane + 0.5f) * __builtin_amdgcn_rcpf((float)nF));
+                    const uint32_t q = (uint32_t)lane - jh * nF;
+                    const int owner = __builtin_amdgcn_ds_bpermute((int)(q * 4u), owner_of_q);
+                    const uint64_t og = a.chain_offset + bid * cpb +
+                                        (uint64_t)(((threadIdx.x & ~63) + (owner & ~(G - 1))) / G);
+                    double h1 = 0.0, h2 = 0.0;
+                    const bool hok = marsaglia_pair(draw(a.seed, og, (uint32_t)i | hi,
+                                                         (uint32_t)(owner & (G - 1)), att + jh),
+                                                    h1, h2);
+                    const uint64_t H = __ballot(hok);
+                    // helpers of rank r are lanes r, r + nF, r + 2 nF, ...
+                    uint64_t pattern = 0;
+                    for (uint32_t l = 0; l < 64u; l += nF) pattern |= 1ull << l;
+                    const uint64_t mine = failing ? (H & (pattern << rank)) : 0ull;
+                    const int hsrc = mine ? __builtin_ctzll(mine) : lane;
+                    const double n1 = pull_from(hsrc, h1), n2 = pull_from(hsrc, h2);
+                    if (failing) {
+                        if (mine) {
+                            v1 = n1; v2 = n2;
+                            acc = true;
+                        } else {
+                            att = att + (64u - rank + nF - 1u) / nF;
+                        }
                     }
                 }
-            }
-            // round 3 (rare): the remaining trials continue alone
-            bool done = !need || acc;
-            while (!done) {
-                if (marsaglia_try(draw(a.seed, g, (uint32_t)i | hi, (uint32_t)t, att), v1, v2, s)) {
-                    done = true;
-                } else if (++att == kMaxAttempt) {
-                    rng_fail = true;
-                    done = true;
+                // round 3 (rare): the remaining trials continue alone
+                bool done = !need || acc;
+                while (!done) {
+                    double u1, u2;
+                    if (marsaglia_pair(draw(a.seed, g, (uint32_t)i | hi, (uint32_t)t, att), u1, u2)) {
+                        v1 = u1; v2 = u2;
+                        done = true;
+                    } else if (++att == kMaxAttempt) {
+                        rng_fail = true;
+                        done = true;
+                    }
                 }
+                s = v1 * v1 + v2 * v2;
             }
             const double qf = 2.0 * sqrt(1.0 - s);
             const double ex = v1 * qf, ey = v2 * qf, ez = 1.0 - 2.0 * s;
@@ -282,32 +351,53 @@ __device__ __forceinline__ void grow_real_body(const GrowArgs &a, uint64_t bid, 
             // 2-3. exact test of this lane's candidate: beads i-2 and i-3 (within
             // 2b of the tip) directly, beads 0 .. i-4 after the culling pass
             bool blocked = false; // bitwise accumulation keeps the tests branch-free
-            const auto test_bead = [&](int j) {
-                const int o = at(j);
-                const double dx = cx - X[o], dy = cy - Y[o], dz = cz - Z[o];
+            const auto test_el = [&](int e) {
+                double x, y, z;
+                load_bead<HBM>(P, e, x, y, z);
+                const double dx = cx - x, dy = cy - y, dz = cz - z;
                 double d2 = dx * dx + dy * dy;
                 d2 = d2 + dz * dz;
                 blocked = blocked | (d2 < sigma2);
             };
-            const auto is_near_at = [&](int o) {
-                const double dx = X[o] - tx, dy = Y[o] - ty, dz = Z[o] - tz;
+            const auto is_near_el = [&](int e) {
+                double x, y, z;
+                load_bead<HBM>(P, e, x, y, z);
+                const double dx = x - tx, dy = y - ty, dz = z - tz;
                 double d2 = dx * dx + dy * dy;
                 d2 = d2 + dz * dz;
                 return !(d2 >= cull2);
             };
-            if (i >= 2) test_bead(i - 2);
-            if (i >= 3) test_bead(i - 3);
+            {
+                // beads i-2 and i-3 (masked before step 2 and 3): reads, one
+                // production round while they are in flight, tests
+                double x2, y2, z2, x3, y3, z3;
+                load_bead<HBM>(P, at(i >= 2 ? i - 2 : 0), x2, y2, z2);
+                load_bead<HBM>(P, at(i >= 3 ? i - 3 : 0), x3, y3, z3);
+                if (!spread) {
+                    round();
+                    // keeps the round here, ahead of the tests that wait for the reads
+                    asm volatile("" ::"v"(lvl), "v"(natt));
+                }
+                const auto overlaps = [&](double x, double y, double z) {
+                    const double dx = cx - x, dy = cy - y, dz = cz - z;
+                    double d2 = dx * dx + dy * dy;
+                    d2 = d2 + dz * dz;
+                    return d2 < sigma2;
+                };
+                const bool o2 = overlaps(x2, y2, z2), o3 = overlaps(x3, y3, z3);
+                blocked = (i >= 2 && o2) || (i >= 3 && o3);
+            }
             const int nb = __builtin_amdgcn_readfirstlane(i - 3);
-            const int o_last = nb > 0 ? at(nb - 1) : 0; // in-plane offset for lanes past nb
             for (int b0 = 0; b0 < nb; b0 += 2 * G) {
                 // two blocks of G beads per pass, lane t taking bead b0 + t and
                 // b0 + G + t; the offsets flagged by any chain of the wave are
                 // re-tested exactly by every chain (a culled bead cannot
                 // overlap, so testing it again changes nothing)
-                // (indices clamped so that both loads issue unconditionally)
                 const int j0 = b0 + t, j1 = b0 + G + t;
-                const bool d0 = is_near_at(j0 < nb ? at_t(b0) : o_last);
-                const bool d1 = is_near_at(j1 < nb ? at_t(b0 + G) : o_last);
+                const int e0 = min(b0 * row + at_lane, last_el);
+                const int e1 = min((b0 + G) * row + at_lane, last_el);
+                const bool d0 = is_near_el(e0);
+                const bool d1 = is_near_el(e1);
                 const bool n0 = alive & (j0 < nb) & d0;
                 const bool n1 = alive & (j1 < nb) & d1;
                 uint64_t u0 = fold_groups<G>(__ballot(n0));
@@ -315,12 +405,12 @@ __device__ __forceinline__ void grow_real_body(const GrowArgs &a, uint64_t bid, 
                 while (u0) {
                     const int q = __builtin_ctzll(u0);
                     u0 &= u0 - 1;
-                    test_bead(b0 + q);
+                    test_el(at(b0 + q));
                 }
                 while (u1) {
                     const int q = __builtin_ctzll(u1);
                     u1 &= u1 - 1;
-                    test_bead(b0 + G + q);
+                    test_el(at(b0 + G + q));
                 }
             }
 
@@ -358,12 +448,14 @@ __device__ __forceinline__ void grow_real_body(const GrowArgs &a, uint64_t bid, 
             }
             if (alive) {
                 if (chosen) {
-                    const int o = at(i);
-                    X[o] = nx; Y[o] = ny; Z[o] = nz;
+                    const int o = 3 * at(i);
+                    P[o] = nx; P[o + 1] = ny; P[o + 2] = nz;
                 }
                 tx = nx; ty = ny; tz = nz;
                 n_mine += (m == (uint32_t)t + 1u) ? 1u : 0u;
             }
+            if (!spread)
+                while (__ballot(starving()) != 0) round();
             plane_sync<HBM>();
         }
         if (alive) grown = N;
@@ -374,7 +466,7 @@ __device__ __forceinline__ void grow_real_body(const GrowArgs &a, uint64_t bid, 
         double lw = 0.0;
         for (int mm = 1; mm <= k; ++mm) {
             const uint32_t nm = __shfl(n_mine, gbase + mm - 1, 64);
-            lw = lw + (double)nm * logm[mm];
+            lw = lw + (double)nm * a.logm[mm];
         }
         if (!alive) lw = -__builtin_huge_val();
 
@@ -382,21 +474,21 @@ __device__ __forceinline__ void grow_real_body(const GrowArgs &a, uint64_t bid, 
         if (ends && t == 0 && valid) {
             double sx = 0.0, sy = 0.0, sz = 0.0;
             for (int j = 0; j < grown; ++j) {
-                const int o = at(j);
-                sx = sx + X[o]; sy = sy + Y[o]; sz = sz + Z[o];
+                const int o = 3 * at(j);
+                sx = sx + P[o]; sy = sy + P[o + 1]; sz = sz + P[o + 2];
             }
             const double gd = (double)grown;
             const double cmx = sx / gd, cmy = sy / gd, cmz = sz / gd;
             double acc = 0.0;
             for (int j = 0; j < grown; ++j) {
-                const int o = at(j);
-                const double dx = X[o] - cmx, dy = Y[o] - cmy, dz = Z[o] - cmz;
+                const int o = 3 * at(j);
+                const double dx = P[o] - cmx, dy = P[o + 1] - cmy, dz = P[o + 2] - cmz;
                 double q = dx * dx + dy * dy;
                 q = q + dz * dz;
                 acc = acc + q;
             }
-            const int oe = at(grown - 1);
-            const double ex = X[oe], ey = Y[oe], ez = Z[oe];
+            const int oe = 3 * at(grown - 1);
+            const double ex = P[oe], ey = P[oe + 1], ez = P[oe + 2];
             double r2 = ex * ex + ey * ey;
             r2 = r2 + ez * ez;
             if (a.log_w) a.log_w[c] = lw;
@@ -470,7 +562,7 @@ static hipError_t real_shape(int N, int k, int G, int threads, GrowVariant *v)
     if (G < k) return hipErrorInvalidValue;
     if (threads != 64 && (threads != 256 || G == 64)) return hipErrorInvalidValue;
     const size_t planes = (size_t)3 * N * plane_row(threads / G, G) * sizeof(double);
-    if (planes + 65 * sizeof(double) > 163840) return hipErrorInvalidValue;
+    if (planes > 163840) return hipErrorInvalidValue;
     v->family = 2;
     v->p0 = G;
     v->p1 = 0;

@@ -1176,6 +1176,9 @@ rsaw_status rsaw_mapping_query(const rsaw_config *cfg, rsaw_mapping *m)
     return query_mapping(cfg, m);
 }
 
+// Relative speed-up a tuned mapping needs over the mapping in force.
+constexpr double kTuneMargin = 0.03;
+
 rsaw_status rsaw_autotune(const rsaw_config *base, const int32_t *n_edges, int32_t n_buckets,
                           int32_t reps, rsaw_mapping *chosen, double *best_ms, void *stream)
 {
@@ -1225,6 +1228,17 @@ rsaw_status rsaw_autotune(const rsaw_config *base, const int32_t *n_edges, int32
         rsaw_mapping win;
         st = query_mapping(&c, &win);
         if (st != RSAW_OK) break;
+        // the mapping in force (built-in rule or an earlier entry), timed
+        // first: a candidate replaces it only when it is at least
+        // kTuneMargin faster, so that timing noise does not move ensembles
+        // away from a mapping that also suits co-scheduled launches
+        const rsaw_mapping cur = win;
+        double cur_ms = -1.0;
+        if (cur.lanes >= 2) {
+            ForceMapping f(cur.lanes, cur.threads);
+            st = time_calls(c, &cur_ms);
+            if (st != RSAW_OK) break;
+        }
         double win_ms = -1.0;
         bool tuned = false;
         for (int lanes : kLanes) {
@@ -1250,6 +1264,10 @@ rsaw_status rsaw_autotune(const rsaw_config *base, const int32_t *n_edges, int32
             // no group kernel at this N: the built-in kernel, timed as is
             st = time_calls(c, &win_ms);
             if (st != RSAW_OK) break;
+        } else if (cur_ms >= 0.0 && !(win_ms < cur_ms * (1.0 - kTuneMargin))) {
+            win = cur; // no candidate clearly faster: keep the mapping in force
+            win_ms = cur_ms;
+            tuned = false;
         }
         win.n_lo = b == 0 ? 1 : n_edges[b - 1] + 1;
         win.n_hi = n_edges[b];

@@ -24,6 +24,17 @@ WORKLOADS = {
     # coordinates, FP64 log W, 256-bin histogram.
     "lattice26_n64": dict(geometry="lattice26", N=64, k=26, n_chains=10_000_000, seed=1,
                           coord="i16", exact_w=False, hist_bins=256),
+    # Long chains (LDS-resident group kernels): simple cubic lattice at
+    # N = 256 (10^6 chains) and N = 2048 (10^5 chains), 26-neighbour lattice
+    # likewise, int16 coordinates, FP64 log W, no histogram.
+    "lattice_n256": dict(geometry="lattice", N=256, k=6, n_chains=1_000_000, seed=1,
+                         coord="i16", exact_w=False, hist_bins=0),
+    "lattice_n2048": dict(geometry="lattice", N=2048, k=6, n_chains=100_000, seed=1,
+                          coord="i16", exact_w=False, hist_bins=0),
+    "lattice26_n256": dict(geometry="lattice26", N=256, k=26, n_chains=1_000_000, seed=1,
+                           coord="i16", exact_w=False, hist_bins=0),
+    "lattice26_n2048": dict(geometry="lattice26", N=2048, k=26, n_chains=100_000, seed=1,
+                            coord="i16", exact_w=False, hist_bins=0),
 }
 
 

@@ -63,7 +63,8 @@ def _case(N, M, seed, coord="i32", exact_w=False, bins=0, offset=0, restart=Fals
 @pytest.mark.parametrize("N,M,seed,coord", [
     (1, 300, 1, "i32"), (2, 257, 2, "i16"), (3, 1_000, 3, "i32"), (5, 999, 4, "i16"),
     (16, 5_000, 5, "i32"), (64, 20_000, 6, "i16"), (100, 3_001, 7, "i32"),
-    (129, 1_000, 8, "i16"), (161, 500, 10, "i16"), (300, 700, 9, "i32"), (600, 200, 14, "i16")])
+    (129, 1_000, 8, "i16"), (161, 500, 10, "i16"), (256, 1_500, 15, "i16"), (257, 600, 16, "i32"),
+    (300, 700, 9, "i32"), (512, 150, 17, "i32"), (513, 120, 18, "i16"), (600, 200, 14, "i16")])
 def test_lattice26_bit_exact(N, M, seed, coord):
     _case(N, M, seed, coord=coord, bins=256 if N > 1 else 0)
 
@@ -82,6 +83,8 @@ def test_lattice26_long_chains(N, M, seed, coord):
 
 def test_lattice26_offset_and_restart():
     _case(64, 2_000, 31, offset=123_456_789, bins=32)
+    # the group kernel (G = 8): offset past 2^32 and restart
+    _case(200, 800, 34, offset=(1 << 32) + 5, bins=32, restart=True)
     a, sa = _case(40, 3_000, 32, restart=True)
     b, sb = _case(40, 3_000, 32, restart=False)
     for key in a:

@@ -105,13 +105,22 @@ def test_lattice_bit_exact(N, M, seed, coord):
 
 @pytest.mark.parametrize("N,M,seed,coord", [
     # LDS kernel: byte words with 4 lanes per chain (N <= 128), wide words with
-    # 8 (N <= 512), 32 (N <= 2048) and 64 lanes per chain, up to the largest N
+    # 8 (N <= 256; one and two scan passes of 32 entries around N = 256), 16
+    # (N <= 512), 32 (N <= 2048) and 64 lanes per chain, up to the largest N
     (65, 3_001, 21, "i16"), (100, 1_500, 22, "i32"), (128, 2_000, 23, "i16"),
-    (129, 801, 24, "i32"), (300, 333, 25, "i16"), (512, 300, 26, "i32"),
+    (129, 801, 24, "i32"), (256, 2_000, 41, "i16"), (257, 700, 42, "i32"),
+    (300, 333, 25, "i16"), (512, 300, 26, "i32"),
     (513, 200, 27, "i16"), (2_048, 60, 28, "i32"), (2_049, 40, 29, "i16"),
     (5_000, 12, 30, "i32"), (16_384, 3, 31, "i16")])
 def test_lattice_long_chains_bit_exact(N, M, seed, coord):
     _lattice_case(N, M, seed, coord=coord, bins=256)
+
+
+def test_lattice_long_offset_and_dead_chains():
+    # the LDS kernel with a chain offset past 2^32; N = 400 chains meet dead
+    # ends often enough to cover that branch
+    out, _ = _lattice_case(400, 2_000, 43, coord="i32", bins=64, offset=(1 << 32) + 5)
+    assert (out["n_grown"].view(np.uint16) < 400).sum() > 10
 
 
 def test_lattice_dead_chains_bit_exact():
