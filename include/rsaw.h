@@ -441,13 +441,16 @@ rsaw_status rsaw_set_workspace(void *d_ws, size_t bytes, void *stream);
 
 /*
  * rsaw_fp64_check — evaluate binary64 square roots and quotients on the
- * device with the compiler settings of the growth kernels (no contraction,
- * the same target), for checking that they are correctly rounded: the
- * hard-sphere kernels take sqrt in the Marsaglia step (Sec. 3.3.3,
- * q = 2 sqrt(1 - s)) and divisions in the centre of mass and Rg^2.
+ * device as the growth kernels do (no contraction, the same target), for
+ * checking that they are correctly rounded: the hard-sphere kernels take
+ * the square root of 1 - s in the Marsaglia step (Sec. 3.3.3,
+ * q = 2 sqrt(1 - s)) with their own routine for arguments in [2^-60, 1],
+ * and divide in the centre of mass and Rg^2.
  *
  *   d_a, d_b        device arrays of n doubles (inputs).
- *   d_sqrt, d_div   device arrays of n doubles: sqrt(a_i) and a_i / b_i.
+ *   d_sqrt, d_div   device arrays of n doubles: sqrt(a_i) (the kernels'
+ *                   routine for a_i in [2^-60, 1], the general device square
+ *                   root elsewhere) and a_i / b_i.
  *   n               element count (0 does nothing).
  *   stream          hipStream_t or NULL.  Asynchronous.
  * Errors: RSAW_E_INVALID for a NULL array with n > 0; RSAW_E_DEVICE for a

@@ -1,13 +1,15 @@
-// Device binary64 square root and division, compiled with the settings of
-// the growth kernels, so that a host program can check them against the
-// correctly rounded host results (the hard-sphere kernels rely on both being
-// correctly rounded to match the CPU bit for bit; Sec. 3.3.3).
+// Device binary64 square root and division as the growth kernels evaluate
+// them (their settings; the hard-sphere kernels' own square root on
+// [2^-60, 1]), so that a host program can check them against the correctly
+// rounded host results (the hard-sphere kernels rely on both being correctly
+// rounded to match the CPU bit for bit; Sec. 3.3.3).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <string>
 
 #include "rsaw.h"
+#include "rsaw_device.hpp"
 
 namespace rsaw {
 
@@ -17,7 +19,8 @@ __global__ __launch_bounds__(256) void fp64_check_kernel(const double *a, const 
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const double x = a[i];
-        sq[i] = sqrt(x);
+        // the hard-sphere kernels' square root on its domain, else the general one
+        sq[i] = (x >= 0x1p-60 && x <= 1.0) ? sqrt_unit(x) : sqrt(x);
         dv[i] = x / b[i];
     }
 }

@@ -19,9 +19,11 @@
 //   24-bit multiply-add);  occ |= bit << code
 // ten operations per pair.  The G partial masks are OR-reduced across the
 // group; every lane then picks the same r-th free code (Lemire on the same
-// 16-bit words as the six-neighbour lattice), and lane (m - 1) mod G counts
-// the steps with m free candidates for log W.  Short chains (N <= 64) use
-// the one-lane-per-chain kernel further down.
+// 16-bit words as the six-neighbour lattice; the code by a binary search
+// over the free mask, the move computed from the code, so that the step
+// makes no LDS table lookup), and lane (m - 1) mod G counts the steps with
+// m free candidates for log W.  Short chains (N <= 64) use the
+// one-lane-per-chain kernel further down.
 #include "rsaw_device.hpp"
 
 namespace rsaw {
@@ -56,7 +58,6 @@ typedef short short2_t __attribute__((ext_vector_type(2)));
 constexpr uint32_t kZ26OriginA = 0x80008000u; // x = y = 0
 constexpr uint32_t kZ26OriginB = 0x00008000u; // z = 0 (also the B sentinel)
 constexpr uint32_t kZ26Codes = 0x7FFFFFFu & ~(1u << 13);
-constexpr int kZ26GroupHead = 64 + 512; // words before the chains: two move tables, select table
 
 __device__ __forceinline__ uint32_t z26_bits(uint32_t wa, uint32_t wb, uint32_t ta, uint32_t tb)
 {
@@ -90,6 +91,33 @@ __device__ __forceinline__ uint32_t z26_select(uint32_t f, uint32_t r, const uin
     return k + sel[byte * 8 + (r - before)];
 }
 
+// Index of the r-th (from 0) set bit of f, r < popcount(f): a binary search
+// over halves of the remaining word, in registers.
+__device__ __forceinline__ uint32_t z26_select_bits(uint32_t f, uint32_t r)
+{
+    uint32_t pos = 0;
+#pragma unroll
+    for (int w = 16; w >= 1; w >>= 1) {
+        const uint32_t c = __builtin_popcount(f & ((1u << w) - 1u));
+        const bool up = r >= c;
+        r = up ? r - c : r;
+        f = up ? f >> w : f;
+        pos = up ? pos + (uint32_t)w : pos;
+    }
+    return pos;
+}
+
+// A- and B-word moves of code c = (dx + 1) + 3 (dy + 1) + 9 (dz + 1), c < 27.
+__device__ __forceinline__ void z26_move(uint32_t code, uint32_t &da, uint32_t &db)
+{
+    const uint32_t z = (code * 57u) >> 9;         // code / 9
+    const uint32_t rem = code - 9u * z;
+    const uint32_t y = (rem * 11u) >> 5;          // rem / 3
+    const uint32_t x = rem - 3u * y;
+    da = (x - 1u) + ((y - 1u) << 16);
+    db = z - 1u;
+}
+
 __device__ __forceinline__ void z26_fill_select_table(uint8_t *sel)
 {
     for (int q = threadIdx.x; q < 2048; q += blockDim.x) {
@@ -105,18 +133,9 @@ __device__ __forceinline__ void grow_lattice26_body(const GrowArgs &a, uint64_t 
 {
     const int cpb = blockDim.x / G;
     extern __shared__ uint32_t z26_lds[];
-    uint32_t *lutA = z26_lds;                    // [27] A-word move of each code
-    uint32_t *lutB = z26_lds + 32;               // [27] B-word move
-    uint8_t *sel = (uint8_t *)(z26_lds + 64);    // [256][8] select table
-    uint32_t *chains = z26_lds + kZ26GroupHead;  // cpb chains of 2 H words
+    uint32_t *chains = z26_lds; // cpb chains of 2 H words
     __shared__ double logm[27];
-    for (int q = threadIdx.x; q < 27; q += blockDim.x) {
-        const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = q / 9 - 1;
-        lutA[q] = (uint32_t)(dx + dy * 65536);
-        lutB[q] = (uint32_t)dz;
-        logm[q] = a.logm[q];
-    }
-    z26_fill_select_table(sel);
+    for (int q = threadIdx.x; q < 27; q += blockDim.x) logm[q] = a.logm[q];
     for (int w = threadIdx.x; w < cpb * 2 * H; w += blockDim.x) chains[w] = (w / H) & 1 ? kZ26OriginB : 0u;
     __syncthreads();
 
@@ -210,7 +229,7 @@ __device__ __forceinline__ void grow_lattice26_body(const GrowArgs &a, uint64_t 
                     r = 0;
                 }
             }
-            const uint32_t code = m ? z26_select(freem, r, sel) : 13u; // the r-th free code
+            const uint32_t code = m ? z26_select_bits(freem, r) : 13u; // the r-th free code
 
             const bool step_ok = alive && m != 0;
             if (alive && m == 0) {
@@ -218,8 +237,10 @@ __device__ __forceinline__ void grow_lattice26_body(const GrowArgs &a, uint64_t 
                 grown = i;
             }
             if (step_ok) {
-                ta = ta + lutA[code];
-                tb = tb + lutB[code];
+                uint32_t da, db;
+                z26_move(code, da, db);
+                ta = ta + da;
+                tb = tb + db;
                 const uint32_t mm1 = m - 1u;
                 n_mine += (mm1 & (G - 1)) == (uint32_t)t ? 1ull << (FW * (mm1 / G)) : 0ull;
                 if (EXACT) wx = wx * (uint64_t)m;
@@ -534,7 +555,7 @@ static hipError_t z26_shape(int N, bool i16, int G, int threads, GrowVariant *v)
     if (threads != 64 && threads != 256) return hipErrorInvalidValue;
     if (G == 4 && N > 256) return hipErrorInvalidValue;
     const int H = (N + 4 * G - 1) / (4 * G) * (4 * G);
-    const size_t bytes = ((size_t)kZ26GroupHead + (size_t)(threads / G) * 2 * H) * sizeof(uint32_t);
+    const size_t bytes = (size_t)(threads / G) * 2 * H * sizeof(uint32_t);
     if (bytes > 163840) return hipErrorInvalidValue;
     v->family = 3;
     v->p0 = G;

@@ -344,7 +344,7 @@ __device__ __forceinline__ void grow_real_body(const GrowArgs &a, uint64_t bid, 
                 }
                 s = v1 * v1 + v2 * v2;
             }
-            const double qf = 2.0 * sqrt(1.0 - s);
+            const double qf = 2.0 * sqrt_unit(1.0 - s); // 1 - s in [2^-53, 1)
             const double ex = v1 * qf, ey = v2 * qf, ez = 1.0 - 2.0 * s;
             const double cx = tx + b * ex, cy = ty + b * ey, cz = tz + b * ez;
 
@@ -388,29 +388,51 @@ __device__ __forceinline__ void grow_real_body(const GrowArgs &a, uint64_t bid, 
                 blocked = (i >= 2 && o2) || (i >= 3 && o3);
             }
             const int nb = __builtin_amdgcn_readfirstlane(i - 3);
-            for (int b0 = 0; b0 < nb; b0 += 2 * G) {
-                // two blocks of G beads per pass, lane t taking bead b0 + t and
-                // b0 + G + t; the offsets flagged by any chain of the wave are
-                // re-tested exactly by every chain (a culled bead cannot
-                // overlap, so testing it again changes nothing)
-                const int j0 = b0 + t, j1 = b0 + G + t;
-                const int e0 = min(b0 * row + at_lane, last_el);
-                const int e1 = min((b0 + G) * row + at_lane, last_el);
-                const bool d0 = is_near_el(e0);
-                const bool d1 = is_near_el(e1);
-                const bool n0 = alive & (j0 < nb) & d0;
-                const bool n1 = alive & (j1 < nb) & d1;
-                uint64_t u0 = fold_groups<G>(__ballot(n0));
-                uint64_t u1 = fold_groups<G>(__ballot(n1));
-                while (u0) {
-                    const int q = __builtin_ctzll(u0);
-                    u0 &= u0 - 1;
-                    test_el(at(b0 + q));
+            // Culling passes of two blocks of G beads, lane t taking beads
+            // b0 + t and b0 + G + t; the offsets flagged by any chain of the
+            // wave are re-tested exactly by every chain (a culled bead cannot
+            // overlap, so testing it again changes nothing), two at a time so
+            // that their reads are in flight together.  (Four blocks per pass
+            // measured 4 % slower at N = 64, k = 8.)
+            constexpr int PB = 2;
+            const auto retest = [&](uint64_t u, int base) {
+                while (u) {
+                    const int qa = __builtin_ctzll(u);
+                    u &= u - 1;
+                    if (u) {
+                        const int qb = __builtin_ctzll(u);
+                        u &= u - 1;
+                        double xa, ya, za, xb, yb, zb;
+                        load_bead<HBM>(P, at(base + qa), xa, ya, za);
+                        load_bead<HBM>(P, at(base + qb), xb, yb, zb);
+                        const auto hit = [&](double x, double y, double z) {
+                            const double dx = cx - x, dy = cy - y, dz = cz - z;
+                            double d2 = dx * dx + dy * dy;
+                            d2 = d2 + dz * dz;
+                            return d2 < sigma2;
+                        };
+                        const bool ha = hit(xa, ya, za), hb = hit(xb, yb, zb);
+                        blocked = blocked || ha || hb;
+                    } else {
+                        test_el(at(base + qa));
+                    }
                 }
-                while (u1) {
-                    const int q = __builtin_ctzll(u1);
-                    u1 &= u1 - 1;
-                    test_el(at(b0 + G + q));
+            };
+            for (int b0 = 0; b0 < nb; b0 += PB * G) {
+                bool nearv[PB];
+#pragma unroll
+                for (int pb = 0; pb < PB; ++pb) {
+                    const int e = min((b0 + pb * G) * row + at_lane, last_el);
+                    nearv[pb] = alive & (b0 + pb * G + t < nb) & is_near_el(e);
+                }
+                if constexpr (PB * G <= 64) {
+                    uint64_t u = 0;
+#pragma unroll
+                    for (int pb = 0; pb < PB; ++pb) u |= fold_groups<G>(__ballot(nearv[pb])) << (pb * G);
+                    retest(u, b0);
+                } else {
+#pragma unroll
+                    for (int pb = 0; pb < PB; ++pb) retest(fold_groups<G>(__ballot(nearv[pb])), b0 + pb * G);
                 }
             }
 

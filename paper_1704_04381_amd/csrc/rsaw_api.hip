@@ -580,12 +580,10 @@ rsaw_status batch_impl(const rsaw_config *cfgs, const rsaw_chain_out *outs, int3
     std::vector<rsaw::GrowVariant> var(n);
     size_t off = 0;
     int max_bins = 0;
-    uint64_t red_blocks = 0;
     for (int32_t i = 0; i < n; ++i) {
         in[i] = outs ? outs[i] : rsaw_chain_out{};
         layout_ensemble(&cfgs[i], in[i], reduce, &off, &L[i]);
         max_bins = std::max(max_bins, L[i].bins);
-        red_blocks += L[i].n_blocks;
         e = ensemble_variant(&cfgs[i], L[i], &var[i]);
         if (e != hipSuccess) return fail(RSAW_E_UNSUPPORTED, "ensemble " + std::to_string(i) + ": no kernel variant");
     }

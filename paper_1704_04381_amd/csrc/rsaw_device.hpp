@@ -49,6 +49,25 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
     return Philox4{c0, c1, c2, c3};
 }
 
+// Square root of x in [2^-60, 1], correctly rounded (checked bit for bit
+// against the host over the Marsaglia domain 1 - s by rsaw_fp64_check): the
+// hardware estimate y of 1/sqrt(x), refined by Goldschmidt's iteration to
+// g ~ sqrt(x) and h ~ 1/(2 g), then two Newton corrections of g on the
+// remainder x - g^2, each a fused multiply-add.  Without the scaling and the
+// special cases of the general square root, which this domain never needs.
+__device__ __forceinline__ double sqrt_unit(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double e = __builtin_fma(-h, g, 0.5);
+    g = __builtin_fma(g, e, g);
+    h = __builtin_fma(h, e, h);
+    double d = __builtin_fma(-g, g, x);
+    g = __builtin_fma(d, h, g);
+    d = __builtin_fma(-g, g, x);
+    return __builtin_fma(d, h, g);
+}
+
 __device__ __forceinline__ Philox4 draw(uint64_t seed, uint64_t g, uint32_t c2, uint32_t slot,
                                         uint32_t attempt)
 {

@@ -1,8 +1,9 @@
 """Device binary64 square root and division against the host.
 
 The hard-sphere kernels reproduce the oracle bit for bit only if the device
-sqrt (Marsaglia's q = 2 sqrt(1 - s), Sec. 3.3.3) and division (centre of
-mass, Rg^2) are correctly rounded, as the host's are (IEEE 754).  This runs
+sqrt (Marsaglia's q = 2 sqrt(1 - s), Sec. 3.3.3, with the kernels' own
+routine on [2^-60, 1]) and division (centre of mass, Rg^2) are correctly
+rounded, as the host's are (IEEE 754).  This runs
 rsaw_fp64_check, compiled with the growth kernels' settings, on 2^21
 inputs of each kind: the Marsaglia domain 1 - s for s in (0, 1) drawn as
 the kernels draw it, uniform mantissas over many binades, the subnormal
@@ -32,12 +33,19 @@ def _inputs(n, seed):
     sub = (g.integers(1, 1 << 52, size=n // 8, dtype=np.uint64)).view(np.float64)
     edge = np.array([0.0, 1.0, 2.0, 0.25, 1.0 - 2.0**-53, 1.0 + 2.0**-52, np.finfo(np.float64).tiny,
                      np.finfo(np.float64).max, 5e-324, 4.0, 9.0, 1e300, 1e-300])
-    a = np.concatenate([dom, wide, sub, edge])
+    # the domain [2^-60, 1] of the hard-sphere kernels' own square root,
+    # uniform mantissas in every binade, and its end points
+    e2 = g.integers(1023 - 60, 1023, size=n // 4, dtype=np.uint64)
+    m2 = g.integers(0, 1 << 52, size=n // 4, dtype=np.uint64)
+    unit = np.concatenate([((e2 << np.uint64(52)) | m2).view(np.float64),
+                           np.array([2.0**-60, 2.0**-53, 0.5, 1.0 - 2.0**-53])])
+    a = np.concatenate([dom, wide, sub, edge, unit])
     # divisors: sums of bead counts as the kernels divide by (1..16384), and
     # random doubles
     b = np.concatenate([g.integers(1, 16385, size=len(dom)).astype(np.float64),
                         wide[::-1].copy(), g.integers(1, 1 << 20, size=len(sub)).astype(np.float64),
-                        np.array([1.0, 3.0, 7.0, 3.0, 3.0, 3.0, 3.0, 2.0, 3.0, 3.0, 3.0, 7.0, 7.0])])
+                        np.array([1.0, 3.0, 7.0, 3.0, 3.0, 3.0, 3.0, 2.0, 3.0, 3.0, 3.0, 7.0, 7.0]),
+                        g.integers(1, 16385, size=len(unit)).astype(np.float64)])
     return a, b
 
 
