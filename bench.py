@@ -159,10 +159,11 @@ def path_model(w) -> dict:
 
 
 def lattice_lds_bytes_per_chain(N: int) -> int:
-    """Algorithmic LDS bytes of one long lattice chain (two 4-byte words per
-    monomer): per step i the floor(i/2) monomers of the tip's opposite
-    parity are read once, and the new monomer is written."""
-    return sum(8 * (i // 2) + 8 for i in range(1, N))
+    """Algorithmic LDS bytes of one long lattice chain (one 4-byte word per
+    monomer up to N = 512, two beyond): per step i the floor(i/2) monomers of
+    the tip's opposite parity are read once, and the new monomer is written."""
+    w = 4 if N <= 512 else 8
+    return sum(w * (i // 2) + w for i in range(1, N))
 
 
 def roofline_object(pm: dict, kernel_ms: float, workload: str) -> dict:

@@ -480,7 +480,11 @@ rsaw_status rsaw_fp64_check(const double *d_a, const double *d_b, double *d_sqrt
  * chain's scan.
  *
  * Legal mappings:
- *   RSAW_LATTICE_SC  lanes 4 (N <= 128 only), 8, 16, 32, 64;
+ *   RSAW_LATTICE_SC  lanes 4 (N <= 2048 only), 8, 16, 32, 64; up to
+ *                    N = 2048 one 4-byte word per monomer (see
+ *                    rsaw_set_byte_box) where the block can also hold one
+ *                    chain's regrowth (all but 64 lanes in 64-thread
+ *                    blocks beyond N = 768), else two;
  *   RSAW_REAL_HS     lanes 8, 16, 32, 64 with lanes >= k; lanes 64 only
  *                    with 64 threads; N <= 1536;
  *   RSAW_LATTICE_26  lanes 4 (N <= 256 only), 8, 16, 32, 64;
@@ -509,6 +513,19 @@ typedef struct {
  * range, n_lo < 1, n_hi < n_lo, or a mapping that is not legal at n_hi.
  */
 rsaw_status rsaw_mapping_set(const rsaw_mapping *m);
+
+/*
+ * rsaw_set_byte_box — tuning and testing knob of the lattice kernels with
+ * one byte per coordinate beyond N = 128 (Sec. 3.3.2 growth on the simple
+ * cubic lattice): a chain whose tip reaches |x|, |y| or |z| = edge is
+ * dropped from the byte-word kernel and grown again, from its first draw,
+ * in two-word format by the same block.  The default, 127, is the largest
+ * exact edge; a smaller one only sends more chains through the regrowth.
+ * Results never depend on it: every chain is bit-identical either way.
+ * Process-wide; applies to calls enqueued after it.  Host-only.
+ * Errors: RSAW_E_INVALID unless 1 <= edge <= 127.
+ */
+rsaw_status rsaw_set_byte_box(int32_t edge);
 
 /* rsaw_mapping_clear — empty the tuning table (the built-in rule applies
  * again to every later call).  Thread-safe. */

@@ -75,7 +75,8 @@ EXPORTS = ["rsaw_gen_chains", "rsaw_gen_chains_sync", "rsaw_gen_batch", "rsaw_se
            "rsaw_last_error", "rsaw_version", "rsaw_kernel_timing", "rsaw_kernel_time",
            "rsaw_workspace_size", "rsaw_mapping_set", "rsaw_mapping_clear", "rsaw_mapping_list", "rsaw_mapping_query",
            "rsaw_autotune", "rsaw_batch_plan_create", "rsaw_batch_plan_launch", "rsaw_batch_plan_destroy",
-           "rsaw_set_workspace", "rsaw_fp64_check", "rsaw_gen_chains_static", "rsaw_shutdown"]
+           "rsaw_set_workspace", "rsaw_fp64_check", "rsaw_gen_chains_static", "rsaw_shutdown",
+           "rsaw_set_byte_box"]
 
 _lib = None
 _lock = threading.Lock()
@@ -140,6 +141,8 @@ def load(path: str = LIB_PATH):
         lib.rsaw_mapping_set.restype = C.c_int
         lib.rsaw_mapping_clear.argtypes = []
         lib.rsaw_mapping_clear.restype = None
+        lib.rsaw_set_byte_box.argtypes = [C.c_int32]
+        lib.rsaw_set_byte_box.restype = C.c_int
         lib.rsaw_mapping_list.argtypes = [C.POINTER(rsaw_mapping), C.c_int32, C.POINTER(C.c_int32)]
         lib.rsaw_mapping_list.restype = C.c_int
         lib.rsaw_mapping_query.argtypes = [C.POINTER(rsaw_config), C.POINTER(rsaw_mapping)]
@@ -525,6 +528,13 @@ def mapping_set(geometry, k, n_lo, n_hi, lanes, threads) -> None:
 def mapping_clear() -> None:
     """Empty the tuning table (rsaw_mapping_clear)."""
     load().rsaw_mapping_clear()
+
+
+def set_byte_box(edge: int) -> None:
+    """|coordinate| at which the lattice byte-word kernels beyond N = 128
+    regrow a chain in two-word format (rsaw_set_byte_box; 1..127, default
+    127).  Results do not depend on it."""
+    _check(load().rsaw_set_byte_box(int(edge)))
 
 
 def mapping_list() -> list[dict]:

@@ -81,41 +81,56 @@ __device__ __forceinline__ uint32_t pair_bits(uint32_t wa, uint32_t wb, uint32_t
     }
 }
 
-template <int G, bool WIDE, typename CT>
-__device__ __forceinline__ void grow_lattice_lds_body(const GrowArgs &a, uint64_t bid, int H, int S)
-{
-    constexpr int WPM = WIDE ? 2 : 1; // words per monomer
-    const int cpb = blockDim.x / G;   // chains per block
-    extern __shared__ uint32_t lds_u[];
-    uint32_t *lut = lds_u;                       // byte-format move, or the A move
-    uint32_t *lutb = lds_u + kLutSize;           // B move (wide only)
-    uint32_t *chains = lds_u + WPM * kLutSize;   // cpb chains of S words
+// Byte words hold each coordinate plus 128 in one byte.  Up to N = 128 no
+// coordinate can leave [-127, 127].  Longer chains ("boxed" byte words)
+// stop growing a chain whose new tip reaches |coordinate| = E (the launch's
+// byte_box, 127 unless a caller lowers it), before the byte test and the
+// carry-free move could stop being exact at -128 and +128; the block then
+// grows that chain again from its first draw in wide words (the same draws
+// and the same tests give the same chain, Sec. 3.3.2), so every chain's
+// result is exact whichever word format produced it.
+constexpr int kByteExactN = 128;
+constexpr int kByteBoxedMaxN = 2048;
+constexpr int kRegrowListWords = 65; // count + one slot per chain of a block (<= 64)
 
+// A- and B-word deltas of a byte-format move (coordinate bytes | dQ).
+__device__ __forceinline__ void wide_move(uint32_t mv, uint32_t &da, uint32_t &db)
+{
+    const int dq = (int)(int8_t)(mv & 0xFFu);
+    const int axis = dq < 0 ? -dq : dq;
+    const int sg = dq < 0 ? -1 : 1;
+    da = axis == 1 ? (uint32_t)sg : (axis == 2 ? (uint32_t)(sg * 65536) : 0u);
+    db = (uint32_t)((axis == 3 ? sg * 65536 : 0) + dq);
+}
+
+__device__ __forceinline__ void lattice_lds_luts(uint32_t *lut, uint32_t *lutb, bool wide)
+{
     for (int idx = threadIdx.x; idx < kLutSize; idx += blockDim.x) {
         const uint32_t mv = lattice_move((uint32_t)idx);
-        if constexpr (WIDE) {
-            const int dq = (int)(int8_t)(mv & 0xFFu);
-            const int axis = dq < 0 ? -dq : dq;
-            const int sg = dq < 0 ? -1 : 1;
-            lut[idx] = axis == 1 ? (uint32_t)sg : (axis == 2 ? (uint32_t)(sg * 65536) : 0u);
-            lutb[idx] = (uint32_t)((axis == 3 ? sg * 65536 : 0) + dq);
-        } else {
+        if (wide)
+            wide_move(mv, lut[idx], lutb[idx]);
+        else
             lut[idx] = mv;
-        }
     }
-    for (int w = threadIdx.x; w < cpb * S; w += blockDim.x) chains[w] = 0u;
-    __syncthreads();
+}
 
+// Grows the chain c of this thread's group of G lanes, its history in the S
+// words at `base`, and writes its outputs.  With `boxed` (byte words only) a
+// chain whose tip reaches the edge of the byte range stops, writes nothing
+// and contributes nothing to the side channels; the function then returns
+// true on the group's lanes.
+template <int G, bool WIDE, typename CT, bool TABLE = true>
+__device__ __forceinline__ bool lattice_lds_grow(const GrowArgs &a, const uint32_t *lut, const uint32_t *lutb,
+                                                 uint32_t *base, int H, int S, uint64_t c, bool valid, bool boxed)
+{
+    constexpr int WPM = WIDE ? 2 : 1; // words per monomer
     const int t = threadIdx.x & (G - 1);
-    const int chb = threadIdx.x / G;
-    const uint64_t c = bid * cpb + chb;
-    const bool valid = c < a.n_chains;
     const uint64_t g = a.chain_offset + c;
     const int N = a.n_monomers;
-    uint32_t *base = chains + chb * S;
 
     uint32_t ta = 0, tb = 0; // tip: A word (or the byte word) and B word (wide only)
     bool alive = false;
+    bool left_box = false;
     int grown = 1;
     uint64_t cnt = 0; // 16-bit fields: steps with m = 2, 3, 4, 5 (step 1 has m = 6)
     bool rng_fail = false;
@@ -126,6 +141,7 @@ __device__ __forceinline__ void grow_lattice_lds_body(const GrowArgs &a, uint64_
     int32_t res_ex = 0, res_ey = 0, res_ez = 0;
     int res_grown = 1;
     bool res_alive = false;
+    bool res_set = false;
     bool pending = valid;
 
     for (uint32_t rd = 0; rd < a.max_rounds; ++rd) {
@@ -186,15 +202,38 @@ __device__ __forceinline__ void grow_lattice_lds_body(const GrowArgs &a, uint64_
                 }
             }
 
-            const bool step_ok = alive && m != 0;
+            bool step_ok = alive && m != 0;
             const uint32_t li = (freem << 3) | (r & 7u);
             uint32_t na, nb = 0u;
             if constexpr (WIDE) {
-                na = ta + lut[li];
-                nb = ((tb + lutb[li]) & 0xFFFF001Fu) | 0x40u;
+                uint32_t da, db;
+                if constexpr (TABLE) {
+                    da = lut[li];
+                    db = lutb[li];
+                } else {
+                    wide_move(lattice_move(li), da, db);
+                }
+                na = ta + da;
+                nb = ((tb + db) & 0xFFFF001Fu) | 0x40u;
             } else {
                 const uint32_t mv = lut[li];
                 na = ((ta & 0xFFFFFF00u) + (mv & 0xFFFFFF00u)) | ((ta + mv) & 0xFFu);
+                // |coordinate| >= E = a.byte_box (possible from step E on):
+                // the chain leaves the box here.  Coordinate bytes b = x + 128
+                // with b < 129 - E or 255 - b < 128 - E, as two byte-wise
+                // "has a byte below n" tests (exact for n <= 128) on the
+                // three bytes and on their complements.
+                if (boxed && i >= a.byte_box) {
+                    const uint32_t v = na >> 8, w = v ^ 0xFFFFFFu;
+                    const uint32_t lo = (uint32_t)(129 - a.byte_box) * 0x010101u;
+                    const uint32_t hi = (uint32_t)(128 - a.byte_box) * 0x010101u;
+                    const uint32_t edge = (((v - lo) & ~v) | ((w - hi) & ~w)) & 0x808080u;
+                    if (step_ok && edge != 0u) {
+                        step_ok = false;
+                        alive = false;
+                        left_box = true;
+                    }
+                }
             }
             if (alive && m == 0) {
                 alive = false;
@@ -267,7 +306,9 @@ __device__ __forceinline__ void grow_lattice_lds_body(const GrowArgs &a, uint64_
             ey = (int32_t)((ta >> 16) & 0xFFu) - 128;
             ez = (int32_t)(ta >> 24) - 128;
         }
-        if (pending && (alive || rd + 1 >= a.max_rounds)) {
+        if (pending && left_box) {
+            pending = false; // grown again in wide words
+        } else if (pending && (alive || rd + 1 >= a.max_rounds)) {
             res_lw = alive ? lw : -__builtin_huge_val();
             res_nn = nn;
             res_ex = ex;
@@ -275,12 +316,13 @@ __device__ __forceinline__ void grow_lattice_lds_body(const GrowArgs &a, uint64_
             res_ez = ez;
             res_grown = grown;
             res_alive = alive;
+            res_set = true;
             pending = false;
         }
         if (__ballot(pending) == 0) break;
     }
 
-    if (valid && t == 0) {
+    if (res_set && t == 0) {
         if (a.log_w) a.log_w[c] = res_lw;
         if (a.r_end) {
             CT *re = (CT *)a.r_end;
@@ -293,10 +335,93 @@ __device__ __forceinline__ void grow_lattice_lds_body(const GrowArgs &a, uint64_
         if (a.rg2) a.rg2[c] = (double)res_nn / ((double)res_grown * (double)res_grown);
         if (a.n_grown) a.n_grown[c] = (uint16_t)res_grown;
     }
-    if (rng_fail) atomicExch(a.status, 6);
+    if (rng_fail && !left_box) atomicExch(a.status, 6);
     const uint64_t bits = (res_alive && t == 0) ? (uint64_t)__double_as_longlong(res_lw) : 0ull;
     const uint64_t wmax = wave_max_u64(bits);
     if ((threadIdx.x & 63) == 0 && wmax != 0) atomicMax(a.log_w_max_bits, (unsigned long long)wmax);
+    return left_box;
+}
+
+// Lanes per chain, plane length and chain stride (words) of the wide
+// regrowth; the same formulas as the launch shapes.
+__host__ __device__ __forceinline__ int regrow_lanes(int N) { return N <= 512 ? 8 : 32; }
+__host__ __device__ __forceinline__ int regrow_plane(int N)
+{
+    const int half = (N + 1) / 2, q = 4 * regrow_lanes(N);
+    return (half + q - 1) / q * q;
+}
+__host__ __device__ __forceinline__ int regrow_stride(int N)
+{
+    const int q = 4 * regrow_lanes(N);
+    return 4 * regrow_plane(N) + (q < 64 ? q : 0);
+}
+
+// Passes of the regrowth: `slots` chains at a time from the list at
+// lds_u[1..n]; moves computed per step (no tables: the regrowth is rare).
+template <int GW, typename CT>
+__device__ void regrow_passes(const GrowArgs &a, uint64_t first_chain, int n, int slots, uint32_t *planes)
+{
+    extern __shared__ uint32_t lds_u[];
+    const int N = a.n_monomers;
+    const int HW = regrow_plane(N), SW = regrow_stride(N);
+    const int gw = threadIdx.x / GW;
+    for (int b0 = 0; b0 < n; b0 += slots) {
+        __syncthreads();
+        for (int w = threadIdx.x; w < slots * SW; w += blockDim.x) planes[w] = 0u;
+        __syncthreads();
+        const bool v = gw < slots && b0 + gw < n;
+        const uint64_t c = first_chain + (v ? lds_u[1 + b0 + gw] : 0u);
+        if (__ballot(v) != 0) // waves without such a chain skip the growth
+            lattice_lds_grow<GW, true, CT, false>(a, nullptr, nullptr, planes + (v ? gw : 0) * SW, HW, SW, c, v,
+                                                  false);
+    }
+}
+
+// Chains of the block that left the byte box (`mine` on the leader lane of
+// each), grown again in wide words in the block's own LDS of `words` words,
+// as many at a time as fit.  Every thread of the block calls this.
+template <typename CT>
+__device__ void regrow_wide(const GrowArgs &a, uint64_t first_chain, bool mine, uint32_t chb, int words)
+{
+    extern __shared__ uint32_t lds_u[];
+    __syncthreads(); // every chain of the block is done with its planes
+    if (threadIdx.x == 0) lds_u[0] = 0u;
+    const int n = __syncthreads_count(mine);
+    if (n == 0) return;
+    if (mine) lds_u[1 + atomicAdd(&lds_u[0], 1u)] = chb;
+    const int N = a.n_monomers;
+    uint32_t *planes = lds_u + kRegrowListWords;
+    const int room = (words - kRegrowListWords) / regrow_stride(N);
+    const int per_block = (int)blockDim.x / regrow_lanes(N);
+    const int slots = room < per_block ? room : per_block; // >= 1: checked by the launch shape
+    if (regrow_lanes(N) == 8)
+        regrow_passes<8, CT>(a, first_chain, n, slots, planes);
+    else
+        regrow_passes<32, CT>(a, first_chain, n, slots, planes);
+}
+
+template <int G, bool WIDE, typename CT>
+__device__ __forceinline__ void grow_lattice_lds_body(const GrowArgs &a, uint64_t bid, int H, int S)
+{
+    constexpr int WPM = WIDE ? 2 : 1; // words per monomer
+    const int cpb = blockDim.x / G;   // chains per block
+    extern __shared__ uint32_t lds_u[];
+    uint32_t *lut = lds_u;                     // byte-format move, or the A move
+    uint32_t *lutb = lds_u + kLutSize;         // B move (wide only)
+    uint32_t *chains = lds_u + WPM * kLutSize; // cpb chains of S words
+    lattice_lds_luts(lut, lutb, WIDE);
+    for (int w = threadIdx.x; w < cpb * S; w += blockDim.x) chains[w] = 0u;
+    __syncthreads();
+
+    const int t = threadIdx.x & (G - 1);
+    const int chb = threadIdx.x / G;
+    const uint64_t c = bid * cpb + chb;
+    const bool boxed = !WIDE && a.n_monomers > kByteExactN;
+    const bool left =
+        lattice_lds_grow<G, WIDE, CT>(a, lut, lutb, chains + chb * S, H, S, c, c < a.n_chains, boxed);
+    if constexpr (!WIDE) {
+        if (boxed) regrow_wide<CT>(a, bid * cpb, left && t == 0, (uint32_t)chb, WPM * kLutSize + cpb * S);
+    }
 }
 
 template <int G, bool WIDE, typename CT>
@@ -318,39 +443,53 @@ __global__ __launch_bounds__(256) void grow_lattice_lds_batch(const GrowEntry *t
 // Largest lattice chain of the LDS kernel (wide words: 128 KiB per chain).
 int lattice_lds_max_monomers() { return 16384; }
 
-// Shape of the LDS kernel for N monomers, G lanes per chain (4: byte words,
-// N <= 128; 8..64: wide words) and `threads` per block (64 or 256).
-// hipErrorInvalidValue when the combination is not legal or the block's
-// LDS exceeds the CU's 160 KiB.
-static hipError_t lds_shape(int N, bool i16, int G, int threads, GrowVariant *v)
+// Shape of the LDS kernel for N monomers, G lanes per chain and `threads`
+// per block (64 or 256) in one word format.  hipErrorInvalidValue when the
+// block's LDS exceeds the CU's 160 KiB or, for boxed byte words, holds no
+// chain of the wide regrowth.
+static hipError_t lds_shape_fmt(int N, bool i16, int G, int threads, bool wide, GrowVariant *v)
 {
-    if (G != 4 && G != 8 && G != 16 && G != 32 && G != 64) return hipErrorInvalidValue;
-    if (threads != 64 && threads != 256) return hipErrorInvalidValue;
-    const int wide = G == 4 ? 0 : 1;
-    if (!wide && N > 128) return hipErrorInvalidValue;
     const int WPM = wide ? 2 : 1;
     const int half = (N + 1) / 2;
     const int H = (half + 4 * G - 1) / (4 * G) * (4 * G);
     // chain stride: pad so that the chains of a wave start on different banks
     const int S = 2 * WPM * H + (4 * G < 64 ? 4 * G : 0);
-    const size_t bytes = ((size_t)WPM * kLutSize + (size_t)(threads / G) * S) * sizeof(uint32_t);
-    if (bytes > 163840) return hipErrorInvalidValue;
+    const int cpb = threads / G;
+    const int words = WPM * kLutSize + cpb * S;
+    if ((size_t)words * sizeof(uint32_t) > 163840) return hipErrorInvalidValue;
+    if (!wide && N > kByteExactN && words - kRegrowListWords < regrow_stride(N)) return hipErrorInvalidValue;
     v->family = 1;
     v->p0 = G;
-    v->p1 = wide;
+    v->p1 = wide ? 1 : 0;
     v->p2 = i16 ? 1 : 0;
     v->threads = threads;
-    v->cpb = threads / G;
-    v->shmem = bytes;
+    v->cpb = cpb;
+    v->shmem = (size_t)words * sizeof(uint32_t);
     v->H = H;
     v->S = S;
     return hipSuccess;
 }
 
-// Variant for 64 < N <= 16384.  Built-in rule: G grows with N so that one
-// wave's chains take at most ~17 KiB of LDS (8 waves per CU) up to N = 2048;
-// four waves per block share the move table when the block fits in half a
-// CU's LDS.  A legal mapping of the tuning table replaces the rule.
+// Shape for a mapping: byte words up to N = 2048 (boxed beyond N = 128)
+// where the block can host the regrowth, else wide words (G >= 8).  Byte
+// words need less LDS than wide ones, and their regrowth room does not grow
+// back as N shrinks, so a mapping legal at some N is legal at every smaller
+// N of the kernel.
+static hipError_t lds_shape(int N, bool i16, int G, int threads, GrowVariant *v)
+{
+    if (G != 4 && G != 8 && G != 16 && G != 32 && G != 64) return hipErrorInvalidValue;
+    if (threads != 64 && threads != 256) return hipErrorInvalidValue;
+    if (N <= kByteBoxedMaxN && lds_shape_fmt(N, i16, G, threads, false, v) == hipSuccess) return hipSuccess;
+    if (G == 4) return hipErrorInvalidValue;
+    return lds_shape_fmt(N, i16, G, threads, true, v);
+}
+
+// Variant for 64 < N <= 16384.  Built-in rule (measured on MI355X, 10^5 to
+// 10^6 chains): byte words with 4 lanes per chain up to N = 256, 8 up to
+// N = 512, 16 up to 1024 and 32 up to 2048; wide words beyond, 32 lanes in
+// 256-thread blocks while eight chains fit in a CU's LDS, else 64 lanes.
+// Four or more waves per block share the move table when the block fits in
+// half a CU's LDS.  A legal mapping of the tuning table replaces the rule.
 hipError_t lattice_lds_variant(const GrowArgs &a, bool i16, GrowVariant *v)
 {
     const int N = a.n_monomers;
@@ -358,7 +497,11 @@ hipError_t lattice_lds_variant(const GrowArgs &a, bool i16, GrowVariant *v)
     if (tuned_mapping(0 /* simple cubic lattice */, N, a.k_trials, &tl, &tt) &&
         lds_shape(N, i16, tl, tt, v) == hipSuccess)
         return hipSuccess;
-    const int G = N <= 128 ? 4 : (N <= 256 ? 8 : (N <= 512 ? 16 : (N <= 1024 ? 32 : 64)));
+    const int G = N <= 256 ? 4 : (N <= 512 ? 8 : (N <= 1024 ? 16 : (N <= 2048 ? 32 : 64)));
+    // wide words just past N = 2048: eight chains of 32 lanes in one
+    // 256-thread block per CU while they fit (N = 2200: 37.8 against 49.2 ms
+    // for one-chain blocks of 64 lanes, 5 * 10^4 chains)
+    if (N > kByteBoxedMaxN && lds_shape(N, i16, 32, 256, v) == hipSuccess) return hipSuccess;
     GrowVariant half_cu;
     if (lds_shape(N, i16, G, 256, &half_cu) == hipSuccess && half_cu.shmem <= 81920) {
         *v = half_cu;
@@ -396,10 +539,18 @@ static hipError_t dispatch_lds(const GrowArgs &a, const GrowVariant &v, const Gr
                : launch_lds<G, W, int32_t>(a, v, tab, block0, n, blocks, shmem, s)
     switch (v.p0) {
     case 4: RSAW_LDS(4, false);
-    case 8: RSAW_LDS(8, true);
-    case 16: RSAW_LDS(16, true);
-    case 32: RSAW_LDS(32, true);
-    default: RSAW_LDS(64, true);
+    case 8:
+        if (!v.p1) RSAW_LDS(8, false);
+        RSAW_LDS(8, true);
+    case 16:
+        if (!v.p1) RSAW_LDS(16, false);
+        RSAW_LDS(16, true);
+    case 32:
+        if (!v.p1) RSAW_LDS(32, false);
+        RSAW_LDS(32, true);
+    default:
+        if (!v.p1) RSAW_LDS(64, false);
+        RSAW_LDS(64, true);
     }
 #undef RSAW_LDS
 }

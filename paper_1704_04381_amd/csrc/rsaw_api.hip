@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <algorithm>
+#include <atomic>
 #include <tuple>
 #include <cstring>
 #include <map>
@@ -344,6 +345,10 @@ rsaw_chain_out bind_outputs(const rsaw_chain_out &in, const EnsLayout &L, char *
     return o;
 }
 
+// |coordinate| at which the boxed byte-word lattice kernels regrow a chain
+// in wide words (rsaw_set_byte_box).
+std::atomic<int32_t> g_byte_box{127};
+
 rsaw::GrowArgs grow_args(const rsaw_config *cfg, const rsaw_chain_out &o, const EnsLayout &L, char *ws)
 {
     rsaw::GrowArgs a;
@@ -358,6 +363,7 @@ rsaw::GrowArgs grow_args(const rsaw_config *cfg, const rsaw_chain_out &o, const 
     const double bs = cfg->bond_length + cfg->bead_diameter;
     a.cull2 = bs * bs * (1.0 + 0x1p-30);
     a.max_rounds = (cfg->flags & RSAW_RESTART) ? 65536u : 1u;
+    a.byte_box = g_byte_box.load(std::memory_order_relaxed);
     a.bead_slots = L.n_slots ? (double *)(ws + L.off_slots) : nullptr;
     a.n_slots = L.n_slots;
     a.log_w = o.log_w;
@@ -1144,6 +1150,13 @@ rsaw_status rsaw_mapping_set(const rsaw_mapping *m)
     e.lds_bytes = 0;
     std::lock_guard<std::mutex> lk(g_map_lock);
     g_map.push_back(e);
+    return RSAW_OK;
+}
+
+rsaw_status rsaw_set_byte_box(int32_t edge)
+{
+    if (edge < 1 || edge > 127) return fail(RSAW_E_INVALID, "byte box edge must be in 1..127");
+    g_byte_box.store(edge, std::memory_order_relaxed);
     return RSAW_OK;
 }
 

@@ -30,7 +30,8 @@ def test_builtin_rule():
     assert _q("lattice", 64, 6)["lanes"] == 1
     assert _q("lattice26", 64, 26)["lanes"] == 1
     # group widths of the built-in rule
-    assert [_q("lattice", n, 6)["lanes"] for n in (65, 128, 129, 300, 600, 1024, 2048)] == [4, 4, 8, 16, 32, 32, 64]
+    assert [_q("lattice", n, 6)["lanes"] for n in (65, 128, 129, 256, 257, 512, 513, 1024, 2048, 2049, 3000)] == \
+        [4, 4, 4, 4, 8, 8, 16, 16, 32, 32, 64]
     assert [_q("lattice26", n, 26)["lanes"] for n in (65, 160, 161, 400, 800, 1600)] == [4, 4, 8, 16, 32, 64]
     assert _q("real", 64, 8)["lanes"] == 8 and _q("real", 64, 16)["lanes"] == 16
     assert _q("real", 300, 8)["lanes"] == 32  # 0.075 N = 22.5 -> 32
@@ -59,7 +60,7 @@ def test_set_overrides_inside_its_range_only():
     rs.mapping_set("lattice", 6, 65, 128, 32, 64)
     m = _q("lattice", 100, 6)
     assert (m["lanes"], m["threads"]) == (32, 64)
-    assert _q("lattice", 129, 6)["lanes"] == 8       # outside the range
+    assert _q("lattice", 129, 6)["lanes"] == 4       # outside the range
     assert _q("lattice", 64, 6)["lanes"] == 1        # register kernel: never tuned
     assert _q("lattice26", 100, 26)["lanes"] == 4    # other geometry
     # a later entry wins where ranges overlap
@@ -77,7 +78,7 @@ def test_hard_sphere_mapping_is_per_k():
 
 
 @pytest.mark.parametrize("args", [
-    ("lattice", 6, 65, 200, 4, 64),      # byte words need N <= 128
+    ("lattice", 6, 65, 2100, 4, 64),     # 4 lanes: byte words, N <= 2048
     ("lattice", 6, 65, 100, 2, 64),      # not a group width
     ("lattice", 6, 65, 100, 8, 128),     # threads must be 64 or 256
     ("lattice", 6, 10, 64, 8, 64),       # N <= 64: register kernel
@@ -128,3 +129,13 @@ def test_list_save_and_load_round_trip(tmp_path):
     assert rs.load_mappings(path) == 3
     assert rs.mapping_list() == rows
     assert [_q(*p) for p in probes] == before
+
+
+def test_byte_box_edge_range():
+    # rsaw_set_byte_box: host-only; 1..127, anything else rejected
+    for bad in (0, -1, 128, 1 << 20):
+        with pytest.raises(rs.RsawError) as e:
+            rs.set_byte_box(bad)
+        assert e.value.status == 1  # RSAW_E_INVALID
+    rs.set_byte_box(1)
+    rs.set_byte_box(127)
