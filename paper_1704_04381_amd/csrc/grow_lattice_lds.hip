@@ -174,15 +174,31 @@ __device__ __forceinline__ bool lattice_lds_grow(const GrowArgs &a, const uint32
             const uint32_t tbh = tb & 0xFFFF0000u;
             const uint32_t tq = (WIDE ? tb : ta) - 3u;
             uint32_t occ = 0, occ2 = 0;
-            for (int q = 0; q < passes; ++q) {
-                const int k = q * 4 * G + 4 * t;
-                const uint4 wa = *(const uint4 *)(pa + k);
-                uint4 wb = make_uint4(0u, 0u, 0u, 0u);
-                if constexpr (WIDE) wb = *(const uint4 *)(pb + k);
+            const auto test4 = [&](const uint4 &wa, const uint4 &wb) {
                 occ |= pair_bits<WIDE>(wa.x, wb.x, tref, tbh, tq);
                 occ2 |= pair_bits<WIDE>(wa.y, wb.y, tref, tbh, tq);
                 occ |= pair_bits<WIDE>(wa.z, wb.z, tref, tbh, tq);
                 occ2 |= pair_bits<WIDE>(wa.w, wb.w, tref, tbh, tq);
+            };
+            // two passes per iteration, so that the second pass's reads are
+            // in flight while the first is tested
+            int q = 0;
+            for (; q + 1 < passes; q += 2) {
+                const int k1 = q * 4 * G + 4 * t, k2 = k1 + 4 * G;
+                const uint4 a1 = *(const uint4 *)(pa + k1), a2 = *(const uint4 *)(pa + k2);
+                uint4 b1 = make_uint4(0u, 0u, 0u, 0u), b2 = b1;
+                if constexpr (WIDE) {
+                    b1 = *(const uint4 *)(pb + k1);
+                    b2 = *(const uint4 *)(pb + k2);
+                }
+                test4(a1, b1);
+                test4(a2, b2);
+            }
+            if (q < passes) {
+                const int k1 = q * 4 * G + 4 * t;
+                uint4 b1 = make_uint4(0u, 0u, 0u, 0u);
+                if constexpr (WIDE) b1 = *(const uint4 *)(pb + k1);
+                test4(*(const uint4 *)(pa + k1), b1);
             }
             occ |= occ2;
             occ = group_or<G>(occ);
