@@ -128,30 +128,67 @@ __device__ __forceinline__ void z26_fill_select_table(uint8_t *sel)
     }
 }
 
-template <int G, bool EXACT, typename CT>
-__device__ __forceinline__ void grow_lattice26_body(const GrowArgs &a, uint64_t bid, int H)
-{
-    const int cpb = blockDim.x / G;
-    extern __shared__ uint32_t z26_lds[];
-    uint32_t *chains = z26_lds; // cpb chains of 2 H words
-    __shared__ double logm[27];
-    for (int q = threadIdx.x; q < 27; q += blockDim.x) logm[q] = a.logm[q];
-    for (int w = threadIdx.x; w < cpb * 2 * H; w += blockDim.x) chains[w] = (w / H) & 1 ? kZ26OriginB : 0u;
-    __syncthreads();
+// Byte words of the group kernel (N <= 640): one word per monomer, bytes
+// (x + 64, y + 64, z + 64) plus 128 each, the pair test of the one-lane
+// kernel (z26_bits8, nine operations) against the tip's raw word.  The test
+// needs every tip coordinate within [-62, 63] (at least 2 from the sentinel
+// at -64) and every stored one within [-64, 63]; a chain whose new tip
+// reaches |coordinate| = E (62, or the launch's byte_box if smaller) stops,
+// writes nothing and is grown again, from its first draw, in wide words by
+// the same block once its other chains are done (the same draws and tests
+// give the same chain, Sec. 3.3.2).
+constexpr int kZ26ByteMaxN = 640;
+constexpr int kZ26ByteEdge = 62;
+constexpr int kZ26RegrowLanes = 8;
+constexpr int kZ26ListWords = 65; // count + one slot per chain of a block (<= 64)
+constexpr uint32_t kZ26Bias = 0x00808080u;
+constexpr uint32_t kZ26LaneOrigin = 0x00404040u; // raw (64, 64, 64): the origin
 
+__device__ __forceinline__ uint32_t z26_bits8(uint32_t w, uint32_t t, uint32_t tb)
+{
+    const uint32_t e = (w - t) ^ kZ26Bias;
+    const uint32_t q = (uint32_t)__builtin_amdgcn_sdot4((int)e, (int)e, 0, false);
+    const uint32_t s1 = __builtin_amdgcn_sad_u8(w, tb, 1u);
+    const int code = __builtin_amdgcn_sdot4((int)e, 0x00090301, 13, false);
+    return __builtin_elementwise_sub_sat(s1, q) << ((uint32_t)code & 31u);
+}
+
+// Bytes (dx + 1, dy + 1, dz + 1) of code c = (dx + 1) + 3 (dy + 1) + 9 (dz + 1).
+__device__ __forceinline__ uint32_t z26_move_bytes(uint32_t code)
+{
+    const uint32_t z = (code * 57u) >> 9; // code / 9
+    const uint32_t rem = code - 9u * z;
+    const uint32_t y = (rem * 11u) >> 5; // rem / 3
+    return (rem - 3u * y) | (y << 8) | (z << 16);
+}
+
+// Plane length of the wide regrowth (kZ26RegrowLanes lanes per chain).
+__host__ __device__ __forceinline__ int z26_regrow_plane(int N)
+{
+    constexpr int q = 4 * kZ26RegrowLanes;
+    return (N + q - 1) / q * q;
+}
+
+// Grows chain c of this thread's group of G lanes, its history at PA (wide
+// words: planes PA and PA + H; byte words: one plane of H words), and writes
+// its outputs.  With box > 0 (byte words) a chain whose tip reaches
+// |coordinate| = box stops, writes nothing and contributes nothing to the
+// side channels; the function then returns true on the group's lanes.
+template <int G, bool EXACT, typename CT, bool BYTE>
+__device__ __forceinline__ bool z26_grow(const GrowArgs &a, const double *logm, uint32_t *PA, int H, uint64_t c,
+                                         bool valid, int box)
+{
     const int t = threadIdx.x & (G - 1);
-    const int chb = threadIdx.x / G;
     const int lane = threadIdx.x & 63;
     const int gbase = lane & ~(G - 1);
-    const uint64_t c = bid * cpb + chb;
-    const bool valid = c < a.n_chains;
     const uint64_t g = a.chain_offset + c;
     const int N = a.n_monomers;
-    uint32_t *PA = chains + chb * 2 * H;
     uint32_t *PB = PA + H;
 
+    // tip: A and B words (wide), or the raw byte word in ta (byte)
     uint32_t ta = 0, tb = 0;
     bool alive = false;
+    bool left_box = false;
     int grown = 1;
     // steps with m free candidates: lane t counts the m with (m - 1) mod G
     // = t, in FW-bit fields at (m - 1) / G (one field for G >= 32; 8-bit
@@ -167,21 +204,31 @@ __device__ __forceinline__ void grow_lattice26_body(const GrowArgs &a, uint64_t 
     int32_t res_ex = 0, res_ey = 0, res_ez = 0;
     int res_grown = 1;
     bool res_alive = false;
+    bool res_set = false;
     bool pending = valid;
 
     for (uint32_t rd = 0; rd < a.max_rounds; ++rd) {
         if (pending) {
-            if (rd > 0)
-                for (int w = t; w < 2 * H; w += G) PA[w] = w < H ? 0u : kZ26OriginB;
-            ta = kZ26OriginA;
-            tb = kZ26OriginB;
+            if (rd > 0) {
+                if constexpr (BYTE) {
+                    for (int w = t; w < H; w += G) PA[w] = kZ26Bias;
+                } else {
+                    for (int w = t; w < 2 * H; w += G) PA[w] = w < H ? 0u : kZ26OriginB;
+                }
+            }
+            ta = BYTE ? kZ26LaneOrigin : kZ26OriginA;
+            tb = BYTE ? 0u : kZ26OriginB;
             n_mine = 0;
             wx = 1;
         }
         z26_wave_sync();
         if (pending && t == 0) {
-            PA[0] = ta;
-            PB[0] = tb;
+            if constexpr (BYTE) {
+                PA[0] = ta + kZ26Bias;
+            } else {
+                PA[0] = ta;
+                PB[0] = tb;
+            }
         }
         z26_wave_sync();
         alive = pending;
@@ -193,26 +240,40 @@ __device__ __forceinline__ void grow_lattice26_body(const GrowArgs &a, uint64_t 
             const int nrel = i - 1;
             const int passes = (nrel + 4 * G - 1) / (4 * G);
             uint32_t occ = 0, occ2 = 0;
+            const uint32_t tbias = ta + kZ26Bias;
             // two passes per iteration, so that the second pass's reads are in
             // flight while the first is tested; entries at nrel and beyond hold
             // the sentinel (never a candidate) or the tip (code 13, masked)
             auto test4 = [&](const uint4 &wa, const uint4 &wb) {
-                occ |= z26_bits(wa.x, wb.x, ta, tb);
-                occ2 |= z26_bits(wa.y, wb.y, ta, tb);
-                occ |= z26_bits(wa.z, wb.z, ta, tb);
-                occ2 |= z26_bits(wa.w, wb.w, ta, tb);
+                if constexpr (BYTE) {
+                    occ |= z26_bits8(wa.x, ta, tbias);
+                    occ2 |= z26_bits8(wa.y, ta, tbias);
+                    occ |= z26_bits8(wa.z, ta, tbias);
+                    occ2 |= z26_bits8(wa.w, ta, tbias);
+                } else {
+                    occ |= z26_bits(wa.x, wb.x, ta, tb);
+                    occ2 |= z26_bits(wa.y, wb.y, ta, tb);
+                    occ |= z26_bits(wa.z, wb.z, ta, tb);
+                    occ2 |= z26_bits(wa.w, wb.w, ta, tb);
+                }
             };
             int q = 0;
             for (; q + 1 < passes; q += 2) {
                 const int k1 = q * 4 * G + 4 * t, k2 = k1 + 4 * G;
-                const uint4 a1 = *(const uint4 *)(PA + k1), b1 = *(const uint4 *)(PB + k1);
-                const uint4 a2 = *(const uint4 *)(PA + k2), b2 = *(const uint4 *)(PB + k2);
+                const uint4 a1 = *(const uint4 *)(PA + k1), a2 = *(const uint4 *)(PA + k2);
+                uint4 b1 = make_uint4(0u, 0u, 0u, 0u), b2 = b1;
+                if constexpr (!BYTE) {
+                    b1 = *(const uint4 *)(PB + k1);
+                    b2 = *(const uint4 *)(PB + k2);
+                }
                 test4(a1, b1);
                 test4(a2, b2);
             }
             if (q < passes) {
                 const int k1 = q * 4 * G + 4 * t;
-                test4(*(const uint4 *)(PA + k1), *(const uint4 *)(PB + k1));
+                uint4 b1 = make_uint4(0u, 0u, 0u, 0u);
+                if constexpr (!BYTE) b1 = *(const uint4 *)(PB + k1);
+                test4(*(const uint4 *)(PA + k1), b1);
             }
             occ = z26_group_or<G>(occ | occ2);
             const uint32_t freem = ~occ & kZ26Codes;
@@ -231,22 +292,50 @@ __device__ __forceinline__ void grow_lattice26_body(const GrowArgs &a, uint64_t 
             }
             const uint32_t code = m ? z26_select_bits(freem, r) : 13u; // the r-th free code
 
-            const bool step_ok = alive && m != 0;
+            bool step_ok = alive && m != 0;
             if (alive && m == 0) {
                 alive = false;
                 grown = i;
             }
-            if (step_ok) {
+            uint32_t na = ta, nb = tb;
+            if constexpr (BYTE) {
+                // bytes dx + 1, dy + 1, dz + 1 added, then 1 taken from each:
+                // no carry or borrow for a tip inside the box
+                na = ta + z26_move_bytes(code) - 0x010101u;
+            } else {
                 uint32_t da, db;
                 z26_move(code, da, db);
-                ta = ta + da;
-                tb = tb + db;
+                na = ta + da;
+                nb = tb + db;
+            }
+            if constexpr (BYTE) {
+                // |coordinate| >= E: bytes b = x + 64 with b < 65 - E or
+                // 127 - b < 64 - E (byte-wise "has a byte below n", exact
+                // for n <= 128), possible from step E on
+                if (box > 0 && i >= box) {
+                    const uint32_t v = na, w = 0x7F7F7Fu - na;
+                    const uint32_t lo = (uint32_t)(65 - box) * 0x010101u, hb = (uint32_t)(64 - box) * 0x010101u;
+                    const uint32_t edge = (((v - lo) & ~v) | ((w - hb) & ~w)) & 0x808080u;
+                    if (step_ok && edge != 0u) {
+                        step_ok = false;
+                        alive = false;
+                        left_box = true;
+                    }
+                }
+            }
+            if (step_ok) {
+                ta = na;
+                tb = nb;
                 const uint32_t mm1 = m - 1u;
                 n_mine += (mm1 & (G - 1)) == (uint32_t)t ? 1ull << (FW * (mm1 / G)) : 0ull;
                 if (EXACT) wx = wx * (uint64_t)m;
                 if (t == 0) {
-                    PA[i] = ta;
-                    PB[i] = tb;
+                    if constexpr (BYTE) {
+                        PA[i] = ta + kZ26Bias;
+                    } else {
+                        PA[i] = ta;
+                        PB[i] = tb;
+                    }
                 }
             }
             z26_wave_sync();
@@ -269,9 +358,17 @@ __device__ __forceinline__ void grow_lattice26_body(const GrowArgs &a, uint64_t 
         int32_t sx = 0, sy = 0, sz = 0;
         int64_t s2 = 0;
         for (int j = t; j < grown; j += G) {
-            const int32_t xx = (int32_t)(PA[j] & 0xFFFFu) - 32768;
-            const int32_t yy = (int32_t)(PA[j] >> 16) - 32768;
-            const int32_t zz = (int32_t)(PB[j] & 0xFFFFu) - 32768;
+            int32_t xx, yy, zz;
+            if constexpr (BYTE) {
+                const uint32_t w = PA[j];
+                xx = (int32_t)(w & 0xFFu) - 192;
+                yy = (int32_t)((w >> 8) & 0xFFu) - 192;
+                zz = (int32_t)((w >> 16) & 0xFFu) - 192;
+            } else {
+                xx = (int32_t)(PA[j] & 0xFFFFu) - 32768;
+                yy = (int32_t)(PA[j] >> 16) - 32768;
+                zz = (int32_t)(PB[j] & 0xFFFFu) - 32768;
+            }
             sx += xx;
             sy += yy;
             sz += zz;
@@ -286,22 +383,31 @@ __device__ __forceinline__ void grow_lattice26_body(const GrowArgs &a, uint64_t 
             const int hh = __shfl_xor((int)(uint32_t)((uint64_t)s2 >> 32), off, 64);
             s2 += (int64_t)(((uint64_t)(uint32_t)hh << 32) | (uint32_t)lo);
         }
-        if (pending && (alive || rd + 1 >= a.max_rounds)) {
+        if (pending && left_box) {
+            pending = false; // grown again in wide words
+        } else if (pending && (alive || rd + 1 >= a.max_rounds)) {
             const int64_t gg = grown;
             res_nn = gg * s2 - ((int64_t)sx * sx + (int64_t)sy * sy + (int64_t)sz * sz);
-            res_ex = (int32_t)(ta & 0xFFFFu) - 32768;
-            res_ey = (int32_t)(ta >> 16) - 32768;
-            res_ez = (int32_t)(tb & 0xFFFFu) - 32768;
+            if constexpr (BYTE) {
+                res_ex = (int32_t)(ta & 0xFFu) - 64;
+                res_ey = (int32_t)((ta >> 8) & 0xFFu) - 64;
+                res_ez = (int32_t)((ta >> 16) & 0xFFu) - 64;
+            } else {
+                res_ex = (int32_t)(ta & 0xFFFFu) - 32768;
+                res_ey = (int32_t)(ta >> 16) - 32768;
+                res_ez = (int32_t)(tb & 0xFFFFu) - 32768;
+            }
             res_lw = alive ? lw : -__builtin_huge_val();
             res_wx = alive ? wx : 0ull;
             res_grown = grown;
             res_alive = alive;
+            res_set = true;
             pending = false;
         }
         if (__ballot(pending) == 0) break;
     }
 
-    if (valid && t == 0) {
+    if (res_set && t == 0) {
         if (a.log_w) a.log_w[c] = res_lw;
         if (EXACT && a.w_exact) a.w_exact[c] = res_wx;
         if (a.r_end) {
@@ -315,25 +421,81 @@ __device__ __forceinline__ void grow_lattice26_body(const GrowArgs &a, uint64_t 
         if (a.rg2) a.rg2[c] = (double)res_nn / ((double)res_grown * (double)res_grown);
         if (a.n_grown) a.n_grown[c] = (uint16_t)res_grown;
     }
-    if (rng_fail) atomicExch(a.status, 6);
+    if (rng_fail && !left_box) atomicExch(a.status, 6);
     const uint64_t bits = (res_alive && t == 0) ? (uint64_t)__double_as_longlong(res_lw) : 0ull;
     const uint64_t wmax = wave_max_u64(bits);
     if ((threadIdx.x & 63) == 0 && wmax != 0) atomicMax(a.log_w_max_bits, (unsigned long long)wmax);
+    return left_box;
 }
 
-template <int G, bool EXACT, typename CT>
+// Chains of the block that left the byte box (`mine` on the leader lane of
+// each), grown again in wide words with kZ26RegrowLanes lanes per chain in
+// the block's own LDS of `words` words, as many at a time as fit.  Every
+// thread of the block calls this.
+template <typename CT>
+__device__ void z26_regrow_wide(const GrowArgs &a, const double *logm, uint64_t first_chain, bool mine,
+                                uint32_t chb, int words)
+{
+    extern __shared__ uint32_t z26_lds[];
+    __syncthreads(); // every chain of the block is done with its plane
+    if (threadIdx.x == 0) z26_lds[0] = 0u;
+    const int n = __syncthreads_count(mine);
+    if (n == 0) return;
+    if (mine) z26_lds[1 + atomicAdd(&z26_lds[0], 1u)] = chb;
+    const int N = a.n_monomers;
+    const int HW = z26_regrow_plane(N);
+    uint32_t *planes = z26_lds + kZ26ListWords;
+    const int room = (words - kZ26ListWords) / (2 * HW);
+    const int per_block = (int)blockDim.x / kZ26RegrowLanes;
+    const int slots = room < per_block ? room : per_block; // >= 1: checked by the launch shape
+    const int gw = threadIdx.x / kZ26RegrowLanes;
+    for (int b0 = 0; b0 < n; b0 += slots) {
+        __syncthreads();
+        for (int w = threadIdx.x; w < slots * 2 * HW; w += blockDim.x)
+            planes[w] = ((w / HW) & 1) ? kZ26OriginB : 0u;
+        __syncthreads();
+        const bool v = gw < slots && b0 + gw < n;
+        const uint64_t c = first_chain + (v ? z26_lds[1 + b0 + gw] : 0u);
+        if (__ballot(v) != 0) // waves without such a chain skip the growth
+            z26_grow<kZ26RegrowLanes, false, CT, false>(a, logm, planes + (v ? gw : 0) * 2 * HW, HW, c, v, 0);
+    }
+}
+
+template <int G, bool EXACT, typename CT, bool BYTE>
+__device__ __forceinline__ void grow_lattice26_body(const GrowArgs &a, uint64_t bid, int H)
+{
+    constexpr int WPM = BYTE ? 1 : 2; // words per monomer
+    const int cpb = blockDim.x / G;
+    extern __shared__ uint32_t z26_lds[];
+    uint32_t *chains = z26_lds; // cpb chains of WPM H words
+    __shared__ double logm[27];
+    for (int q = threadIdx.x; q < 27; q += blockDim.x) logm[q] = a.logm[q];
+    for (int w = threadIdx.x; w < cpb * WPM * H; w += blockDim.x)
+        chains[w] = BYTE ? kZ26Bias : (((w / H) & 1) ? kZ26OriginB : 0u);
+    __syncthreads();
+
+    const int t = threadIdx.x & (G - 1);
+    const int chb = threadIdx.x / G;
+    const uint64_t c = bid * cpb + chb;
+    const int box = BYTE ? (a.byte_box < kZ26ByteEdge ? a.byte_box : kZ26ByteEdge) : 0;
+    const bool left =
+        z26_grow<G, EXACT, CT, BYTE>(a, logm, chains + chb * WPM * H, H, c, c < a.n_chains, box);
+    if constexpr (BYTE) z26_regrow_wide<CT>(a, logm, bid * cpb, left && t == 0, (uint32_t)chb, cpb * H);
+}
+
+template <int G, bool EXACT, typename CT, bool BYTE>
 __global__ __launch_bounds__(256) void grow_lattice26(GrowArgs a, int H, uint64_t base)
 {
-    grow_lattice26_body<G, EXACT, CT>(a, base + blockIdx.x, H);
+    grow_lattice26_body<G, EXACT, CT, BYTE>(a, base + blockIdx.x, H);
 }
 
-template <int G, bool EXACT, typename CT>
+template <int G, bool EXACT, typename CT, bool BYTE>
 __global__ __launch_bounds__(256) void grow_lattice26_batch(const GrowEntry *tab, const uint64_t *block0, int n,
                                                             uint64_t base)
 {
     const uint64_t bid = base + blockIdx.x;
     const int e = find_segment(block0, n, bid);
-    grow_lattice26_body<G, EXACT, CT>(tab[e].a, bid - block0[e], tab[e].H);
+    grow_lattice26_body<G, EXACT, CT, BYTE>(tab[e].a, bid - block0[e], tab[e].H);
 }
 
 // Short chains (N <= 64): one lane per chain.  The lane's history sits in
@@ -353,22 +515,12 @@ __global__ __launch_bounds__(256) void grow_lattice26_batch(const GrowEntry *tab
 // of the k-th set bit of every byte value.
 constexpr int kZ26LaneMax = 64;
 constexpr int kZ26LaneThreads = 256;
-constexpr uint32_t kZ26Bias = 0x00808080u;
-constexpr uint32_t kZ26LaneOrigin = 0x00404040u; // raw (64, 64, 64): the origin
 
 __host__ __device__ constexpr size_t z26_lane_shmem(int N, int T)
 {
     return (size_t)((N + 3) / 4) * T * 16 + (size_t)7 * T * 4 + 32 * 4 + 2048;
 }
 
-__device__ __forceinline__ uint32_t z26_bits8(uint32_t w, uint32_t t, uint32_t tb)
-{
-    const uint32_t e = (w - t) ^ kZ26Bias;
-    const uint32_t q = (uint32_t)__builtin_amdgcn_sdot4((int)e, (int)e, 0, false);
-    const uint32_t s1 = __builtin_amdgcn_sad_u8(w, tb, 1u);
-    const int code = __builtin_amdgcn_sdot4((int)e, 0x00090301, 13, false);
-    return __builtin_elementwise_sub_sat(s1, q) << ((uint32_t)code & 31u);
-}
 
 template <bool EXACT, typename CT>
 __device__ __forceinline__ void grow_lattice26_lane_body(const GrowArgs &a, uint64_t bid)
@@ -545,36 +697,51 @@ __global__ __launch_bounds__(kZ26LaneThreads) void grow_lattice26_lane_batch(con
 
 int lattice26_max_monomers() { return 16384; }
 
-// Shape of the group kernel for N monomers, G lanes per chain (4: 8-bit n_m
-// fields, N <= 256; 8..64: 16-bit fields) and `threads` per block (64 or
-// 256).  hipErrorInvalidValue when the combination is not legal or the
-// block's LDS exceeds the CU's 160 KiB.
-static hipError_t z26_shape(int N, bool i16, int G, int threads, GrowVariant *v)
+// Shape of the group kernel for N monomers, G lanes per chain and `threads`
+// per block in one word format.  hipErrorInvalidValue when the block's LDS
+// exceeds the CU's 160 KiB or, for byte words, holds no chain of the wide
+// regrowth.
+static hipError_t z26_shape_fmt(int N, bool i16, int G, int threads, bool byte, GrowVariant *v)
 {
-    if (G != 4 && G != 8 && G != 16 && G != 32 && G != 64) return hipErrorInvalidValue;
-    if (threads != 64 && threads != 256) return hipErrorInvalidValue;
-    if (G == 4 && N > 256) return hipErrorInvalidValue;
+    const int WPM = byte ? 1 : 2;
     const int H = (N + 4 * G - 1) / (4 * G) * (4 * G);
-    const size_t bytes = (size_t)(threads / G) * 2 * H * sizeof(uint32_t);
-    if (bytes > 163840) return hipErrorInvalidValue;
+    const int cpb = threads / G;
+    const size_t words = (size_t)cpb * WPM * H;
+    if (words * sizeof(uint32_t) > 163840) return hipErrorInvalidValue;
+    if (byte && (int)words - kZ26ListWords < 2 * z26_regrow_plane(N)) return hipErrorInvalidValue;
     v->family = 3;
     v->p0 = G;
-    v->p1 = 0;
+    v->p1 = byte ? 1 : 0;
     v->p2 = i16 ? 1 : 0;
     v->threads = threads;
-    v->cpb = threads / G;
-    v->shmem = bytes;
+    v->cpb = cpb;
+    v->shmem = words * sizeof(uint32_t);
     v->H = H;
     v->S = 0;
     return hipSuccess;
 }
 
+// Shape of the group kernel for a mapping: G lanes per chain (4: 8-bit n_m
+// fields, N <= 256; 8..64: 16-bit fields), `threads` per block (64 or 256);
+// byte words up to N = 640 where the block can host the regrowth, else wide
+// words.  For N <= 640 wide words always fit when byte words lack that room
+// (at most two chains per block), so a mapping legal at some N is legal at
+// every smaller N of the group kernel.
+static hipError_t z26_shape(int N, bool i16, int G, int threads, GrowVariant *v)
+{
+    if (G != 4 && G != 8 && G != 16 && G != 32 && G != 64) return hipErrorInvalidValue;
+    if (threads != 64 && threads != 256) return hipErrorInvalidValue;
+    if (G == 4 && N > 256) return hipErrorInvalidValue;
+    if (N <= kZ26ByteMaxN && z26_shape_fmt(N, i16, G, threads, true, v) == hipSuccess) return hipSuccess;
+    return z26_shape_fmt(N, i16, G, threads, false, v);
+}
+
 // One lane per chain up to N = 64 (and for exact weights, N <= 14); above,
 // G lanes per chain.  Built-in rule: G grows with N so that the chains a
-// CU's LDS holds still fill the CU (measured best widths): 4 up to N = 160
-// (whose 8-bit n_m fields need N <= 256), 8 up to 384, 16 up to 768, 32 up
-// to 1536, 64 beyond; 256-thread blocks when the block's planes fit in half
-// a CU's LDS, else one wave.  A legal mapping of the tuning table replaces
+// CU's LDS holds still fill the CU (measured best widths, byte words up to
+// N = 640): 4 up to N = 256 (whose 8-bit n_m fields need N <= 256), 8 up to
+// 384, 16 up to 768, 32 up to 1536, 64 beyond; 256-thread blocks when the
+// block's planes fit in half a CU's LDS, else one wave.  A legal mapping of the tuning table replaces
 // the rule for the group kernel.
 hipError_t lattice26_variant(const GrowArgs &a, bool exact, bool i16, GrowVariant *v)
 {
@@ -596,7 +763,7 @@ hipError_t lattice26_variant(const GrowArgs &a, bool exact, bool i16, GrowVarian
     if (tuned_mapping(2 /* 26-neighbour lattice */, N, a.k_trials, &tl, &tt) &&
         z26_shape(N, i16, tl, tt, v) == hipSuccess)
         return hipSuccess;
-    const int G = N <= 160 ? 4 : (N <= 384 ? 8 : (N <= 768 ? 16 : (N <= 1536 ? 32 : 64)));
+    const int G = N <= 256 ? 4 : (N <= 384 ? 8 : (N <= 768 ? 16 : (N <= 1536 ? 32 : 64)));
     GrowVariant half_cu;
     if (z26_shape(N, i16, G, 256, &half_cu) == hipSuccess && half_cu.shmem <= 81920) {
         *v = half_cu;
@@ -624,22 +791,36 @@ static hipError_t launch26_lane(const GrowArgs &a, const GrowVariant &v, const G
     });
 }
 
-template <int G, bool EXACT, typename CT>
+template <int G, typename CT, bool BYTE>
 static hipError_t launch26(const GrowArgs &a, const GrowVariant &v, const GrowEntry *tab, const uint64_t *block0,
                            int n, uint64_t blocks, size_t shmem, hipStream_t s)
 {
-    const void *fn = tab ? (const void *)grow_lattice26_batch<G, EXACT, CT> : (const void *)grow_lattice26<G, EXACT, CT>;
+    const void *fn = tab ? (const void *)grow_lattice26_batch<G, false, CT, BYTE>
+                         : (const void *)grow_lattice26<G, false, CT, BYTE>;
     if (shmem > 65536) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
         if (e != hipSuccess) return e;
     }
     return launch_sliced(blocks, v.threads, [&](uint64_t b0, uint32_t nb) {
         if (tab)
-            hipLaunchKernelGGL((grow_lattice26_batch<G, EXACT, CT>), dim3(nb), dim3(v.threads), shmem, s, tab,
+            hipLaunchKernelGGL((grow_lattice26_batch<G, false, CT, BYTE>), dim3(nb), dim3(v.threads), shmem, s, tab,
                                block0, n, b0);
         else
-            hipLaunchKernelGGL((grow_lattice26<G, EXACT, CT>), dim3(nb), dim3(v.threads), shmem, s, a, v.H, b0);
+            hipLaunchKernelGGL((grow_lattice26<G, false, CT, BYTE>), dim3(nb), dim3(v.threads), shmem, s, a, v.H,
+                               b0);
     });
+}
+
+template <int G>
+static hipError_t launch26_g(const GrowArgs &a, const GrowVariant &v, const GrowEntry *tab, const uint64_t *block0,
+                             int n, uint64_t blocks, size_t shmem, hipStream_t s)
+{
+    const bool i16 = v.p2 != 0;
+    if (v.p1)
+        return i16 ? launch26<G, int16_t, true>(a, v, tab, block0, n, blocks, shmem, s)
+                   : launch26<G, int32_t, true>(a, v, tab, block0, n, blocks, shmem, s);
+    return i16 ? launch26<G, int16_t, false>(a, v, tab, block0, n, blocks, shmem, s)
+               : launch26<G, int32_t, false>(a, v, tab, block0, n, blocks, shmem, s);
 }
 
 static hipError_t dispatch26(const GrowArgs &a, const GrowVariant &v, const GrowEntry *tab, const uint64_t *block0,
@@ -653,20 +834,13 @@ static hipError_t dispatch26(const GrowArgs &a, const GrowVariant &v, const Grow
         return i16 ? launch26_lane<false, int16_t>(a, v, tab, block0, n, blocks, shmem, s)
                    : launch26_lane<false, int32_t>(a, v, tab, block0, n, blocks, shmem, s);
     }
-    if (v.p0 == 4)
-        return i16 ? launch26<4, false, int16_t>(a, v, tab, block0, n, blocks, shmem, s)
-                   : launch26<4, false, int32_t>(a, v, tab, block0, n, blocks, shmem, s);
-    if (v.p0 == 8)
-        return i16 ? launch26<8, false, int16_t>(a, v, tab, block0, n, blocks, shmem, s)
-                   : launch26<8, false, int32_t>(a, v, tab, block0, n, blocks, shmem, s);
-    if (v.p0 == 16)
-        return i16 ? launch26<16, false, int16_t>(a, v, tab, block0, n, blocks, shmem, s)
-                   : launch26<16, false, int32_t>(a, v, tab, block0, n, blocks, shmem, s);
-    if (v.p0 == 32)
-        return i16 ? launch26<32, false, int16_t>(a, v, tab, block0, n, blocks, shmem, s)
-                   : launch26<32, false, int32_t>(a, v, tab, block0, n, blocks, shmem, s);
-    return i16 ? launch26<64, false, int16_t>(a, v, tab, block0, n, blocks, shmem, s)
-               : launch26<64, false, int32_t>(a, v, tab, block0, n, blocks, shmem, s);
+    switch (v.p0) {
+    case 4: return launch26_g<4>(a, v, tab, block0, n, blocks, shmem, s);
+    case 8: return launch26_g<8>(a, v, tab, block0, n, blocks, shmem, s);
+    case 16: return launch26_g<16>(a, v, tab, block0, n, blocks, shmem, s);
+    case 32: return launch26_g<32>(a, v, tab, block0, n, blocks, shmem, s);
+    default: return launch26_g<64>(a, v, tab, block0, n, blocks, shmem, s);
+    }
 }
 
 hipError_t launch_grow_lattice26(const GrowArgs &a, bool exact, bool i16, hipStream_t s)

@@ -1,4 +1,4 @@
-"""Boxed byte words of the long-chain lattice kernel against the oracle.
+"""Boxed byte words of the long-chain lattice kernels against the oracle.
 
 Beyond N = 128 the simple cubic LDS kernel keeps one byte per coordinate
 up to N = 2048 and regrows, in two-word format, any chain whose tip reaches
@@ -7,8 +7,10 @@ chain of these sizes gets there).  Lowering the edge sends many chains of
 every block through that regrowth, including blocks with more such chains
 than fit in one pass of the block's LDS and, at edge 1, every chain.  Every
 per-chain output and the summaries must still match the oracle bit for bit
-(Sec. 3.3.2; the oracle knows nothing of word formats).  GPU test; calls the
-HIP library through its C ABI.
+(Sec. 3.3.2; the oracle knows nothing of word formats).  The 26-neighbour
+group kernel keeps byte words up to N = 640 in a box of |coordinate| <= 61
+and regrows the same way.  GPU test; calls the HIP library through its C
+ABI.
 """
 import numpy as np
 import pytest
@@ -84,3 +86,48 @@ def test_regrown_chains_in_a_batch():
         np.testing.assert_array_equal(out["n2rg2"].cpu().numpy(), ref["n2rg2"])
         red = oracle.reduce(sp["N"], ref["log_w"], ref["r2"], ref["rg2"], ref["n_grown"])
         _check_summary(s, red, sp["n_chains"])
+
+
+# 26-neighbour lattice: byte words (x, y, z + 64, plus 128) in the group
+# kernel up to N = 640; a chain whose tip reaches |coordinate| = min(edge,
+# 62) is regrown in two-word format by its block.
+@pytest.mark.parametrize("N,M,seed,coord,edge,mapping,offset,restart", [
+    (200, 800, 91, "i16", 20, None, 0, False),
+    # 4 lanes per chain (8-bit n_m fields), every chain regrown from step 1
+    (129, 600, 92, "i32", 1, None, 0, False),
+    (300, 300, 93, "i16", 25, None, 0, True),
+    (384, 200, 94, "i32", 30, None, 0, False),
+    (640, 60, 95, "i16", 40, None, 0, False),
+    # the production edge: chain 11031 of seed 1 (N = 256) reaches x = 63
+    (256, 300, 1, "i16", 127, None, 11_000, False),
+    # four chains per one-wave block; one chain per block (wide words)
+    (200, 300, 96, "i32", 20, (16, 64), 0, False),
+    (200, 300, 97, "i16", 20, (64, 64), 0, False),
+])
+def test_lattice26_regrown_chains_bit_exact(N, M, seed, coord, edge, mapping, offset, restart):
+    from test_gpu_lattice26 import _case
+    rs.set_byte_box(edge)
+    if mapping:
+        rs.mapping_set("lattice26", 26, N, N, *mapping)
+        q = rs.mapping_query(rs.make_config("lattice26", N, 26, M, seed))
+        assert (q["lanes"], q["threads"]) == mapping
+    out, _ = _case(N, M, seed, coord=coord, bins=64, offset=offset, restart=restart)
+    reach = np.abs(out["r_end"].astype(np.int64)).max(axis=0)
+    assert (reach >= min(edge, 62)).sum() > 0 or offset
+
+
+def test_lattice26_regrown_chains_in_a_batch():
+    rs.set_byte_box(20)
+    specs = [dict(geometry="lattice26", N=200, k=26, n_chains=500, seed=98),
+             dict(geometry="lattice", N=300, k=6, n_chains=300, seed=99, coord="i16"),
+             dict(geometry="lattice26", N=150, k=26, n_chains=300, seed=100, coord="i16")]
+    print("[gpu] boxed z26 batch", flush=True)
+    res = rs.gen_batch(specs)
+    torch.cuda.synchronize()
+    for sp, (out, s) in zip(specs, res):
+        z26 = sp["geometry"] == "lattice26"
+        ref = oracle.gen_lattice(sp["seed"], sp["N"], sp["n_chains"], z26=z26)
+        np.testing.assert_array_equal(out["n_grown"].cpu().numpy().view(np.uint16), ref["n_grown"])
+        np.testing.assert_array_equal(out["log_w"].cpu().numpy(), ref["log_w"])
+        np.testing.assert_array_equal(out["r_end"].cpu().numpy().astype(np.int32), ref["r_end"])
+        np.testing.assert_array_equal(out["n2rg2"].cpu().numpy(), ref["n2rg2"])
