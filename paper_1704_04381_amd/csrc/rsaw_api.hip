@@ -106,6 +106,7 @@ rsaw_status workspace(int dev, hipStream_t s, size_t need, void **out)
         hipError_t e = hipMalloc(&w.base, sz);
         if (e != hipSuccess) {
             w.base = nullptr;
+            (void)hipGetLastError(); // a failed allocation must not fail the thread's next launch check
             return fail(RSAW_E_NOMEM, std::string("workspace hipMalloc: ") + hipGetErrorString(e));
         }
         w.bytes = sz;
@@ -137,6 +138,7 @@ rsaw_status staging(int dev, hipStream_t s, size_t need, void **out, hipEvent_t 
         hipError_t e = hipHostMalloc(&w.stage, sz, hipHostMallocDefault);
         if (e != hipSuccess) {
             w.stage = nullptr;
+            (void)hipGetLastError();
             return fail(RSAW_E_NOMEM, std::string("staging hipHostMalloc: ") + hipGetErrorString(e));
         }
         w.stage_bytes = sz;
@@ -637,7 +639,10 @@ rsaw_status batch_impl(const rsaw_config *cfgs, const rsaw_chain_out *outs, int3
     hipEvent_t stage_done = nullptr;
     if (plan) {
         e = hipMalloc(&wsv, off_end);
-        if (e != hipSuccess) return fail(RSAW_E_NOMEM, std::string("plan hipMalloc: ") + hipGetErrorString(e));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(RSAW_E_NOMEM, std::string("plan hipMalloc: ") + hipGetErrorString(e));
+        }
         plan->dev = dev;
         plan->ws = wsv;
         plan_stage.resize(tab_bytes);

@@ -279,6 +279,7 @@ rsaw_status rsaw_server_create(const rsaw_server_params *params, int32_t device,
         if (!ok) break;
     }
     if (!ok) {
+        (void)hipGetLastError(); // the failed call must not fail the thread's next launch check
         for (Slot &sl : s->slots) {
             if (sl.stream) {
                 (void)rsaw_set_workspace(nullptr, 0, sl.stream);
