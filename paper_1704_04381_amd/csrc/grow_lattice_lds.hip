@@ -132,7 +132,10 @@ __device__ __forceinline__ bool lattice_lds_grow(const GrowArgs &a, const uint32
     bool alive = false;
     bool left_box = false;
     int grown = 1;
-    uint64_t cnt = 0; // 16-bit fields: steps with m = 2, 3, 4, 5 (step 1 has m = 6)
+    // steps with m free candidates: 16-bit fields for m = 2, 3, 4, 5 (wide
+    // words; step 1 has m = 6), 12-bit fields at 12 (m - 1) for m = 1..6
+    // (byte words, N <= 2048: no test of m or i needed)
+    uint64_t cnt = 0;
     bool rng_fail = false;
     Philox4 blk{0, 0, 0, 0};
     // outputs of the attempt that ends the chain (see the register kernel)
@@ -219,7 +222,7 @@ __device__ __forceinline__ bool lattice_lds_grow(const GrowArgs &a, const uint32
             }
 
             bool step_ok = alive && m != 0;
-            const uint32_t li = (freem << 3) | (r & 7u);
+            const uint32_t li = (freem << 3) | r; // r < m <= 6, or 0
             uint32_t na, nb = 0u;
             if constexpr (WIDE) {
                 uint32_t da, db;
@@ -258,7 +261,11 @@ __device__ __forceinline__ bool lattice_lds_grow(const GrowArgs &a, const uint32
             if (step_ok) {
                 ta = na;
                 tb = nb;
-                if (i >= 2 && m >= 2) cnt += 1ull << (16u * (m - 2u));
+                if constexpr (WIDE) {
+                    if (i >= 2 && m >= 2) cnt += 1ull << (16u * (m - 2u));
+                } else {
+                    cnt += 1ull << (12u * (m - 1u));
+                }
                 if (t == 0) {
                     uint32_t *wp = base + (i & 1) * WPM * H + (i >> 1);
                     wp[0] = na;
@@ -272,10 +279,12 @@ __device__ __forceinline__ bool lattice_lds_grow(const GrowArgs &a, const uint32
         // m_1 = 6 always
         double lw = 0.0;
         if (N >= 2) {
-            lw = lw + (double)(uint32_t)(cnt & 0xFFFFu) * a.logm[2];
-            lw = lw + (double)(uint32_t)((cnt >> 16) & 0xFFFFu) * a.logm[3];
-            lw = lw + (double)(uint32_t)((cnt >> 32) & 0xFFFFu) * a.logm[4];
-            lw = lw + (double)(uint32_t)((cnt >> 48) & 0xFFFFu) * a.logm[5];
+            const int f0 = WIDE ? 0 : 12, fw = WIDE ? 16 : 12;
+            const uint64_t fm = WIDE ? 0xFFFFu : 0xFFFu;
+            lw = lw + (double)(uint32_t)((cnt >> f0) & fm) * a.logm[2];
+            lw = lw + (double)(uint32_t)((cnt >> (f0 + fw)) & fm) * a.logm[3];
+            lw = lw + (double)(uint32_t)((cnt >> (f0 + 2 * fw)) & fm) * a.logm[4];
+            lw = lw + (double)(uint32_t)((cnt >> (f0 + 3 * fw)) & fm) * a.logm[5];
             lw = lw + a.logm[6];
         }
 
