@@ -130,7 +130,7 @@ __device__ __forceinline__ void z26_fill_select_table(uint8_t *sel)
 
 // Byte words of the group kernel (N <= 640): one word per monomer, bytes
 // (x + 64, y + 64, z + 64) plus 128 each, the pair test of the one-lane
-// kernel (z26_bits8, nine operations) against the tip's raw word.  The test
+// kernel (z26_bits8, six operations) against the tip's raw word.  The test
 // needs every tip coordinate within [-62, 63] (at least 2 from the sentinel
 // at -64) and every stored one within [-64, 63]; a chain whose new tip
 // reaches |coordinate| = E (62, or the launch's byte_box if smaller) stops,
@@ -144,13 +144,19 @@ constexpr int kZ26ListWords = 65; // count + one slot per chain of a block (<= 6
 constexpr uint32_t kZ26Bias = 0x00808080u;
 constexpr uint32_t kZ26LaneOrigin = 0x00404040u; // raw (64, 64, 64): the origin
 
-__device__ __forceinline__ uint32_t z26_bits8(uint32_t w, uint32_t t, uint32_t tb)
+// Pair test of a stored byte word w (raw bytes + 128) against
+// tp = tip + 0x7F7F7F (raw tip bytes + 127), for tips at least 2 from the
+// sentinel: v = w - tp has bytes d + 1 for d = raw_w - raw_tip when every
+// |d| <= 1 (no byte borrows); a byte with d <= -2 borrows and is left at
+// 0x80 or above, a byte with d >= 2 is left at 3 or above.  So the site is a
+// candidate iff every byte of v and of v + 0x010101 stays below 4, and its
+// code (dx + 1) + 3 (dy + 1) + 9 (dz + 1) is dot4(v, (1, 3, 9, 0)).
+__device__ __forceinline__ uint32_t z26_bits8(uint32_t w, uint32_t tp)
 {
-    const uint32_t e = (w - t) ^ kZ26Bias;
-    const uint32_t q = (uint32_t)__builtin_amdgcn_sdot4((int)e, (int)e, 0, false);
-    const uint32_t s1 = __builtin_amdgcn_sad_u8(w, tb, 1u);
-    const int code = __builtin_amdgcn_sdot4((int)e, 0x00090301, 13, false);
-    return __builtin_elementwise_sub_sat(s1, q) << ((uint32_t)code & 31u);
+    const uint32_t v = w - tp;
+    const uint32_t bad = (v | (v + 0x010101u)) & 0x00FCFCFCu;
+    const uint32_t code = __builtin_amdgcn_udot4(v, 0x00090301u, 0u, false);
+    return __builtin_elementwise_sub_sat(1u, bad) << (code & 31u);
 }
 
 // Bytes (dx + 1, dy + 1, dz + 1) of code c = (dx + 1) + 3 (dy + 1) + 9 (dz + 1).
@@ -240,16 +246,16 @@ __device__ __forceinline__ bool z26_grow(const GrowArgs &a, const double *logm, 
             const int nrel = i - 1;
             const int passes = (nrel + 4 * G - 1) / (4 * G);
             uint32_t occ = 0, occ2 = 0;
-            const uint32_t tbias = ta + kZ26Bias;
+            const uint32_t tp = ta + 0x7F7F7Fu;
             // two passes per iteration, so that the second pass's reads are in
             // flight while the first is tested; entries at nrel and beyond hold
             // the sentinel (never a candidate) or the tip (code 13, masked)
             auto test4 = [&](const uint4 &wa, const uint4 &wb) {
                 if constexpr (BYTE) {
-                    occ |= z26_bits8(wa.x, ta, tbias);
-                    occ2 |= z26_bits8(wa.y, ta, tbias);
-                    occ |= z26_bits8(wa.z, ta, tbias);
-                    occ2 |= z26_bits8(wa.w, ta, tbias);
+                    occ |= z26_bits8(wa.x, tp);
+                    occ2 |= z26_bits8(wa.y, tp);
+                    occ |= z26_bits8(wa.z, tp);
+                    occ2 |= z26_bits8(wa.w, tp);
                 } else {
                     occ |= z26_bits(wa.x, wb.x, ta, tb);
                     occ2 |= z26_bits(wa.y, wb.y, ta, tb);
@@ -504,12 +510,12 @@ __global__ __launch_bounds__(256) void grow_lattice26_batch(const GrowEntry *tab
 // of lane L is entry g * T + L of the block's group array, so a wave reads
 // 1 KB of consecutive groups per ds_read_b128.  Unplaced entries hold the
 // sentinel 0x00808080 (raw coordinates -64, at least 2 from every tip).
-// Pair test of a stored word w against the tip word t (raw, unbiased):
-//   e  = (w - t) ^ 0x00808080       signed bytes (dx, dy, dz, 0), no borrow
-//   q  = dot4(e, e) = dx^2 + dy^2 + dz^2
-//   s1 = sad_u8(w, t + 0x00808080) + 1 = |dx| + |dy| + |dz| + 1
-//   code = dot4(e, (1, 3, 9, 0)) + 13;   occ |= sat(s1 - q) << code
-// nine operations with the two accumulator copies.  The counts n_m of the
+// Pair test of a stored word w against the tip word t (raw, unbiased), with
+// tp = t + 0x7F7F7F (z26_bits8):
+//   v    = w - tp                    bytes d + 1 when every |d| <= 1
+//   bad  = (v | (v + 0x010101)) & 0xFCFCFC   0 iff every |d| <= 1
+//   code = dot4(v, (1, 3, 9, 0));    occ |= sat(1 - bad) << code
+// six operations.  The counts n_m of the
 // steps with m free candidates are 8-bit fields in LDS (seven words per
 // lane); the r-th free code comes from the byte holding it and a 2 KB table
 // of the k-th set bit of every byte value.
@@ -582,13 +588,13 @@ __device__ __forceinline__ void grow_lattice26_lane_body(const GrowArgs &a, uint
             // monomers 0 .. i-2 in groups of four; the last group may also hold
             // the tip (code 13, masked) and sentinels
             const int ng = (i + 2) >> 2;
-            const uint32_t tb = tip + kZ26Bias;
+            const uint32_t tp = tip + 0x7F7F7Fu;
             uint32_t occ = 0, occ2 = 0;
             auto test4 = [&](const uint4 &w) {
-                occ |= z26_bits8(w.x, tip, tb);
-                occ2 |= z26_bits8(w.y, tip, tb);
-                occ |= z26_bits8(w.z, tip, tb);
-                occ2 |= z26_bits8(w.w, tip, tb);
+                occ |= z26_bits8(w.x, tp);
+                occ2 |= z26_bits8(w.y, tp);
+                occ |= z26_bits8(w.z, tp);
+                occ2 |= z26_bits8(w.w, tp);
             };
             int q = 0;
             for (; q + 1 < ng; q += 2) { // two groups in flight, as in the group kernel
