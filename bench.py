@@ -124,12 +124,13 @@ def lattice26_alg_ops_per_chain(N: int) -> int:
     """Algorithmic VALU lane-operations to grow one 26-neighbour lattice chain.
 
     Per step i: the pair tests against monomers 0..i-2 (no parity pruning:
-    a diagonal step keeps the parity), 7 operations each (byte difference,
-    sign fix, squared distance, L1 distance, direction code, neighbour flag,
-    mask insert); 8 for the step's share of a Philox block; and 20 to count
-    the free codes, select the r-th, apply the move and tally m_i.
+    a diagonal step keeps the parity), 6 operations each (byte differences,
+    their shifted copy, the range test of every coordinate, the neighbour
+    flag, the direction code, the mask insert); 8 for the step's share of a
+    Philox block; and 20 to count the free codes, select the r-th, apply the
+    move and tally m_i.
     """
-    return sum(7 * max(i - 1, 0) + 8 + 20 for i in range(1, N))
+    return sum(6 * max(i - 1, 0) + 8 + 20 for i in range(1, N))
 
 
 def path_model(w) -> dict:

@@ -23,8 +23,8 @@ def test_lattice_model_per_chain():
 
 
 def test_lattice26_model_per_chain():
-    # sum over steps i = 1..63 of 7 (i - 1) + 28
-    assert bench.lattice26_alg_ops_per_chain(64) == 7 * 1953 + 28 * 63 == 15435
+    # sum over steps i = 1..63 of 6 (i - 1) + 28
+    assert bench.lattice26_alg_ops_per_chain(64) == 6 * 1953 + 28 * 63 == 13482
     assert bench.lattice26_alg_ops_per_chain(2) == 28
 
 
