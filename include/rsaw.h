@@ -488,7 +488,7 @@ rsaw_status rsaw_fp64_check(const double *d_a, const double *d_b, double *d_sqrt
  *   RSAW_REAL_HS     lanes 8, 16, 32, 64 with lanes >= k; lanes 64 only
  *                    with 64 threads; N <= 1536;
  *   RSAW_LATTICE_26  lanes 4 (N <= 256 only), 8, 16, 32, 64; up to
- *                    N = 640 one word per monomer where the block can
+ *                    N = 4096 one word per monomer where the block can
  *                    also hold one chain's regrowth, else two;
  * threads 64 or 256; and the block's LDS (lds_bytes) at most 160 KiB.
  * Calls outside the group kernels' ranges (lattice N <= 64 or exact
@@ -517,17 +517,18 @@ typedef struct {
 rsaw_status rsaw_mapping_set(const rsaw_mapping *m);
 
 /*
- * rsaw_set_byte_box — tuning and testing knob of the lattice kernels with
- * one byte per coordinate (Sec. 3.3.2 growth; simple cubic lattice beyond
- * N = 128, 26-neighbour group kernel up to N = 640): a chain whose tip
- * reaches |x|, |y| or |z| = edge (at most 62 on the 26-neighbour lattice)
- * is dropped from the byte-word kernel and grown again, from its first
- * draw, in two-word format by the same block.  The default, 127, gives the
- * largest exact edges (127 and 62); a smaller one only sends more chains
- * through the regrowth.
- * Results never depend on it: every chain is bit-identical either way.
- * Process-wide; applies to calls enqueued after it.  Host-only.
- * Errors: RSAW_E_INVALID unless 1 <= edge <= 127.
+ * rsaw_set_byte_box — tuning and testing knob of the lattice kernels that
+ * keep one 32-bit word per monomer (Sec. 3.3.2 growth; simple cubic lattice
+ * beyond N = 128 in byte words, 26-neighbour group kernel in byte words up
+ * to N = 640 and packed 11/11/10-bit words up to N = 4096): a chain whose
+ * tip reaches |x|, |y| or |z| = edge is dropped from that kernel and grown
+ * again, from its first draw, in two-word format by the same block.  Each
+ * format has its own largest exact edge (127, 62 and 254); edge = 0 (the
+ * default) uses those, 1..127 lowers every edge to at most that value,
+ * which only sends more chains through the regrowth.  Results never depend
+ * on it: every chain is bit-identical either way.  Process-wide; applies
+ * to calls enqueued after it.  Host-only.
+ * Errors: RSAW_E_INVALID unless 0 <= edge <= 127.
  */
 rsaw_status rsaw_set_byte_box(int32_t edge);
 

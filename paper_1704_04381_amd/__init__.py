@@ -531,9 +531,9 @@ def mapping_clear() -> None:
 
 
 def set_byte_box(edge: int) -> None:
-    """|coordinate| at which the lattice byte-word kernels beyond N = 128
-    regrow a chain in two-word format (rsaw_set_byte_box; 1..127, default
-    127).  Results do not depend on it."""
+    """|coordinate| at which the one-word lattice kernels regrow a chain in
+    two-word format (rsaw_set_byte_box; 1..127 lowers every format's edge,
+    0 restores each format's own).  Results do not depend on it."""
     _check(load().rsaw_set_byte_box(int(edge)))
 
 

@@ -139,7 +139,6 @@ __device__ __forceinline__ void z26_fill_select_table(uint8_t *sel)
 // give the same chain, Sec. 3.3.2).
 constexpr int kZ26ByteMaxN = 640;
 constexpr int kZ26ByteEdge = 62;
-constexpr int kZ26RegrowLanes = 8;
 constexpr int kZ26ListWords = 65; // count + one slot per chain of a block (<= 64)
 constexpr uint32_t kZ26Bias = 0x00808080u;
 constexpr uint32_t kZ26LaneOrigin = 0x00404040u; // raw (64, 64, 64): the origin
@@ -168,19 +167,60 @@ __device__ __forceinline__ uint32_t z26_move_bytes(uint32_t code)
     return (rem - 3u * y) | (y << 8) | (z << 16);
 }
 
-// Plane length of the wide regrowth (kZ26RegrowLanes lanes per chain).
+// Packed words of the group kernel (640 < N <= 4096): one word per
+// monomer, x + 1024 in bits 0-10, y + 1024 in bits 11-21, z + 512 in bits
+// 22-31.  The byte test carries over field by field: with
+// tp = tip - (1, 1, 1), v = w - tp has fields d + 1 when every |d| <= 1; a
+// field with d <= -2 borrows and, for |d| <= 2^(width - 1) - 2, is left at
+// 2^(width - 1) + 2 or above, one with d >= 2 at 3 or above.  Tips stay
+// within |coordinate| <= 253 (a box like the byte words'), stored monomers
+// within 254, the sentinel (-512, -512, -256) is at least 3 away, so every
+// difference meets that bound.  The code (dx + 1) + 3 (dy + 1) + 9 (dz + 1)
+// of a candidate is bits 22-26 of v * (2^22 + 3 * 2^11 + 9) (24-bit
+// multiply; the lower products stay below 2^22).  Seven operations.
+constexpr int kZ26PackedMaxN = 4096;
+constexpr int kZ26PackedEdge = 254;
+constexpr uint32_t kP32One = 1u | (1u << 11) | (1u << 22);
+constexpr uint32_t kP32Origin = 1024u | (1024u << 11) | (512u << 22);
+constexpr uint32_t kP32Sentinel = 512u | (512u << 11) | (256u << 22);
+constexpr uint32_t kP32High = 0x7FCu | (0x7FCu << 11) | (0x3FCu << 22); // field bits above 1
+constexpr uint32_t kP32Code = (1u << 22) + (3u << 11) + 9u;
+
+__device__ __forceinline__ uint32_t z26_bits32(uint32_t w, uint32_t tp)
+{
+    const uint32_t v = w - tp;
+    const uint32_t bad = (v | (v + kP32One)) & kP32High;
+    const uint32_t code = __umul24(v, kP32Code) >> 22;
+    return __builtin_elementwise_sub_sat(1u, bad) << (code & 31u);
+}
+
+// Fields (dx + 1, dy + 1, dz + 1) of code c in the packed layout.
+__device__ __forceinline__ uint32_t z26_move_packed(uint32_t code)
+{
+    const uint32_t z = (code * 57u) >> 9; // code / 9
+    const uint32_t rem = code - 9u * z;
+    const uint32_t y = (rem * 11u) >> 5; // rem / 3
+    return (rem - 3u * y) | (y << 11) | (z << 22);
+}
+
+// Lanes per chain and plane length of the wide regrowth.
+__host__ __device__ __forceinline__ int z26_regrow_lanes(int N) { return N <= 512 ? 8 : 32; }
 __host__ __device__ __forceinline__ int z26_regrow_plane(int N)
 {
-    constexpr int q = 4 * kZ26RegrowLanes;
+    const int q = 4 * z26_regrow_lanes(N);
     return (N + q - 1) / q * q;
 }
 
+// Word formats of the group kernel.
+constexpr int kZ26Wide = 0, kZ26Byte = 1, kZ26Packed = 2;
+
 // Grows chain c of this thread's group of G lanes, its history at PA (wide
-// words: planes PA and PA + H; byte words: one plane of H words), and writes
-// its outputs.  With box > 0 (byte words) a chain whose tip reaches
-// |coordinate| = box stops, writes nothing and contributes nothing to the
-// side channels; the function then returns true on the group's lanes.
-template <int G, bool EXACT, typename CT, bool BYTE>
+// words: planes PA and PA + H; byte or packed words: one plane of H words),
+// and writes its outputs.  With box > 0 (byte and packed words) a chain
+// whose tip reaches |coordinate| = box stops, writes nothing and contributes
+// nothing to the side channels; the function then returns true on the
+// group's lanes.
+template <int G, bool EXACT, typename CT, int FMT>
 __device__ __forceinline__ bool z26_grow(const GrowArgs &a, const double *logm, uint32_t *PA, int H, uint64_t c,
                                          bool valid, int box)
 {
@@ -190,8 +230,9 @@ __device__ __forceinline__ bool z26_grow(const GrowArgs &a, const double *logm, 
     const uint64_t g = a.chain_offset + c;
     const int N = a.n_monomers;
     uint32_t *PB = PA + H;
+    constexpr bool BYTE = FMT == kZ26Byte, PACKED = FMT == kZ26Packed, ONE = FMT != kZ26Wide;
 
-    // tip: A and B words (wide), or the raw byte word in ta (byte)
+    // tip: A and B words (wide), the raw byte word (byte) or the packed word
     uint32_t ta = 0, tb = 0;
     bool alive = false;
     bool left_box = false;
@@ -216,21 +257,21 @@ __device__ __forceinline__ bool z26_grow(const GrowArgs &a, const double *logm, 
     for (uint32_t rd = 0; rd < a.max_rounds; ++rd) {
         if (pending) {
             if (rd > 0) {
-                if constexpr (BYTE) {
-                    for (int w = t; w < H; w += G) PA[w] = kZ26Bias;
+                if constexpr (ONE) {
+                    for (int w = t; w < H; w += G) PA[w] = BYTE ? kZ26Bias : kP32Sentinel;
                 } else {
                     for (int w = t; w < 2 * H; w += G) PA[w] = w < H ? 0u : kZ26OriginB;
                 }
             }
-            ta = BYTE ? kZ26LaneOrigin : kZ26OriginA;
-            tb = BYTE ? 0u : kZ26OriginB;
+            ta = BYTE ? kZ26LaneOrigin : (PACKED ? kP32Origin : kZ26OriginA);
+            tb = ONE ? 0u : kZ26OriginB;
             n_mine = 0;
             wx = 1;
         }
         z26_wave_sync();
         if (pending && t == 0) {
-            if constexpr (BYTE) {
-                PA[0] = ta + kZ26Bias;
+            if constexpr (ONE) {
+                PA[0] = BYTE ? ta + kZ26Bias : ta;
             } else {
                 PA[0] = ta;
                 PB[0] = tb;
@@ -246,7 +287,7 @@ __device__ __forceinline__ bool z26_grow(const GrowArgs &a, const double *logm, 
             const int nrel = i - 1;
             const int passes = (nrel + 4 * G - 1) / (4 * G);
             uint32_t occ = 0, occ2 = 0;
-            const uint32_t tp = ta + 0x7F7F7Fu;
+            const uint32_t tp = PACKED ? ta - kP32One : ta + 0x7F7F7Fu;
             // two passes per iteration, so that the second pass's reads are in
             // flight while the first is tested; entries at nrel and beyond hold
             // the sentinel (never a candidate) or the tip (code 13, masked)
@@ -256,6 +297,11 @@ __device__ __forceinline__ bool z26_grow(const GrowArgs &a, const double *logm, 
                     occ2 |= z26_bits8(wa.y, tp);
                     occ |= z26_bits8(wa.z, tp);
                     occ2 |= z26_bits8(wa.w, tp);
+                } else if constexpr (PACKED) {
+                    occ |= z26_bits32(wa.x, tp);
+                    occ2 |= z26_bits32(wa.y, tp);
+                    occ |= z26_bits32(wa.z, tp);
+                    occ2 |= z26_bits32(wa.w, tp);
                 } else {
                     occ |= z26_bits(wa.x, wb.x, ta, tb);
                     occ2 |= z26_bits(wa.y, wb.y, ta, tb);
@@ -268,7 +314,7 @@ __device__ __forceinline__ bool z26_grow(const GrowArgs &a, const double *logm, 
                 const int k1 = q * 4 * G + 4 * t, k2 = k1 + 4 * G;
                 const uint4 a1 = *(const uint4 *)(PA + k1), a2 = *(const uint4 *)(PA + k2);
                 uint4 b1 = make_uint4(0u, 0u, 0u, 0u), b2 = b1;
-                if constexpr (!BYTE) {
+                if constexpr (!ONE) {
                     b1 = *(const uint4 *)(PB + k1);
                     b2 = *(const uint4 *)(PB + k2);
                 }
@@ -278,7 +324,7 @@ __device__ __forceinline__ bool z26_grow(const GrowArgs &a, const double *logm, 
             if (q < passes) {
                 const int k1 = q * 4 * G + 4 * t;
                 uint4 b1 = make_uint4(0u, 0u, 0u, 0u);
-                if constexpr (!BYTE) b1 = *(const uint4 *)(PB + k1);
+                if constexpr (!ONE) b1 = *(const uint4 *)(PB + k1);
                 test4(*(const uint4 *)(PA + k1), b1);
             }
             occ = z26_group_or<G>(occ | occ2);
@@ -308,6 +354,8 @@ __device__ __forceinline__ bool z26_grow(const GrowArgs &a, const double *logm, 
                 // bytes dx + 1, dy + 1, dz + 1 added, then 1 taken from each:
                 // no carry or borrow for a tip inside the box
                 na = ta + z26_move_bytes(code) - 0x010101u;
+            } else if constexpr (PACKED) {
+                na = ta + z26_move_packed(code) - kP32One; // no carry or borrow in the box
             } else {
                 uint32_t da, db;
                 z26_move(code, da, db);
@@ -328,6 +376,20 @@ __device__ __forceinline__ bool z26_grow(const GrowArgs &a, const double *logm, 
                         left_box = true;
                     }
                 }
+            } else if constexpr (PACKED) {
+                // |coordinate| >= E, possible from step E on
+                if (box > 0 && i >= box) {
+                    const int ex = (int)(na & 0x7FFu) - 1024, ey = (int)((na >> 11) & 0x7FFu) - 1024,
+                              ez = (int)(na >> 22) - 512;
+                    const uint32_t span = 2u * (uint32_t)box - 2u; // |e| < E iff e + E - 1 <= 2 E - 2
+                    const bool out = (uint32_t)(ex + box - 1) > span || (uint32_t)(ey + box - 1) > span ||
+                                     (uint32_t)(ez + box - 1) > span;
+                    if (step_ok && out) {
+                        step_ok = false;
+                        alive = false;
+                        left_box = true;
+                    }
+                }
             }
             if (step_ok) {
                 ta = na;
@@ -336,8 +398,8 @@ __device__ __forceinline__ bool z26_grow(const GrowArgs &a, const double *logm, 
                 n_mine += (mm1 & (G - 1)) == (uint32_t)t ? 1ull << (FW * (mm1 / G)) : 0ull;
                 if (EXACT) wx = wx * (uint64_t)m;
                 if (t == 0) {
-                    if constexpr (BYTE) {
-                        PA[i] = ta + kZ26Bias;
+                    if constexpr (ONE) {
+                        PA[i] = BYTE ? ta + kZ26Bias : ta;
                     } else {
                         PA[i] = ta;
                         PB[i] = tb;
@@ -370,6 +432,11 @@ __device__ __forceinline__ bool z26_grow(const GrowArgs &a, const double *logm, 
                 xx = (int32_t)(w & 0xFFu) - 192;
                 yy = (int32_t)((w >> 8) & 0xFFu) - 192;
                 zz = (int32_t)((w >> 16) & 0xFFu) - 192;
+            } else if constexpr (PACKED) {
+                const uint32_t w = PA[j];
+                xx = (int32_t)(w & 0x7FFu) - 1024;
+                yy = (int32_t)((w >> 11) & 0x7FFu) - 1024;
+                zz = (int32_t)(w >> 22) - 512;
             } else {
                 xx = (int32_t)(PA[j] & 0xFFFFu) - 32768;
                 yy = (int32_t)(PA[j] >> 16) - 32768;
@@ -398,6 +465,10 @@ __device__ __forceinline__ bool z26_grow(const GrowArgs &a, const double *logm, 
                 res_ex = (int32_t)(ta & 0xFFu) - 64;
                 res_ey = (int32_t)((ta >> 8) & 0xFFu) - 64;
                 res_ez = (int32_t)((ta >> 16) & 0xFFu) - 64;
+            } else if constexpr (PACKED) {
+                res_ex = (int32_t)(ta & 0x7FFu) - 1024;
+                res_ey = (int32_t)((ta >> 11) & 0x7FFu) - 1024;
+                res_ez = (int32_t)(ta >> 22) - 512;
             } else {
                 res_ex = (int32_t)(ta & 0xFFFFu) - 32768;
                 res_ey = (int32_t)(ta >> 16) - 32768;
@@ -434,10 +505,31 @@ __device__ __forceinline__ bool z26_grow(const GrowArgs &a, const double *logm, 
     return left_box;
 }
 
-// Chains of the block that left the byte box (`mine` on the leader lane of
-// each), grown again in wide words with kZ26RegrowLanes lanes per chain in
-// the block's own LDS of `words` words, as many at a time as fit.  Every
-// thread of the block calls this.
+// Passes of the wide regrowth with GW lanes per chain: `slots` chains at a
+// time from the list at z26_lds[1..n].
+template <int GW, typename CT>
+__device__ void z26_regrow_passes(const GrowArgs &a, const double *logm, uint64_t first_chain, int n, int slots)
+{
+    extern __shared__ uint32_t z26_lds[];
+    const int HW = z26_regrow_plane(a.n_monomers);
+    uint32_t *planes = z26_lds + kZ26ListWords;
+    const int gw = threadIdx.x / GW;
+    for (int b0 = 0; b0 < n; b0 += slots) {
+        __syncthreads();
+        for (int w = threadIdx.x; w < slots * 2 * HW; w += blockDim.x)
+            planes[w] = ((w / HW) & 1) ? kZ26OriginB : 0u;
+        __syncthreads();
+        const bool v = gw < slots && b0 + gw < n;
+        const uint64_t c = first_chain + (v ? z26_lds[1 + b0 + gw] : 0u);
+        if (__ballot(v) != 0) // waves without such a chain skip the growth
+            z26_grow<GW, false, CT, kZ26Wide>(a, logm, planes + (v ? gw : 0) * 2 * HW, HW, c, v, 0);
+    }
+}
+
+// Chains of the block that left the box of the byte or packed words (`mine`
+// on the leader lane of each), grown again in wide words (8 lanes per chain
+// up to N = 512, 32 beyond) in the block's own LDS of `words` words, as many
+// at a time as fit.  Every thread of the block calls this.
 template <typename CT>
 __device__ void z26_regrow_wide(const GrowArgs &a, const double *logm, uint64_t first_chain, bool mine,
                                 uint32_t chb, int words)
@@ -449,59 +541,58 @@ __device__ void z26_regrow_wide(const GrowArgs &a, const double *logm, uint64_t 
     if (n == 0) return;
     if (mine) z26_lds[1 + atomicAdd(&z26_lds[0], 1u)] = chb;
     const int N = a.n_monomers;
-    const int HW = z26_regrow_plane(N);
-    uint32_t *planes = z26_lds + kZ26ListWords;
-    const int room = (words - kZ26ListWords) / (2 * HW);
-    const int per_block = (int)blockDim.x / kZ26RegrowLanes;
+    const int room = (words - kZ26ListWords) / (2 * z26_regrow_plane(N));
+    const int per_block = (int)blockDim.x / z26_regrow_lanes(N);
     const int slots = room < per_block ? room : per_block; // >= 1: checked by the launch shape
-    const int gw = threadIdx.x / kZ26RegrowLanes;
-    for (int b0 = 0; b0 < n; b0 += slots) {
-        __syncthreads();
-        for (int w = threadIdx.x; w < slots * 2 * HW; w += blockDim.x)
-            planes[w] = ((w / HW) & 1) ? kZ26OriginB : 0u;
-        __syncthreads();
-        const bool v = gw < slots && b0 + gw < n;
-        const uint64_t c = first_chain + (v ? z26_lds[1 + b0 + gw] : 0u);
-        if (__ballot(v) != 0) // waves without such a chain skip the growth
-            z26_grow<kZ26RegrowLanes, false, CT, false>(a, logm, planes + (v ? gw : 0) * 2 * HW, HW, c, v, 0);
-    }
+    if (z26_regrow_lanes(N) == 8)
+        z26_regrow_passes<8, CT>(a, logm, first_chain, n, slots);
+    else
+        z26_regrow_passes<32, CT>(a, logm, first_chain, n, slots);
 }
 
-template <int G, bool EXACT, typename CT, bool BYTE>
+// Box edge of the byte (62) and packed (254) words; a launch's byte_box in
+// 1..127 lowers it (tests), 0 keeps it.
+__device__ __forceinline__ int z26_box(const GrowArgs &a, int natural)
+{
+    return (a.byte_box > 0 && a.byte_box < natural) ? a.byte_box : natural;
+}
+
+template <int G, bool EXACT, typename CT, int FMT>
 __device__ __forceinline__ void grow_lattice26_body(const GrowArgs &a, uint64_t bid, int H)
 {
-    constexpr int WPM = BYTE ? 1 : 2; // words per monomer
+    constexpr bool ONE = FMT != kZ26Wide;
+    constexpr int WPM = ONE ? 1 : 2; // words per monomer
     const int cpb = blockDim.x / G;
     extern __shared__ uint32_t z26_lds[];
     uint32_t *chains = z26_lds; // cpb chains of WPM H words
     __shared__ double logm[27];
     for (int q = threadIdx.x; q < 27; q += blockDim.x) logm[q] = a.logm[q];
     for (int w = threadIdx.x; w < cpb * WPM * H; w += blockDim.x)
-        chains[w] = BYTE ? kZ26Bias : (((w / H) & 1) ? kZ26OriginB : 0u);
+        chains[w] = FMT == kZ26Byte ? kZ26Bias
+                                    : (FMT == kZ26Packed ? kP32Sentinel : (((w / H) & 1) ? kZ26OriginB : 0u));
     __syncthreads();
 
     const int t = threadIdx.x & (G - 1);
     const int chb = threadIdx.x / G;
     const uint64_t c = bid * cpb + chb;
-    const int box = BYTE ? (a.byte_box < kZ26ByteEdge ? a.byte_box : kZ26ByteEdge) : 0;
-    const bool left =
-        z26_grow<G, EXACT, CT, BYTE>(a, logm, chains + chb * WPM * H, H, c, c < a.n_chains, box);
-    if constexpr (BYTE) z26_regrow_wide<CT>(a, logm, bid * cpb, left && t == 0, (uint32_t)chb, cpb * H);
+    const int box = FMT == kZ26Byte ? z26_box(a, kZ26ByteEdge) : (FMT == kZ26Packed ? z26_box(a, kZ26PackedEdge) : 0);
+    const bool left = z26_grow<G, EXACT, CT, FMT>(a, logm, chains + chb * WPM * H, H, c, c < a.n_chains, box);
+    if constexpr (ONE) z26_regrow_wide<CT>(a, logm, bid * cpb, left && t == 0, (uint32_t)chb, cpb * H);
 }
 
-template <int G, bool EXACT, typename CT, bool BYTE>
+template <int G, bool EXACT, typename CT, int FMT>
 __global__ __launch_bounds__(256) void grow_lattice26(GrowArgs a, int H, uint64_t base)
 {
-    grow_lattice26_body<G, EXACT, CT, BYTE>(a, base + blockIdx.x, H);
+    grow_lattice26_body<G, EXACT, CT, FMT>(a, base + blockIdx.x, H);
 }
 
-template <int G, bool EXACT, typename CT, bool BYTE>
+template <int G, bool EXACT, typename CT, int FMT>
 __global__ __launch_bounds__(256) void grow_lattice26_batch(const GrowEntry *tab, const uint64_t *block0, int n,
                                                             uint64_t base)
 {
     const uint64_t bid = base + blockIdx.x;
     const int e = find_segment(block0, n, bid);
-    grow_lattice26_body<G, EXACT, CT, BYTE>(tab[e].a, bid - block0[e], tab[e].H);
+    grow_lattice26_body<G, EXACT, CT, FMT>(tab[e].a, bid - block0[e], tab[e].H);
 }
 
 // Short chains (N <= 64): one lane per chain.  The lane's history sits in
@@ -705,19 +796,19 @@ int lattice26_max_monomers() { return 16384; }
 
 // Shape of the group kernel for N monomers, G lanes per chain and `threads`
 // per block in one word format.  hipErrorInvalidValue when the block's LDS
-// exceeds the CU's 160 KiB or, for byte words, holds no chain of the wide
-// regrowth.
-static hipError_t z26_shape_fmt(int N, bool i16, int G, int threads, bool byte, GrowVariant *v)
+// exceeds the CU's 160 KiB or, for byte and packed words, holds no chain of
+// the wide regrowth.
+static hipError_t z26_shape_fmt(int N, bool i16, int G, int threads, int fmt, GrowVariant *v)
 {
-    const int WPM = byte ? 1 : 2;
+    const int WPM = fmt == kZ26Wide ? 2 : 1;
     const int H = (N + 4 * G - 1) / (4 * G) * (4 * G);
     const int cpb = threads / G;
     const size_t words = (size_t)cpb * WPM * H;
     if (words * sizeof(uint32_t) > 163840) return hipErrorInvalidValue;
-    if (byte && (int)words - kZ26ListWords < 2 * z26_regrow_plane(N)) return hipErrorInvalidValue;
+    if (fmt != kZ26Wide && (int)words - kZ26ListWords < 2 * z26_regrow_plane(N)) return hipErrorInvalidValue;
     v->family = 3;
     v->p0 = G;
-    v->p1 = byte ? 1 : 0;
+    v->p1 = fmt;
     v->p2 = i16 ? 1 : 0;
     v->threads = threads;
     v->cpb = cpb;
@@ -729,17 +820,19 @@ static hipError_t z26_shape_fmt(int N, bool i16, int G, int threads, bool byte, 
 
 // Shape of the group kernel for a mapping: G lanes per chain (4: 8-bit n_m
 // fields, N <= 256; 8..64: 16-bit fields), `threads` per block (64 or 256);
-// byte words up to N = 640 where the block can host the regrowth, else wide
-// words.  For N <= 640 wide words always fit when byte words lack that room
-// (at most two chains per block), so a mapping legal at some N is legal at
-// every smaller N of the group kernel.
+// byte words up to N = 640 and packed words up to N = 4096 where the block
+// can host the regrowth, else wide words.  Up to N = 4096 wide words always
+// fit when the one-word formats lack that room (at most two chains per
+// block), so a mapping legal at some N is legal at every smaller N of the
+// group kernel.
 static hipError_t z26_shape(int N, bool i16, int G, int threads, GrowVariant *v)
 {
     if (G != 4 && G != 8 && G != 16 && G != 32 && G != 64) return hipErrorInvalidValue;
     if (threads != 64 && threads != 256) return hipErrorInvalidValue;
     if (G == 4 && N > 256) return hipErrorInvalidValue;
-    if (N <= kZ26ByteMaxN && z26_shape_fmt(N, i16, G, threads, true, v) == hipSuccess) return hipSuccess;
-    return z26_shape_fmt(N, i16, G, threads, false, v);
+    const int fmt = N <= kZ26ByteMaxN ? kZ26Byte : (N <= kZ26PackedMaxN ? kZ26Packed : kZ26Wide);
+    if (fmt != kZ26Wide && z26_shape_fmt(N, i16, G, threads, fmt, v) == hipSuccess) return hipSuccess;
+    return z26_shape_fmt(N, i16, G, threads, kZ26Wide, v);
 }
 
 // One lane per chain up to N = 64 (and for exact weights, N <= 14); above,
@@ -797,36 +890,41 @@ static hipError_t launch26_lane(const GrowArgs &a, const GrowVariant &v, const G
     });
 }
 
-template <int G, typename CT, bool BYTE>
+template <int G, typename CT, int FMT>
 static hipError_t launch26(const GrowArgs &a, const GrowVariant &v, const GrowEntry *tab, const uint64_t *block0,
                            int n, uint64_t blocks, size_t shmem, hipStream_t s)
 {
-    const void *fn = tab ? (const void *)grow_lattice26_batch<G, false, CT, BYTE>
-                         : (const void *)grow_lattice26<G, false, CT, BYTE>;
+    const void *fn = tab ? (const void *)grow_lattice26_batch<G, false, CT, FMT>
+                         : (const void *)grow_lattice26<G, false, CT, FMT>;
     if (shmem > 65536) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
         if (e != hipSuccess) return e;
     }
     return launch_sliced(blocks, v.threads, [&](uint64_t b0, uint32_t nb) {
         if (tab)
-            hipLaunchKernelGGL((grow_lattice26_batch<G, false, CT, BYTE>), dim3(nb), dim3(v.threads), shmem, s, tab,
+            hipLaunchKernelGGL((grow_lattice26_batch<G, false, CT, FMT>), dim3(nb), dim3(v.threads), shmem, s, tab,
                                block0, n, b0);
         else
-            hipLaunchKernelGGL((grow_lattice26<G, false, CT, BYTE>), dim3(nb), dim3(v.threads), shmem, s, a, v.H,
+            hipLaunchKernelGGL((grow_lattice26<G, false, CT, FMT>), dim3(nb), dim3(v.threads), shmem, s, a, v.H,
                                b0);
     });
+}
+
+template <int G, typename CT>
+static hipError_t launch26_ct(const GrowArgs &a, const GrowVariant &v, const GrowEntry *tab,
+                              const uint64_t *block0, int n, uint64_t blocks, size_t shmem, hipStream_t s)
+{
+    if (v.p1 == kZ26Byte) return launch26<G, CT, kZ26Byte>(a, v, tab, block0, n, blocks, shmem, s);
+    if (v.p1 == kZ26Packed) return launch26<G, CT, kZ26Packed>(a, v, tab, block0, n, blocks, shmem, s);
+    return launch26<G, CT, kZ26Wide>(a, v, tab, block0, n, blocks, shmem, s);
 }
 
 template <int G>
 static hipError_t launch26_g(const GrowArgs &a, const GrowVariant &v, const GrowEntry *tab, const uint64_t *block0,
                              int n, uint64_t blocks, size_t shmem, hipStream_t s)
 {
-    const bool i16 = v.p2 != 0;
-    if (v.p1)
-        return i16 ? launch26<G, int16_t, true>(a, v, tab, block0, n, blocks, shmem, s)
-                   : launch26<G, int32_t, true>(a, v, tab, block0, n, blocks, shmem, s);
-    return i16 ? launch26<G, int16_t, false>(a, v, tab, block0, n, blocks, shmem, s)
-               : launch26<G, int32_t, false>(a, v, tab, block0, n, blocks, shmem, s);
+    return v.p2 ? launch26_ct<G, int16_t>(a, v, tab, block0, n, blocks, shmem, s)
+                : launch26_ct<G, int32_t>(a, v, tab, block0, n, blocks, shmem, s);
 }
 
 static hipError_t dispatch26(const GrowArgs &a, const GrowVariant &v, const GrowEntry *tab, const uint64_t *block0,

@@ -83,8 +83,8 @@ __device__ __forceinline__ uint32_t pair_bits(uint32_t wa, uint32_t wb, uint32_t
 
 // Byte words hold each coordinate plus 128 in one byte.  Up to N = 128 no
 // coordinate can leave [-127, 127].  Longer chains ("boxed" byte words)
-// stop growing a chain whose new tip reaches |coordinate| = E (the launch's
-// byte_box, 127 unless a caller lowers it), before the byte test and the
+// stop growing a chain whose new tip reaches |coordinate| = E (127, or the
+// launch's byte_box when a caller lowers it), before the byte test and the
 // carry-free move could stop being exact at -128 and +128; the block then
 // grows that chain again from its first draw in wide words (the same draws
 // and the same tests give the same chain, Sec. 3.3.2), so every chain's
@@ -127,6 +127,7 @@ __device__ __forceinline__ bool lattice_lds_grow(const GrowArgs &a, const uint32
     const int t = threadIdx.x & (G - 1);
     const uint64_t g = a.chain_offset + c;
     const int N = a.n_monomers;
+    const int edge = a.byte_box > 0 ? a.byte_box : 127; // box of the byte words
 
     uint32_t ta = 0, tb = 0; // tip: A word (or the byte word) and B word (wide only)
     bool alive = false;
@@ -237,15 +238,16 @@ __device__ __forceinline__ bool lattice_lds_grow(const GrowArgs &a, const uint32
             } else {
                 const uint32_t mv = lut[li];
                 na = ((ta & 0xFFFFFF00u) + (mv & 0xFFFFFF00u)) | ((ta + mv) & 0xFFu);
-                // |coordinate| >= E = a.byte_box (possible from step E on):
+                // |coordinate| >= E (127, or the launch's byte_box if set;
+                // possible from step E on):
                 // the chain leaves the box here.  Coordinate bytes b = x + 128
                 // with b < 129 - E or 255 - b < 128 - E, as two byte-wise
                 // "has a byte below n" tests (exact for n <= 128) on the
                 // three bytes and on their complements.
-                if (boxed && i >= a.byte_box) {
+                if (boxed && i >= edge) {
                     const uint32_t v = na >> 8, w = v ^ 0xFFFFFFu;
-                    const uint32_t lo = (uint32_t)(129 - a.byte_box) * 0x010101u;
-                    const uint32_t hi = (uint32_t)(128 - a.byte_box) * 0x010101u;
+                    const uint32_t lo = (uint32_t)(129 - edge) * 0x010101u;
+                    const uint32_t hi = (uint32_t)(128 - edge) * 0x010101u;
                     const uint32_t edge = (((v - lo) & ~v) | ((w - hi) & ~w)) & 0x808080u;
                     if (step_ok && edge != 0u) {
                         step_ok = false;

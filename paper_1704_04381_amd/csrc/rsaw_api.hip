@@ -347,9 +347,9 @@ rsaw_chain_out bind_outputs(const rsaw_chain_out &in, const EnsLayout &L, char *
     return o;
 }
 
-// |coordinate| at which the boxed byte-word lattice kernels regrow a chain
-// in wide words (rsaw_set_byte_box).
-std::atomic<int32_t> g_byte_box{127};
+// |coordinate| at which the boxed lattice kernels regrow a chain in wide
+// words, 0 for each format's own edge (rsaw_set_byte_box).
+std::atomic<int32_t> g_byte_box{0};
 
 rsaw::GrowArgs grow_args(const rsaw_config *cfg, const rsaw_chain_out &o, const EnsLayout &L, char *ws)
 {
@@ -1160,7 +1160,7 @@ rsaw_status rsaw_mapping_set(const rsaw_mapping *m)
 
 rsaw_status rsaw_set_byte_box(int32_t edge)
 {
-    if (edge < 1 || edge > 127) return fail(RSAW_E_INVALID, "byte box edge must be in 1..127");
+    if (edge < 0 || edge > 127) return fail(RSAW_E_INVALID, "byte box edge must be in 0..127");
     g_byte_box.store(edge, std::memory_order_relaxed);
     return RSAW_OK;
 }

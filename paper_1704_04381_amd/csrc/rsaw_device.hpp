@@ -144,7 +144,7 @@ struct GrowArgs {
     double sigma2;
     double cull2; // (b + sigma)^2 (1 + 2^-30): beads at or beyond it cannot overlap
     uint32_t max_rounds; // growth attempts per chain: 1, or 65536 when a dead end restarts
-    int32_t byte_box;    // lattice byte words beyond N = 128: |coordinate| (1..127) at which a chain is regrown in wide words
+    int32_t byte_box;    // boxed lattice words: |coordinate| (1..127) at which a chain is regrown in wide words; 0: each format's own edge
     double *bead_slots;  // hard spheres beyond the LDS limit: n_slots regions of 3 N doubles (HBM)
     uint32_t n_slots;
     // per-chain outputs (device, any may be null)

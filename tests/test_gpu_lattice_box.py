@@ -9,7 +9,7 @@ than fit in one pass of the block's LDS and, at edge 1, every chain.  Every
 per-chain output and the summaries must still match the oracle bit for bit
 (Sec. 3.3.2; the oracle knows nothing of word formats).  The 26-neighbour
 group kernel keeps byte words up to N = 640 in a box of |coordinate| <= 61
-and regrows the same way.  GPU test; calls the HIP library through its C
+and packed words up to N = 4096 in a box of 253, and regrows the same way.  GPU test; calls the HIP library through its C
 ABI.
 """
 import numpy as np
@@ -27,7 +27,7 @@ pytestmark = pytest.mark.gpu
 @pytest.fixture(autouse=True)
 def _restore():
     yield
-    rs.set_byte_box(127)
+    rs.set_byte_box(0)
     rs.mapping_clear()
 
 
@@ -89,8 +89,9 @@ def test_regrown_chains_in_a_batch():
 
 
 # 26-neighbour lattice: byte words (x, y, z + 64, plus 128) in the group
-# kernel up to N = 640; a chain whose tip reaches |coordinate| = min(edge,
-# 62) is regrown in two-word format by its block.
+# kernel up to N = 640, packed 11/11/10-bit words up to N = 4096; a chain
+# whose tip reaches |coordinate| = the edge (62 or 254, lowered by the
+# knob) is regrown in two-word format by its block.
 @pytest.mark.parametrize("N,M,seed,coord,edge,mapping,offset,restart", [
     (200, 800, 91, "i16", 20, None, 0, False),
     # 4 lanes per chain (8-bit n_m fields), every chain regrown from step 1
@@ -103,6 +104,14 @@ def test_regrown_chains_in_a_batch():
     # four chains per one-wave block; one chain per block (wide words)
     (200, 300, 96, "i32", 20, (16, 64), 0, False),
     (200, 300, 97, "i16", 20, (64, 64), 0, False),
+    # packed 11/11/10-bit words (640 < N <= 4096), regrown with 32 lanes per
+    # chain; one chain per 64-thread block falls back to wide words
+    (700, 80, 102, "i16", 30, None, 0, False),
+    (1_000, 40, 103, "i32", 40, None, 0, True),
+    (2_048, 16, 104, "i16", 60, None, (1 << 32) + 5, False),
+    (4_096, 4, 105, "i32", 100, None, 0, False),
+    (1_000, 30, 106, "i32", 40, (64, 64), 0, False),
+    (900, 24, 107, "i16", 0, None, 0, False),
 ])
 def test_lattice26_regrown_chains_bit_exact(N, M, seed, coord, edge, mapping, offset, restart):
     from test_gpu_lattice26 import _case
@@ -113,7 +122,7 @@ def test_lattice26_regrown_chains_bit_exact(N, M, seed, coord, edge, mapping, of
         assert (q["lanes"], q["threads"]) == mapping
     out, _ = _case(N, M, seed, coord=coord, bins=64, offset=offset, restart=restart)
     reach = np.abs(out["r_end"].astype(np.int64)).max(axis=0)
-    assert (reach >= min(edge, 62)).sum() > 0 or offset
+    assert edge in (0, 127) or (reach >= min(edge, 62)).sum() > 0 or offset
 
 
 def test_lattice26_regrown_chains_in_a_batch():

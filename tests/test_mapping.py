@@ -132,10 +132,12 @@ def test_list_save_and_load_round_trip(tmp_path):
 
 
 def test_byte_box_edge_range():
-    # rsaw_set_byte_box: host-only; 1..127, anything else rejected
-    for bad in (0, -1, 128, 1 << 20):
+    # rsaw_set_byte_box: host-only; 0 (each format's own edge) or 1..127,
+    # anything else rejected
+    for bad in (-1, 128, 1 << 20):
         with pytest.raises(rs.RsawError) as e:
             rs.set_byte_box(bad)
         assert e.value.status == 1  # RSAW_E_INVALID
     rs.set_byte_box(1)
     rs.set_byte_box(127)
+    rs.set_byte_box(0)
