@@ -35,6 +35,13 @@ WORKLOADS = {
                            coord="i16", exact_w=False, hist_bins=0),
     "lattice26_n2048": dict(geometry="lattice26", N=2048, k=26, n_chains=100_000, seed=1,
                             coord="i16", exact_w=False, hist_bins=0),
+    # Long hard-sphere chains, k = 8, b = sigma = 1: N = 256 (bead planes in
+    # LDS, 32 lanes per chain; 2 10^5 chains) and N = 3000 (bead planes in
+    # HBM, one chain per wave of the persistent grid; 3 10^3 chains).
+    "real_n256": dict(geometry="real", N=256, k=8, n_chains=200_000, seed=1,
+                      coord="f64", bond_length=1.0, bead_diameter=1.0, hist_bins=0),
+    "real_n3000": dict(geometry="real", N=3000, k=8, n_chains=3_000, seed=1,
+                       coord="f64", bond_length=1.0, bead_diameter=1.0, hist_bins=0),
 }
 
 
