@@ -578,7 +578,7 @@ def main():
                          "the FETCH_SIZE / WRITE_SIZE counters of a profiler run")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only: this build has no multi-GPU path "
+        print(f"bench.py measures one GPU only: the library has no multi-GPU path "
               f"(asked for --gpus {args.gpus}); the chain ranges would shard by chain_offset "
               f"with no data exchange beyond the ensemble partials.", file=sys.stderr)
         sys.exit(2)

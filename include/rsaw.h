@@ -48,7 +48,7 @@ extern "C" {
 typedef enum {
     RSAW_OK = 0,
     RSAW_E_INVALID = 1,     /* bad argument (see rsaw_last_error)                 */
-    RSAW_E_UNSUPPORTED = 2, /* valid request this build has no kernel for         */
+    RSAW_E_UNSUPPORTED = 2, /* valid request the library has no kernel for       */
     RSAW_E_OVERFLOW = 3,    /* exact 64-bit weight requested beyond its N limit   */
     RSAW_E_NOMEM = 4,       /* device allocation of the workspace failed          */
     RSAW_E_DEVICE = 5,      /* a HIP runtime call failed                          */

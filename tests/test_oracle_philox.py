@@ -3,7 +3,7 @@ installed implementations (rocRAND's engine header and PyTorch's
 PhiloxRNGEngine header), both called from small host programs.
 
 The method itself needs only independent uniform streams per thread (paper
-Sec. 3.2); the counter-based generator is this build's choice, so it is
+Sec. 3.2); the counter-based generator is this library's choice, so it is
 pinned to the published generator rather than to anything in the paper.
 """
 import subprocess
