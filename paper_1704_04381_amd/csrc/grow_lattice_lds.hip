@@ -13,11 +13,12 @@
 // needs no bounds test and H is the half length rounded up to 4 G.
 //
 // Monomer words.
-//   byte format (N <= 128, coordinates within [-127, 127]): as in the
-//     register kernel, (Q mod 256, x + 128, y + 128, z + 128); pair test
-//     L = msad(r_j, tip & ~0xFF), bit = sat(2 - L), code = (r_j - tip + 3)
-//     mod 32 from the Q byte, 4 operations.
-//   wide format (N <= 16384): A = (x + 2^15) | (y + 2^15) << 16 and
+//   byte format (N <= 2048; coordinates within [-127, 127], exact by
+//     construction up to N = 128, kept by the box and the regrowth below
+//     beyond): as in the register kernel, (Q mod 256, x + 128, y + 128,
+//     z + 128); pair test L = msad(r_j, tip & ~0xFF), bit = sat(2 - L),
+//     code = (r_j - tip + 3) mod 32 from the Q byte, 4 operations.
+//   wide format (N > 2048, and the regrowth): A = (x + 2^15) | (y + 2^15) << 16 and
 //     B = (64 + Q mod 32) | (z + 2^15) << 16; pair test
 //     L = sad_u16(A_j, A_t) + sad_u16(B_j & 0xFFFF0000, B_t & 0xFFFF0000),
 //     bit = sat(2 - L), code = (B_j - B_t + 3) mod 32, 6 operations.  A move
