@@ -4,12 +4,15 @@
 // 9 (dz + 1) (13, the tip itself, excluded); the growth rule and weight are
 // those of Algorithm 1 and Eq. 3 with m_i <= 26.
 //
-// Chains beyond N = 64: G lanes per chain (8 to 64, by N), the history in
-// LDS as two words per monomer, A = (x + 2^15) | (y + 2^15) << 16 and
-// B = z + 2^15, in two planes of H words (monomer order; no bipartite
-// pruning on this lattice: a diagonal step keeps the parity).  Entries not
-// yet placed hold A = 0 (x = y = -2^15, far from every tip) and B = 2^15.
-// Pair test of monomer j against tip t:
+// Chains beyond N = 64: G lanes per chain (4 to 64, by N), the history in
+// LDS in monomer order (no bipartite pruning on this lattice: a diagonal
+// step keeps the parity).  Up to N = 640 one byte word per monomer and up
+// to N = 4096 one packed word, each with a box and a regrowth of the chains
+// that leave it (both described further down); beyond, and for the
+// regrowth, two words per monomer ("wide"), A = (x + 2^15) | (y + 2^15)
+// << 16 and B = z + 2^15, in two planes of H words.  Entries not yet placed
+// hold A = 0 (x = y = -2^15, far from every tip) and B = 2^15.
+// Wide pair test of monomer j against tip t:
 //   (dx, dy) as packed 16-bit differences of the A words, dz = B_j - B_t
 //   q  = dx^2 + dy^2 + dz^2          (dot2 onto a 24-bit product)
 //   s  = |dx| + |dy| + |dz|          (two chained sad_u16 operations)
