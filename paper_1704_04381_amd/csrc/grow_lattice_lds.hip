@@ -276,6 +276,13 @@ __device__ __forceinline__ bool lattice_lds_grow(const GrowArgs &a, const uint32
                 }
             }
             lattice_wave_sync();
+            // one chain per wave: once it has ended (a third of N = 3000 chains
+            // meet a dead end, two thirds of N = 5000 ones), the wave leaves
+            // the step loop instead of scanning on (N = 5000, 2 10^4 chains:
+            // 94.2 -> 62.4 ms; N = 10000, 5 10^3 chains: 188.7 -> 79.0 ms)
+            if constexpr (G == 64) {
+                if (__ballot(alive) == 0) break;
+            }
         }
         if (alive) grown = N;
         // log W = sum over m = 1..6, ascending, of n_m log m; n_1 log 1 = 0 and
