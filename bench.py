@@ -139,11 +139,12 @@ def path_model(w) -> dict:
     geo, N, M = w["geometry"], w["N"], w["n_chains"]
     if geo == "lattice":
         reg = N <= 64 or w.get("exact_w", False)
-        return dict(kernel="grow_lattice_reg" if reg else "grow_lattice_lds",
-                    kernel_file="grow_lattice.hip" if reg else "grow_lattice_lds.hip",
+        grp = not reg and 128 < N <= 2048  # history in the group's VGPRs (built-in lane rule)
+        kernel = "grow_lattice_reg" if reg else ("grow_lattice_grp" if grp else "grow_lattice_lds")
+        return dict(kernel=kernel, kernel_file="grow_lattice.hip" if reg else "grow_lattice_lds.hip",
                     ops=lattice_alg_ops_per_chain(N) * M, peak=VALU_PEAK_INT32_TOPS, int_path=True,
-                    lds_bytes=0.0 if reg else lattice_lds_bytes_per_chain(N) * M,
-                    lds_note=("chain history in VGPRs: no LDS traffic" if reg else
+                    lds_bytes=0.0 if reg or grp else lattice_lds_bytes_per_chain(N) * M,
+                    lds_note=("chain history in VGPRs: no LDS traffic" if reg or grp else
                               "parity-plane words of the neighbour candidates read once per step"))
     if geo == "lattice26":
         lane = N <= 64
@@ -160,10 +161,11 @@ def path_model(w) -> dict:
 
 
 def lattice_lds_bytes_per_chain(N: int) -> int:
-    """Algorithmic LDS bytes of one long lattice chain (one 4-byte word per
-    monomer up to N = 512, two beyond): per step i the floor(i/2) monomers of
-    the tip's opposite parity are read once, and the new monomer is written."""
-    w = 4 if N <= 512 else 8
+    """Algorithmic LDS bytes of one long lattice chain in LDS (one 4-byte
+    word per monomer up to N = 2048, two beyond): per step i the floor(i/2)
+    monomers of the tip's opposite parity are read once, and the new monomer
+    is written."""
+    w = 4 if N <= 2048 else 8
     return sum(w * (i // 2) + w for i in range(1, N))
 
 

@@ -1,16 +1,26 @@
-// Lattice chain growth for chains too long to keep in registers (N > 64):
-// the same growth rule as the register kernel (Sec. 3.3.2, Algorithm 1;
-// weight of Eq. 3) with the chain history in LDS and G lanes per chain.
+// Lattice chain growth for chains too long to keep in one lane's registers
+// (N > 64): the same growth rule as the register kernel (Sec. 3.3.2,
+// Algorithm 1; weight of Eq. 3) with G lanes per chain.  Two kernels share
+// the step: one keeps the chain history in the group's VGPRs (byte words,
+// 128 < N <= 64 G), the other in LDS (any N to 16384).
 //
-// Layout.  Each chain owns S words of LDS: two parity planes (monomers of
-// even and odd index) of H words each, times one (byte format) or two (wide
-// format) words per monomer.  On the bipartite cubic lattice the monomers
-// that can neighbour the tip at step i are those of index i - 2, i - 4, ...,
-// i.e. the first floor(i / 2) entries of the plane of parity i, so the scan
-// reads one contiguous run.  Lane t of the chain's group reads 4 consecutive
-// words (one b128 load) per pass, the group 4 G words.  Entries not yet
-// placed hold 0, a sentinel that is never adjacent to any tip, so the scan
-// needs no bounds test and H is the half length rounded up to 4 G.
+// On the bipartite cubic lattice the monomers that can neighbour the tip at
+// step i are those of index i - 2, i - 4, ..., i.e. the first floor(i / 2)
+// entries of the plane of parity i (monomers of even, or odd, index), so
+// both kernels keep two parity planes and scan one run of one of them.
+// Entries not yet placed hold 0, a sentinel that is never adjacent to any
+// tip, so a scan may run past the chain's last entry without a bounds test.
+//
+// Registers.  Entry k of a plane sits in lane k mod G of the group, slot
+// k / G of that lane's 32-slot array (64 VGPRs for both planes).  A step
+// tests the slots that hold entries, four at a time behind one wave-uniform
+// count test, and appends the new monomer with one indexed register read
+// and write (uniform slot; the lane holding it takes the new word).
+//
+// LDS.  Each chain owns S words: two planes of H words each, times one
+// (byte format) or two (wide format) words per monomer.  Lane t of the
+// chain's group reads 4 consecutive words (one b128 load) per pass, the
+// group 4 G words, and H is the half length rounded up to 4 G.
 //
 // Monomer words.
 //   byte format (N <= 2048; coordinates within [-127, 127], exact by
@@ -28,7 +38,7 @@
 // Per step the G partial occupancy masks are OR-reduced across the group
 // (cross-lane DPP and permute operations, no LDS round trip);
 // every lane of the group then performs the same pick (same Philox words),
-// and lane 0 appends the new monomer to its parity plane.
+// and the lane that holds the new entry appends it to its parity plane.
 #include "lattice_common.hpp"
 
 namespace rsaw {
@@ -435,6 +445,230 @@ __device__ void regrow_wide(const GrowArgs &a, uint64_t first_chain, bool mine, 
         regrow_passes<32, CT>(a, first_chain, n, slots, planes);
 }
 
+// Register-resident byte words (128 < N <= 64 G, G <= 32), the layout of
+// the file header.  Against the LDS kernel (same lanes, 10^5 to 10^6
+// chains, MI355X) the step loses its scan loads and their round trips, and
+// the block's LDS shrinks to the move table and the regrowth, so the kernel
+// runs at 3 waves per SIMD (168 VGPRs) where the LDS kernel ran at 2 to 3:
+// N = 160, 2.09 -> 1.86 ms; N = 256, 4.95 -> 3.49 ms; N = 384, 13.5 ->
+// 9.2 ms; N = 512, 19.9 -> 13.7 ms; N = 2048, 35.0 -> 26.1 ms,
+// bit-identical.  Up to N = 128 the LDS kernel's chains are short enough
+// for 4 waves per SIMD, and it stays (N = 80: 0.83 against 0.86 ms).
+// Unbounded, the compiler takes 186 VGPRs (2 waves per SIMD: 4.20 ms at
+// N = 256); at 4 waves it spills in the step loop.
+constexpr int kGrpSlots = 32; // slots per lane and plane
+
+template <int G, typename CT>
+__device__ __forceinline__ bool lattice_grp_grow(const GrowArgs &a, const uint32_t *lut, uint64_t c, bool valid)
+{
+    constexpr int SL = kGrpSlots;
+    const int t = threadIdx.x & (G - 1);
+    const uint64_t g = a.chain_offset + c;
+    const int N = a.n_monomers;
+    const bool boxed = N > kByteExactN;
+    const int edge = a.byte_box > 0 ? a.byte_box : 127; // box of the byte words
+
+    uint32_t pe[SL], po[SL]; // planes of even and odd monomers
+#pragma unroll
+    for (int s = 0; s < SL; ++s) pe[s] = po[s] = 0u;
+    uint32_t ta = 0;
+    bool alive = false;
+    bool left_box = false;
+    int grown = 1;
+    uint64_t cnt = 0; // n_m in 12-bit fields at 12 (m - 1), m = 1..6
+    bool rng_fail = false;
+    Philox4 blk{0, 0, 0, 0};
+    double res_lw = -__builtin_huge_val();
+    int64_t res_nn = 0;
+    int32_t res_ex = 0, res_ey = 0, res_ez = 0;
+    int res_grown = 1;
+    bool res_alive = false;
+    bool res_set = false;
+    bool pending = valid;
+
+    for (uint32_t rd = 0; rd < a.max_rounds; ++rd) {
+        if (rd > 0) {
+#pragma unroll
+            for (int s = 0; s < SL; ++s) {
+                pe[s] = pending ? 0u : pe[s];
+                po[s] = pending ? 0u : po[s];
+            }
+        }
+        if (pending) {
+            ta = kByteOrigin;
+            cnt = 0;
+        }
+        pe[0] = (pending && t == 0) ? kByteOrigin : pe[0];
+        alive = pending;
+        grown = 1;
+        const uint32_t hi = rd << 16;
+
+        const auto step = [&](int i, uint32_t(&pl)[SL]) {
+            const int ns = ((i >> 1) + G - 1) / G; // slots holding entries of plane i mod 2
+            const uint32_t tref = ta & 0xFFFFFF00u;
+            const uint32_t tq = ta - 3u;
+            uint32_t occ = 0, occ2 = 0;
+#pragma unroll
+            for (int q = 0; q < SL / 4; ++q) {
+                if (4 * q >= ns) break;
+                occ |= pair_bits<false>(pl[4 * q], 0u, tref, 0u, tq);
+                occ2 |= pair_bits<false>(pl[4 * q + 1], 0u, tref, 0u, tq);
+                occ |= pair_bits<false>(pl[4 * q + 2], 0u, tref, 0u, tq);
+                occ2 |= pair_bits<false>(pl[4 * q + 3], 0u, tref, 0u, tq);
+            }
+            occ |= occ2;
+            occ = group_or<G>(occ);
+            const uint32_t freem = ~occ & 0x77u;
+            const uint32_t m = __builtin_popcount(freem);
+
+            if (i == 1 || (i & 7) == 0) blk = draw(a.seed, g, (uint32_t)(i >> 3) | hi, kSlotSelect, 0);
+            const uint32_t x = half_word(blk, (uint32_t)(i & 7));
+            const uint32_t p = x * m;
+            uint32_t r = p >> 16;
+            if (__builtin_expect(alive && (p & 0xFFFFu) < m, 0)) {
+                r = lemire_redraw16(a.seed, g, (uint32_t)i | hi, m, x);
+                if (r == kPickFailed) {
+                    rng_fail = true;
+                    r = 0;
+                }
+            }
+
+            bool step_ok = alive && m != 0;
+            const uint32_t mv = lut[(freem << 3) | r];
+            const uint32_t na = ((ta & 0xFFFFFF00u) + (mv & 0xFFFFFF00u)) | ((ta + mv) & 0xFFu);
+            if (boxed && i >= edge) {
+                const uint32_t v = na >> 8, w = v ^ 0xFFFFFFu;
+                const uint32_t lo = (uint32_t)(129 - edge) * 0x010101u;
+                const uint32_t hb = (uint32_t)(128 - edge) * 0x010101u;
+                const bool out = ((((v - lo) & ~v) | ((w - hb) & ~w)) & 0x808080u) != 0u;
+                left_box = left_box || (step_ok && out);
+                alive = alive && !(step_ok && out);
+                step_ok = step_ok && !out;
+            }
+            grown = (alive && m == 0) ? i : grown;
+            alive = alive && m != 0;
+            ta = step_ok ? na : ta;
+            cnt += step_ok ? (1ull << (12u * (m - 1u))) : 0ull;
+            const int k = i >> 1;
+            const uint32_t old = pl[k / G];
+            pl[k / G] = (step_ok && t == (k & (G - 1))) ? na : old;
+        };
+        for (int i = 1; i < N; i += 2) {
+            step(i, po);
+            if (i + 1 < N) step(i + 1, pe);
+        }
+        if (alive) grown = N;
+        double lw = 0.0;
+        if (N >= 2) {
+            lw = lw + (double)(uint32_t)((cnt >> 12) & 0xFFFu) * a.logm[2];
+            lw = lw + (double)(uint32_t)((cnt >> 24) & 0xFFFu) * a.logm[3];
+            lw = lw + (double)(uint32_t)((cnt >> 36) & 0xFFFu) * a.logm[4];
+            lw = lw + (double)(uint32_t)((cnt >> 48) & 0xFFFu) * a.logm[5];
+            lw = lw + a.logm[6];
+        }
+
+        // observables over the placed monomers (the non-zero words; integer
+        // sums: any order)
+        int32_t sx = 0, sy = 0, sz = 0;
+        int64_t s2 = 0;
+        const auto add = [&](uint32_t w) {
+            const int32_t x = w ? (int32_t)((w >> 8) & 0xFFu) - 128 : 0;
+            const int32_t y = w ? (int32_t)((w >> 16) & 0xFFu) - 128 : 0;
+            const int32_t z = w ? (int32_t)(w >> 24) - 128 : 0;
+            sx += x;
+            sy += y;
+            sz += z;
+            s2 += (int64_t)(x * x + y * y + z * z);
+        };
+#pragma unroll
+        for (int s = 0; s < SL; ++s) {
+            add(pe[s]);
+            add(po[s]);
+        }
+#pragma unroll
+        for (int off = 1; off < G; off <<= 1) {
+            sx += __shfl_xor(sx, off, 64);
+            sy += __shfl_xor(sy, off, 64);
+            sz += __shfl_xor(sz, off, 64);
+            const int lo = __shfl_xor((int)(uint32_t)s2, off, 64);
+            const int hi2 = __shfl_xor((int)(uint32_t)((uint64_t)s2 >> 32), off, 64);
+            s2 += (int64_t)(((uint64_t)(uint32_t)hi2 << 32) | (uint32_t)lo);
+        }
+        const int64_t gg = grown;
+        const int64_t nn = gg * s2 - ((int64_t)sx * sx + (int64_t)sy * sy + (int64_t)sz * sz);
+        const int32_t ex = (int32_t)((ta >> 8) & 0xFFu) - 128;
+        const int32_t ey = (int32_t)((ta >> 16) & 0xFFu) - 128;
+        const int32_t ez = (int32_t)(ta >> 24) - 128;
+        if (pending && left_box) {
+            pending = false; // grown again in wide words
+        } else if (pending && (alive || rd + 1 >= a.max_rounds)) {
+            res_lw = alive ? lw : -__builtin_huge_val();
+            res_nn = nn;
+            res_ex = ex;
+            res_ey = ey;
+            res_ez = ez;
+            res_grown = grown;
+            res_alive = alive;
+            res_set = true;
+            pending = false;
+        }
+        if (__ballot(pending) == 0) break;
+    }
+
+    if (res_set && t == 0) {
+        if (a.log_w) a.log_w[c] = res_lw;
+        if (a.r_end) {
+            CT *re = (CT *)a.r_end;
+            re[c] = (CT)res_ex;
+            re[a.n_chains + c] = (CT)res_ey;
+            re[2 * a.n_chains + c] = (CT)res_ez;
+        }
+        if (a.r2) a.r2[c] = (double)((int64_t)res_ex * res_ex + (int64_t)res_ey * res_ey + (int64_t)res_ez * res_ez);
+        if (a.n2rg2) a.n2rg2[c] = res_nn;
+        if (a.rg2) a.rg2[c] = (double)res_nn / ((double)res_grown * (double)res_grown);
+        if (a.n_grown) a.n_grown[c] = (uint16_t)res_grown;
+    }
+    if (rng_fail && !left_box) atomicExch(a.status, 6);
+    const uint64_t bits = (res_alive && t == 0) ? (uint64_t)__double_as_longlong(res_lw) : 0ull;
+    const uint64_t wmax = wave_max_u64(bits);
+    if ((threadIdx.x & 63) == 0 && wmax != 0) atomicMax(a.log_w_max_bits, (unsigned long long)wmax);
+    return left_box;
+}
+
+// One block: the move table, each group's chain, then the regrowth of the
+// block's chains that left the byte box, in the block's `words` of LDS.
+template <int G, typename CT>
+__device__ __forceinline__ void grow_lattice_grp_body(const GrowArgs &a, uint64_t bid, int words)
+{
+    const int cpb = blockDim.x / G;
+    extern __shared__ uint32_t lds_u[];
+    lattice_lds_luts(lds_u, nullptr, false);
+    __syncthreads();
+    const int t = threadIdx.x & (G - 1);
+    const int chb = threadIdx.x / G;
+    const uint64_t c = bid * cpb + chb;
+    const bool left = lattice_grp_grow<G, CT>(a, lds_u, c, c < a.n_chains);
+    if (a.n_monomers > kByteExactN) regrow_wide<CT>(a, bid * cpb, left && t == 0, (uint32_t)chb, words);
+}
+
+// At least 3 waves per SIMD: the register budget of 168 VGPRs.
+template <int G, typename CT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void
+grow_lattice_grp(GrowArgs a, int words, uint64_t base)
+{
+    grow_lattice_grp_body<G, CT>(a, base + blockIdx.x, words);
+}
+
+// Batched launch: block b serves the ensemble whose block range holds b.
+template <int G, typename CT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void
+grow_lattice_grp_batch(const GrowEntry *tab, const uint64_t *block0, int n, uint64_t base)
+{
+    const uint64_t bid = base + blockIdx.x;
+    const int e = find_segment(block0, n, bid);
+    grow_lattice_grp_body<G, CT>(tab[e].a, bid - block0[e], tab[e].S);
+}
+
 template <int G, bool WIDE, typename CT>
 __device__ __forceinline__ void grow_lattice_lds_body(const GrowArgs &a, uint64_t bid, int H, int S)
 {
@@ -478,12 +712,32 @@ __global__ __launch_bounds__(256) void grow_lattice_lds_batch(const GrowEntry *t
 // Largest lattice chain of the LDS kernel (wide words: 128 KiB per chain).
 int lattice_lds_max_monomers() { return 16384; }
 
-// Shape of the LDS kernel for N monomers, G lanes per chain and `threads`
-// per block (64 or 256) in one word format.  hipErrorInvalidValue when the
+// Shape of a lattice group kernel for N monomers, G lanes per chain and
+// `threads` per block (64 or 256) in one word format: byte words (in the
+// group's registers where 128 < N <= 64 G and G <= 32, format 2, else in
+// LDS, format 0) or wide words (LDS, format 1).  hipErrorInvalidValue when the
 // block's LDS exceeds the CU's 160 KiB or, for boxed byte words, holds no
 // chain of the wide regrowth.
 static hipError_t lds_shape_fmt(int N, bool i16, int G, int threads, bool wide, GrowVariant *v)
 {
+    if (!wide && N > kByteExactN && N <= 2 * kGrpSlots * G && G <= 32) {
+        // registers: LDS for the move table and the regrowth of up to four
+        // chains at a time (fewer where they would pass 40 KiB)
+        int room = 4;
+        while (room > 1 && (kRegrowListWords + room * regrow_stride(N)) * 4 > 40960) --room;
+        int words = kRegrowListWords + room * regrow_stride(N);
+        if (words < kLutSize) words = kLutSize;
+        v->family = 1;
+        v->p0 = G;
+        v->p1 = 2;
+        v->p2 = i16 ? 1 : 0;
+        v->threads = threads;
+        v->cpb = threads / G;
+        v->shmem = (size_t)words * sizeof(uint32_t);
+        v->H = 0;
+        v->S = words;
+        return hipSuccess;
+    }
     const int WPM = wide ? 2 : 1;
     const int half = (N + 1) / 2;
     const int H = (half + 4 * G - 1) / (4 * G) * (4 * G);
@@ -520,8 +774,10 @@ static hipError_t lds_shape(int N, bool i16, int G, int threads, GrowVariant *v)
 }
 
 // Variant for 64 < N <= 16384.  Built-in rule (measured on MI355X, 10^5 to
-// 10^6 chains): byte words with 4 lanes per chain up to N = 256, 8 up to
-// N = 512, 16 up to 1024 and 32 up to 2048; wide words beyond, 32 lanes in
+// 10^6 chains): byte words with 4 lanes per chain up to N = 256 (in LDS to
+// N = 128, in the group's registers beyond), 8 up to N = 512, 16 up to 1024
+// and 32 up to 2048 (registers: the fewest lanes whose 32 slots hold a
+// plane); wide words beyond, 32 lanes in
 // 256-thread blocks while eight chains fit in a CU's LDS, else 64 lanes.
 // Four or more waves per block share the move table when the block fits in
 // half a CU's LDS.  A legal mapping of the tuning table replaces the rule.
@@ -543,6 +799,24 @@ hipError_t lattice_lds_variant(const GrowArgs &a, bool i16, GrowVariant *v)
         return hipSuccess;
     }
     return lds_shape(N, i16, G, 64, v);
+}
+
+template <int G, typename CT>
+static hipError_t launch_grp(const GrowArgs &a, const GrowVariant &v, const GrowEntry *tab,
+                             const uint64_t *block0, int n, uint64_t blocks, size_t shmem, hipStream_t s)
+{
+    const void *fn = tab ? (const void *)grow_lattice_grp_batch<G, CT> : (const void *)grow_lattice_grp<G, CT>;
+    if (shmem > 65536) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+        if (e != hipSuccess) return e;
+    }
+    return launch_sliced(blocks, v.threads, [&](uint64_t b0, uint32_t nb) {
+        if (tab)
+            hipLaunchKernelGGL((grow_lattice_grp_batch<G, CT>), dim3(nb), dim3(v.threads), shmem, s, tab, block0,
+                               n, b0);
+        else
+            hipLaunchKernelGGL((grow_lattice_grp<G, CT>), dim3(nb), dim3(v.threads), shmem, s, a, v.S, b0);
+    });
 }
 
 template <int G, bool WIDE, typename CT>
@@ -572,6 +846,18 @@ static hipError_t dispatch_lds(const GrowArgs &a, const GrowVariant &v, const Gr
 #define RSAW_LDS(G, W)                                                                                \
     return i16 ? launch_lds<G, W, int16_t>(a, v, tab, block0, n, blocks, shmem, s)                    \
                : launch_lds<G, W, int32_t>(a, v, tab, block0, n, blocks, shmem, s)
+#define RSAW_GRP(G)                                                                                   \
+    return i16 ? launch_grp<G, int16_t>(a, v, tab, block0, n, blocks, shmem, s)                       \
+               : launch_grp<G, int32_t>(a, v, tab, block0, n, blocks, shmem, s)
+    if (v.p1 == 2) {
+        switch (v.p0) {
+        case 4: RSAW_GRP(4);
+        case 8: RSAW_GRP(8);
+        case 16: RSAW_GRP(16);
+        default: RSAW_GRP(32);
+        }
+    }
+#undef RSAW_GRP
     switch (v.p0) {
     case 4: RSAW_LDS(4, false);
     case 8:

@@ -1,16 +1,18 @@
 """Boxed byte words of the long-chain lattice kernels against the oracle.
 
-Beyond N = 128 the simple cubic LDS kernel keeps one byte per coordinate
-up to N = 2048 and regrows, in two-word format, any chain whose tip reaches
-|coordinate| = edge (rsaw_set_byte_box; 127 by default, when no sampled
-chain of these sizes gets there).  Lowering the edge sends many chains of
-every block through that regrowth, including blocks with more such chains
-than fit in one pass of the block's LDS and, at edge 1, every chain.  Every
-per-chain output and the summaries must still match the oracle bit for bit
-(Sec. 3.3.2; the oracle knows nothing of word formats).  The 26-neighbour
-group kernel keeps byte words up to N = 640 in a box of |coordinate| <= 61
-and packed words up to N = 4096 in a box of 253, and regrows the same way.  GPU test; calls the HIP library through its C
-ABI.
+Beyond N = 128 the simple cubic group kernels keep one byte per coordinate
+up to N = 2048 (in the group's registers, or in LDS for mappings whose
+lanes cannot hold a plane) and regrow, in two-word format in LDS, any chain
+whose tip reaches |coordinate| = edge (rsaw_set_byte_box; 127 by default,
+when no sampled chain of these sizes gets there).  Lowering the edge sends
+many chains of every block through that regrowth, including blocks with
+more such chains than fit in one pass of the block's LDS and, at edge 1,
+every chain.  Every per-chain output and the summaries must still match
+the oracle bit for bit (Sec. 3.3.2; the oracle knows nothing of word
+formats).  The 26-neighbour group kernel keeps byte words up to N = 640 in
+a box of |coordinate| <= 61 and packed words up to N = 4096 in a box of
+253, and regrows the same way.  GPU test; calls the HIP library through
+its C ABI.
 """
 import numpy as np
 import pytest
@@ -43,7 +45,8 @@ def _restore():
     (512, 300, 74, "i32", 40, None, 0, False),
     # dead ends restarted, and regrown chains among them
     (400, 500, 76, "i32", 25, None, 0, True),
-    # other legal mappings: 8 lanes in one-wave blocks, 4 lanes in one-wave blocks
+    # other legal mappings: 8 lanes in one-wave blocks (registers), 4 lanes
+    # in one-wave blocks (N > 256: byte words in LDS)
     (200, 700, 77, "i16", 20, (8, 64), 0, False),
     (300, 500, 78, "i32", 30, (4, 64), 0, False),
     # chain offset past 2^32

@@ -104,13 +104,15 @@ def test_lattice_bit_exact(N, M, seed, coord):
 
 
 @pytest.mark.parametrize("N,M,seed,coord", [
-    # LDS kernel: byte words with 4 lanes per chain (N <= 128), wide words with
-    # 8 (N <= 256; one and two scan passes of 32 entries around N = 256), 16
-    # (N <= 512), 32 (N <= 2048) and 64 lanes per chain, up to the largest N
+    # group kernels: byte words with 4 lanes per chain (N <= 128 in LDS; to
+    # 256 boxed, in the group's registers), 8 (N <= 512), 16 (N <= 1024) and
+    # 32 (N <= 2048; each lane's last slot at the top of each range), then
+    # wide words in LDS with 32 and 64 lanes per chain, up to the largest N
     (65, 3_001, 21, "i16"), (100, 1_500, 22, "i32"), (128, 2_000, 23, "i16"),
     (129, 801, 24, "i32"), (256, 2_000, 41, "i16"), (257, 700, 42, "i32"),
     (300, 333, 25, "i16"), (512, 300, 26, "i32"),
-    (513, 200, 27, "i16"), (2_048, 60, 28, "i32"), (2_049, 40, 29, "i16"),
+    (513, 200, 27, "i16"), (1_024, 100, 32, "i16"), (1_025, 80, 33, "i32"),
+    (2_048, 60, 28, "i32"), (2_049, 40, 29, "i16"),
     (5_000, 12, 30, "i32"), (16_384, 3, 31, "i16")])
 def test_lattice_long_chains_bit_exact(N, M, seed, coord):
     _lattice_case(N, M, seed, coord=coord, bins=256)
