@@ -148,11 +148,12 @@ def path_model(w) -> dict:
                               "parity-plane words of the neighbour candidates read once per step"))
     if geo == "lattice26":
         lane = N <= 64
-        return dict(kernel="grow_lattice26_lane" if lane else "grow_lattice26",
+        grp = not lane and N <= 4096  # one-word formats in the group's VGPRs (built-in lane rule)
+        return dict(kernel="grow_lattice26_lane" if lane else ("grow_lattice26_grp" if grp else "grow_lattice26"),
                     kernel_file="grow_lattice26.hip",
                     ops=lattice26_alg_ops_per_chain(N) * M, peak=VALU_PEAK_INT32_TOPS, int_path=True,
-                    lds_bytes=lattice26_lds_bytes_per_chain(N) * M * (1 if lane else 2),
-                    lds_note="monomer words read once per step")
+                    lds_bytes=0.0 if grp else lattice26_lds_bytes_per_chain(N) * M * (1 if lane else 2),
+                    lds_note="chain history in VGPRs: no LDS traffic" if grp else "monomer words read once per step")
     hbm = N > 1536
     return dict(kernel="grow_real_hbm" if hbm else "grow_real_tp", kernel_file="grow_real.hip",
                 ops=real_alg_ops_per_chain(N, w["k"]) * M, peak=VALU_PEAK_FP64_TOPS, int_path=False,

@@ -5,13 +5,15 @@
 // those of Algorithm 1 and Eq. 3 with m_i <= 26.
 //
 // Chains beyond N = 64: G lanes per chain (4 to 64, by N), the history in
-// LDS in monomer order (no bipartite pruning on this lattice: a diagonal
-// step keeps the parity).  Up to N = 640 one byte word per monomer and up
-// to N = 4096 one packed word, each with a box and a regrowth of the chains
-// that leave it (both described further down); beyond, and for the
-// regrowth, two words per monomer ("wide"), A = (x + 2^15) | (y + 2^15)
-// << 16 and B = z + 2^15, in two planes of H words.  Entries not yet placed
-// hold A = 0 (x = y = -2^15, far from every tip) and B = 2^15.
+// monomer order (no bipartite pruning on this lattice: a diagonal step
+// keeps the parity).  Up to N = 640 one byte word per monomer and up to
+// N = 4096 one packed word, each with a box and a regrowth of the chains
+// that leave it (both described further down), held in the group's
+// registers where its lanes' 64 slots hold the chain (N <= 64 G), else in
+// LDS; beyond, and for the regrowth, two words per monomer ("wide") in LDS,
+// A = (x + 2^15) | (y + 2^15) << 16 and B = z + 2^15, in two planes of H
+// words.  Entries not yet placed hold A = 0 (x = y = -2^15, far from every
+// tip) and B = 2^15.
 // Wide pair test of monomer j against tip t:
 //   (dx, dy) as packed 16-bit differences of the A words, dz = B_j - B_t
 //   q  = dx^2 + dy^2 + dz^2          (dot2 onto a 24-bit product)
@@ -508,6 +510,239 @@ __device__ __forceinline__ bool z26_grow(const GrowArgs &a, const double *logm, 
     return left_box;
 }
 
+// Register-resident one-word formats (byte or packed words, N <= 64 G):
+// entry j (monomer j) of the chain sits in lane j mod G of its group, slot
+// j / G of a 64-slot array.  A step tests the slots that can hold monomers
+// 0 .. i - 2, four at a time behind one wave-uniform count test (slots past
+// them hold the tip, code 13, masked, or the sentinel), and appends the new
+// word with one indexed register read and write (uniform slot; the lane that
+// holds entry i takes it).  Against the same mapping with the words in LDS
+// (MI355X, kernel time, bit-identical): N = 100, 2.57 -> 2.07 ms; N = 256,
+// 15.2 -> 8.27 ms; N = 640, 35.8 -> 25.8 ms; N = 2048, 49.4 -> 35.9 ms;
+// N = 4000, 81.0 -> 51.0 ms.  The step loses its scan loads and their
+// round trips, and the kernel runs at 3 waves per SIMD (168 VGPRs; the
+// compiler spills a few values outside the step loop) where the LDS kernel
+// ran at 2; unbounded it takes 192 VGPRs and runs 10-40 % slower.
+constexpr int kZ26Slots = 64;
+
+template <int G, typename CT, int FMT>
+__device__ __forceinline__ bool z26_grp_grow(const GrowArgs &a, const double *logm, uint64_t c, bool valid, int box)
+{
+    constexpr int SL = kZ26Slots;
+    constexpr bool BYTE = FMT == kZ26Byte;
+    constexpr uint32_t SENT = BYTE ? kZ26Bias : kP32Sentinel;
+    const int t = threadIdx.x & (G - 1);
+    const int lane = threadIdx.x & 63;
+    const int gbase = lane & ~(G - 1);
+    const uint64_t g = a.chain_offset + c;
+    const int N = a.n_monomers;
+
+    // slots 0-31 and 32-63 as two arrays (each indexed append stays in
+    // registers)
+    uint32_t pl[SL / 2], ph[SL / 2];
+#pragma unroll
+    for (int s = 0; s < SL / 2; ++s) pl[s] = ph[s] = SENT;
+    uint32_t ta = 0;
+    bool alive = false;
+    bool left_box = false;
+    int grown = 1;
+    constexpr uint32_t FW = G >= 8 ? 16u : 8u;
+    uint64_t n_mine = 0;
+    bool rng_fail = false;
+    Philox4 blk{0, 0, 0, 0};
+    double res_lw = -__builtin_huge_val();
+    int64_t res_nn = 0;
+    int32_t res_ex = 0, res_ey = 0, res_ez = 0;
+    int res_grown = 1;
+    bool res_alive = false;
+    bool res_set = false;
+    bool pending = valid;
+
+    for (uint32_t rd = 0; rd < a.max_rounds; ++rd) {
+        if (rd > 0) {
+#pragma unroll
+            for (int s = 0; s < SL / 2; ++s) {
+                pl[s] = pending ? SENT : pl[s];
+                ph[s] = pending ? SENT : ph[s];
+            }
+        }
+        if (pending) {
+            ta = BYTE ? kZ26LaneOrigin : kP32Origin;
+            n_mine = 0;
+        }
+        pl[0] = (pending && t == 0) ? (BYTE ? kZ26LaneOrigin + kZ26Bias : kP32Origin) : pl[0];
+        alive = pending;
+        grown = 1;
+        const uint32_t hi = rd << 16;
+
+        for (int i = 1; i < N; ++i) {
+            const int ns = (i - 1 + G - 1) / G; // slots that can hold monomers 0 .. i - 2
+            uint32_t occ = 0, occ2 = 0;
+            const uint32_t tp = BYTE ? ta + 0x7F7F7Fu : ta - kP32One;
+            const auto test4 = [&](uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3) {
+                if constexpr (BYTE) {
+                    occ |= z26_bits8(w0, tp);
+                    occ2 |= z26_bits8(w1, tp);
+                    occ |= z26_bits8(w2, tp);
+                    occ2 |= z26_bits8(w3, tp);
+                } else {
+                    occ |= z26_bits32(w0, tp);
+                    occ2 |= z26_bits32(w1, tp);
+                    occ |= z26_bits32(w2, tp);
+                    occ2 |= z26_bits32(w3, tp);
+                }
+            };
+#pragma unroll
+            for (int q = 0; q < SL / 4; ++q) {
+                if (4 * q >= ns) break;
+                if (q < SL / 8)
+                    test4(pl[4 * q], pl[4 * q + 1], pl[4 * q + 2], pl[4 * q + 3]);
+                else
+                    test4(ph[4 * q - SL / 2], ph[4 * q + 1 - SL / 2], ph[4 * q + 2 - SL / 2], ph[4 * q + 3 - SL / 2]);
+            }
+            occ = z26_group_or<G>(occ | occ2);
+            const uint32_t freem = ~occ & kZ26Codes;
+            const uint32_t m = __builtin_popcount(freem);
+
+            if (i == 1 || (i & 7) == 0) blk = draw(a.seed, g, (uint32_t)(i >> 3) | hi, kSlotSelect, 0);
+            const uint32_t x = half_word(blk, (uint32_t)(i & 7));
+            const uint32_t p = x * m;
+            uint32_t r = p >> 16;
+            if (__builtin_expect(alive && (p & 0xFFFFu) < m, 0)) {
+                r = lemire_redraw16_inline(a.seed, g, (uint32_t)i | hi, m, x);
+                if (r == kPickFailed) {
+                    rng_fail = true;
+                    r = 0;
+                }
+            }
+            const uint32_t code = m ? z26_select_bits(freem, r) : 13u;
+
+            bool step_ok = alive && m != 0;
+            grown = (alive && m == 0) ? i : grown;
+            alive = alive && m != 0;
+            const uint32_t na =
+                BYTE ? ta + z26_move_bytes(code) - 0x010101u : ta + z26_move_packed(code) - kP32One;
+            if (box > 0 && i >= box) {
+                bool out;
+                if constexpr (BYTE) {
+                    const uint32_t v = na, w = 0x7F7F7Fu - na;
+                    const uint32_t lo = (uint32_t)(65 - box) * 0x010101u, hb = (uint32_t)(64 - box) * 0x010101u;
+                    out = ((((v - lo) & ~v) | ((w - hb) & ~w)) & 0x808080u) != 0u;
+                } else {
+                    const int ex = (int)(na & 0x7FFu) - 1024, ey = (int)((na >> 11) & 0x7FFu) - 1024,
+                              ez = (int)(na >> 22) - 512;
+                    const uint32_t span = 2u * (uint32_t)box - 2u;
+                    out = (uint32_t)(ex + box - 1) > span || (uint32_t)(ey + box - 1) > span ||
+                          (uint32_t)(ez + box - 1) > span;
+                }
+                left_box = left_box || (step_ok && out);
+                alive = alive && !(step_ok && out);
+                step_ok = step_ok && !out;
+            }
+            ta = step_ok ? na : ta;
+            const uint32_t mm1 = m - 1u;
+            n_mine += (step_ok && (mm1 & (G - 1)) == (uint32_t)t) ? 1ull << (FW * (mm1 / G)) : 0ull;
+            const bool mine = step_ok && t == (i & (G - 1));
+            const uint32_t nw = BYTE ? na + kZ26Bias : na;
+            const int slot = i / G;
+            if (slot < SL / 2) {
+                const uint32_t old = pl[slot];
+                pl[slot] = mine ? nw : old;
+            } else {
+                const uint32_t old = ph[slot - SL / 2];
+                ph[slot - SL / 2] = mine ? nw : old;
+            }
+        }
+        if (alive) grown = N;
+
+        double lw = 0.0;
+#pragma unroll 1
+        for (int mm = 1; mm <= 26; ++mm) {
+            const int f = (mm - 1) / G;
+            const int per = 32 / (int)FW;
+            const uint32_t half = (uint32_t)(n_mine >> (32 * (f / per)));
+            const uint32_t v = (uint32_t)__shfl((int)half, gbase + ((mm - 1) & (G - 1)), 64);
+            const uint32_t nm = (v >> (FW * (uint32_t)(f % per))) & ((1u << FW) - 1u);
+            lw = lw + (double)nm * logm[mm];
+        }
+        // observables over the placed monomers (the slots off the sentinel;
+        // integer sums: any order)
+        int32_t sx = 0, sy = 0, sz = 0;
+        int64_t s2 = 0;
+#pragma unroll
+        for (int s = 0; s < SL; ++s) {
+            const uint32_t w = s < SL / 2 ? pl[s] : ph[s - SL / 2];
+            const bool placed = w != SENT;
+            int32_t xx, yy, zz;
+            if constexpr (BYTE) {
+                xx = (int32_t)(w & 0xFFu) - 192;
+                yy = (int32_t)((w >> 8) & 0xFFu) - 192;
+                zz = (int32_t)((w >> 16) & 0xFFu) - 192;
+            } else {
+                xx = (int32_t)(w & 0x7FFu) - 1024;
+                yy = (int32_t)((w >> 11) & 0x7FFu) - 1024;
+                zz = (int32_t)(w >> 22) - 512;
+            }
+            xx = placed ? xx : 0;
+            yy = placed ? yy : 0;
+            zz = placed ? zz : 0;
+            sx += xx;
+            sy += yy;
+            sz += zz;
+            s2 += (int64_t)(xx * xx + yy * yy + zz * zz);
+        }
+#pragma unroll
+        for (int off = 1; off < G; off <<= 1) {
+            sx += __shfl_xor(sx, off, 64);
+            sy += __shfl_xor(sy, off, 64);
+            sz += __shfl_xor(sz, off, 64);
+            const int lo = __shfl_xor((int)(uint32_t)s2, off, 64);
+            const int hh = __shfl_xor((int)(uint32_t)((uint64_t)s2 >> 32), off, 64);
+            s2 += (int64_t)(((uint64_t)(uint32_t)hh << 32) | (uint32_t)lo);
+        }
+        if (pending && left_box) {
+            pending = false; // grown again in wide words
+        } else if (pending && (alive || rd + 1 >= a.max_rounds)) {
+            const int64_t gg = grown;
+            res_nn = gg * s2 - ((int64_t)sx * sx + (int64_t)sy * sy + (int64_t)sz * sz);
+            if constexpr (BYTE) {
+                res_ex = (int32_t)(ta & 0xFFu) - 64;
+                res_ey = (int32_t)((ta >> 8) & 0xFFu) - 64;
+                res_ez = (int32_t)((ta >> 16) & 0xFFu) - 64;
+            } else {
+                res_ex = (int32_t)(ta & 0x7FFu) - 1024;
+                res_ey = (int32_t)((ta >> 11) & 0x7FFu) - 1024;
+                res_ez = (int32_t)(ta >> 22) - 512;
+            }
+            res_lw = alive ? lw : -__builtin_huge_val();
+            res_grown = grown;
+            res_alive = alive;
+            res_set = true;
+            pending = false;
+        }
+        if (__ballot(pending) == 0) break;
+    }
+
+    if (res_set && t == 0) {
+        if (a.log_w) a.log_w[c] = res_lw;
+        if (a.r_end) {
+            CT *re = (CT *)a.r_end;
+            re[c] = (CT)res_ex;
+            re[a.n_chains + c] = (CT)res_ey;
+            re[2 * a.n_chains + c] = (CT)res_ez;
+        }
+        if (a.r2) a.r2[c] = (double)((int64_t)res_ex * res_ex + (int64_t)res_ey * res_ey + (int64_t)res_ez * res_ez);
+        if (a.n2rg2) a.n2rg2[c] = res_nn;
+        if (a.rg2) a.rg2[c] = (double)res_nn / ((double)res_grown * (double)res_grown);
+        if (a.n_grown) a.n_grown[c] = (uint16_t)res_grown;
+    }
+    if (rng_fail && !left_box) atomicExch(a.status, 6);
+    const uint64_t bits = (res_alive && t == 0) ? (uint64_t)__double_as_longlong(res_lw) : 0ull;
+    const uint64_t wmax = wave_max_u64(bits);
+    if ((threadIdx.x & 63) == 0 && wmax != 0) atomicMax(a.log_w_max_bits, (unsigned long long)wmax);
+    return left_box;
+}
+
 // Passes of the wide regrowth with GW lanes per chain: `slots` chains at a
 // time from the list at z26_lds[1..n].
 template <int GW, typename CT>
@@ -596,6 +831,41 @@ __global__ __launch_bounds__(256) void grow_lattice26_batch(const GrowEntry *tab
     const uint64_t bid = base + blockIdx.x;
     const int e = find_segment(block0, n, bid);
     grow_lattice26_body<G, EXACT, CT, FMT>(tab[e].a, bid - block0[e], tab[e].H);
+}
+
+// Register formats: one block grows its chains with their words in the
+// groups' registers, then regrows the chains that left the box in wide
+// words in its `words` of LDS.
+template <int G, typename CT, int FMT>
+__device__ __forceinline__ void grow_lattice26_grp_body(const GrowArgs &a, uint64_t bid, int words)
+{
+    const int cpb = blockDim.x / G;
+    __shared__ double logm[27];
+    for (int q = threadIdx.x; q < 27; q += blockDim.x) logm[q] = a.logm[q];
+    __syncthreads();
+    const int t = threadIdx.x & (G - 1);
+    const int chb = threadIdx.x / G;
+    const uint64_t c = bid * cpb + chb;
+    const int box = FMT == kZ26Byte ? z26_box(a, kZ26ByteEdge) : z26_box(a, kZ26PackedEdge);
+    const bool left = z26_grp_grow<G, CT, FMT>(a, logm, c, c < a.n_chains, box);
+    z26_regrow_wide<CT>(a, logm, bid * cpb, left && t == 0, (uint32_t)chb, words);
+}
+
+// At least 3 waves per SIMD: the register budget of 168 VGPRs.
+template <int G, typename CT, int FMT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void
+grow_lattice26_grp(GrowArgs a, int words, uint64_t base)
+{
+    grow_lattice26_grp_body<G, CT, FMT>(a, base + blockIdx.x, words);
+}
+
+template <int G, typename CT, int FMT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void
+grow_lattice26_grp_batch(const GrowEntry *tab, const uint64_t *block0, int n, uint64_t base)
+{
+    const uint64_t bid = base + blockIdx.x;
+    const int e = find_segment(block0, n, bid);
+    grow_lattice26_grp_body<G, CT, FMT>(tab[e].a, bid - block0[e], tab[e].S);
 }
 
 // Short chains (N <= 64): one lane per chain.  The lane's history sits in
@@ -823,8 +1093,9 @@ static hipError_t z26_shape_fmt(int N, bool i16, int G, int threads, int fmt, Gr
 
 // Shape of the group kernel for a mapping: G lanes per chain (4: 8-bit n_m
 // fields, N <= 256; 8..64: 16-bit fields), `threads` per block (64 or 256);
-// byte words up to N = 640 and packed words up to N = 4096 where the block
-// can host the regrowth, else wide words.  Up to N = 4096 wide words always
+// byte words up to N = 640 and packed words up to N = 4096, in the group's
+// registers where N <= 64 G (formats 3 and 4; LDS for the regrowth only),
+// else in LDS where the block can host the regrowth; else wide words.  Up to N = 4096 wide words always
 // fit when the one-word formats lack that room (at most two chains per
 // block), so a mapping legal at some N is legal at every smaller N of the
 // group kernel.
@@ -834,16 +1105,32 @@ static hipError_t z26_shape(int N, bool i16, int G, int threads, GrowVariant *v)
     if (threads != 64 && threads != 256) return hipErrorInvalidValue;
     if (G == 4 && N > 256) return hipErrorInvalidValue;
     const int fmt = N <= kZ26ByteMaxN ? kZ26Byte : (N <= kZ26PackedMaxN ? kZ26Packed : kZ26Wide);
+    if (fmt != kZ26Wide && N <= kZ26Slots * G) {
+        // registers: LDS for the regrowth of up to four chains at a time
+        // (fewer where they would pass 40 KiB)
+        int room = 4;
+        while (room > 1 && (kZ26ListWords + room * 2 * z26_regrow_plane(N)) * 4 > 40960) --room;
+        v->family = 3;
+        v->p0 = G;
+        v->p1 = fmt + 2; // 3: byte words, 4: packed words, in registers
+        v->p2 = i16 ? 1 : 0;
+        v->threads = threads;
+        v->cpb = threads / G;
+        v->S = kZ26ListWords + room * 2 * z26_regrow_plane(N);
+        v->shmem = (size_t)v->S * sizeof(uint32_t);
+        v->H = 0;
+        return hipSuccess;
+    }
     if (fmt != kZ26Wide && z26_shape_fmt(N, i16, G, threads, fmt, v) == hipSuccess) return hipSuccess;
     return z26_shape_fmt(N, i16, G, threads, kZ26Wide, v);
 }
 
 // One lane per chain up to N = 64 (and for exact weights, N <= 14); above,
-// G lanes per chain.  Built-in rule: G grows with N so that the chains a
-// CU's LDS holds still fill the CU (measured best widths, byte words up to
-// N = 640): 4 up to N = 256 (whose 8-bit n_m fields need N <= 256), 8 up to
-// 384, 16 up to 768, 32 up to 1536, 64 beyond; 256-thread blocks when the
-// block's planes fit in half a CU's LDS, else one wave.  A legal mapping of the tuning table replaces
+// G lanes per chain.  Built-in rule: G grows with N (the widths measured
+// best when the words sat in LDS): 4 up to N = 256 (whose 8-bit n_m fields
+// need N <= 256), 8 up to 384, 16 up to 768, 32 up to 1536, 64 beyond, so
+// every chain up to N = 4096 keeps its words in registers; 256-thread
+// blocks when the block's LDS fits in half a CU's, else one wave.  A legal mapping of the tuning table replaces
 // the rule for the group kernel.
 hipError_t lattice26_variant(const GrowArgs &a, bool exact, bool i16, GrowVariant *v)
 {
@@ -913,10 +1200,31 @@ static hipError_t launch26(const GrowArgs &a, const GrowVariant &v, const GrowEn
     });
 }
 
+template <int G, typename CT, int FMT>
+static hipError_t launch26_grp(const GrowArgs &a, const GrowVariant &v, const GrowEntry *tab,
+                               const uint64_t *block0, int n, uint64_t blocks, size_t shmem, hipStream_t s)
+{
+    const void *fn = tab ? (const void *)grow_lattice26_grp_batch<G, CT, FMT>
+                         : (const void *)grow_lattice26_grp<G, CT, FMT>;
+    if (shmem > 65536) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+        if (e != hipSuccess) return e;
+    }
+    return launch_sliced(blocks, v.threads, [&](uint64_t b0, uint32_t nb) {
+        if (tab)
+            hipLaunchKernelGGL((grow_lattice26_grp_batch<G, CT, FMT>), dim3(nb), dim3(v.threads), shmem, s, tab,
+                               block0, n, b0);
+        else
+            hipLaunchKernelGGL((grow_lattice26_grp<G, CT, FMT>), dim3(nb), dim3(v.threads), shmem, s, a, v.S, b0);
+    });
+}
+
 template <int G, typename CT>
 static hipError_t launch26_ct(const GrowArgs &a, const GrowVariant &v, const GrowEntry *tab,
                               const uint64_t *block0, int n, uint64_t blocks, size_t shmem, hipStream_t s)
 {
+    if (v.p1 == kZ26Byte + 2) return launch26_grp<G, CT, kZ26Byte>(a, v, tab, block0, n, blocks, shmem, s);
+    if (v.p1 == kZ26Packed + 2) return launch26_grp<G, CT, kZ26Packed>(a, v, tab, block0, n, blocks, shmem, s);
     if (v.p1 == kZ26Byte) return launch26<G, CT, kZ26Byte>(a, v, tab, block0, n, blocks, shmem, s);
     if (v.p1 == kZ26Packed) return launch26<G, CT, kZ26Packed>(a, v, tab, block0, n, blocks, shmem, s);
     return launch26<G, CT, kZ26Wide>(a, v, tab, block0, n, blocks, shmem, s);

@@ -92,7 +92,8 @@ def test_regrown_chains_in_a_batch():
 
 
 # 26-neighbour lattice: byte words (x, y, z + 64, plus 128) in the group
-# kernel up to N = 640, packed 11/11/10-bit words up to N = 4096; a chain
+# kernel up to N = 640, packed 11/11/10-bit words up to N = 4096 (in the
+# group's registers where its lanes hold the chain, else in LDS); a chain
 # whose tip reaches |coordinate| = the edge (62 or 254, lowered by the
 # knob) is regrown in two-word format by its block.
 @pytest.mark.parametrize("N,M,seed,coord,edge,mapping,offset,restart", [
@@ -104,17 +105,21 @@ def test_regrown_chains_in_a_batch():
     (640, 60, 95, "i16", 40, None, 0, False),
     # the production edge: chain 11031 of seed 1 (N = 256) reaches x = 63
     (256, 300, 1, "i16", 127, None, 11_000, False),
-    # four chains per one-wave block; one chain per block (wide words)
+    # four chains per one-wave block; one chain per block
     (200, 300, 96, "i32", 20, (16, 64), 0, False),
     (200, 300, 97, "i16", 20, (64, 64), 0, False),
     # packed 11/11/10-bit words (640 < N <= 4096), regrown with 32 lanes per
-    # chain; one chain per 64-thread block falls back to wide words
+    # chain; one chain per 64-thread block
     (700, 80, 102, "i16", 30, None, 0, False),
     (1_000, 40, 103, "i32", 40, None, 0, True),
     (2_048, 16, 104, "i16", 60, None, (1 << 32) + 5, False),
     (4_096, 4, 105, "i32", 100, None, 0, False),
     (1_000, 30, 106, "i32", 40, (64, 64), 0, False),
     (900, 24, 107, "i16", 0, None, 0, False),
+    # words in LDS: mappings whose lanes cannot hold the chain (N > 64 G),
+    # byte words with 8 lanes, packed words with 16
+    (600, 60, 108, "i32", 30, (8, 256), 0, False),
+    (1_100, 20, 109, "i16", 40, (16, 256), 0, True),
 ])
 def test_lattice26_regrown_chains_bit_exact(N, M, seed, coord, edge, mapping, offset, restart):
     from test_gpu_lattice26 import _case

@@ -61,6 +61,9 @@ CASES = [
     ("lattice26", 26, 65, 2_000, dict(coord="i16")),
     ("lattice26", 26, 256, 600, dict(coord="i32")),
     ("lattice26", 26, 400, 300, dict(coord="i16")),
+    # 8 lanes hold at most N = 512 in registers: LDS byte words beside
+    # register words of 16 to 64 lanes
+    ("lattice26", 26, 600, 120, dict(coord="i32")),
 ]
 
 
