@@ -2,7 +2,7 @@
 // (N > 64): the same growth rule as the register kernel (Sec. 3.3.2,
 // Algorithm 1; weight of Eq. 3) with G lanes per chain.  Two kernels share
 // the step: one keeps the chain history in the group's VGPRs (byte words,
-// 128 < N <= 64 G), the other in LDS (any N to 16384).
+// 128 < N <= 64 G, so N <= 4096), the other in LDS (any N to 16384).
 //
 // On the bipartite cubic lattice the monomers that can neighbour the tip at
 // step i are those of index i - 2, i - 4, ..., i.e. the first floor(i / 2)
@@ -23,12 +23,12 @@
 // group 4 G words, and H is the half length rounded up to 4 G.
 //
 // Monomer words.
-//   byte format (N <= 2048; coordinates within [-127, 127], exact by
-//     construction up to N = 128, kept by the box and the regrowth below
-//     beyond): as in the register kernel, (Q mod 256, x + 128, y + 128,
+//   byte format (N <= 2048 in LDS, N <= 4096 in registers; coordinates
+//     within [-127, 127], exact by construction up to N = 128, kept by the
+//     box and the regrowth below beyond): as in the register kernel, (Q mod 256, x + 128, y + 128,
 //     z + 128); pair test L = msad(r_j, tip & ~0xFF), bit = sat(2 - L),
 //     code = (r_j - tip + 3) mod 32 from the Q byte, 4 operations.
-//   wide format (N > 2048, and the regrowth): A = (x + 2^15) | (y + 2^15) << 16 and
+//   wide format (LDS beyond, and the regrowth): A = (x + 2^15) | (y + 2^15) << 16 and
 //     B = (64 + Q mod 32) | (z + 2^15) << 16; pair test
 //     L = sad_u16(A_j, A_t) + sad_u16(B_j & 0xFFFF0000, B_t & 0xFFFF0000),
 //     bit = sat(2 - L), code = (B_j - B_t + 3) mod 32, 6 operations.  A move
@@ -445,15 +445,20 @@ __device__ void regrow_wide(const GrowArgs &a, uint64_t first_chain, bool mine, 
         regrow_passes<32, CT>(a, first_chain, n, slots, planes);
 }
 
-// Register-resident byte words (128 < N <= 64 G, G <= 32), the layout of
+// Register-resident byte words (128 < N <= 64 G), the layout of
 // the file header.  Against the LDS kernel (same lanes, 10^5 to 10^6
 // chains, MI355X) the step loses its scan loads and their round trips, and
 // the block's LDS shrinks to the move table and the regrowth, so the kernel
 // runs at 3 waves per SIMD (168 VGPRs) where the LDS kernel ran at 2 to 3:
 // N = 160, 2.09 -> 1.86 ms; N = 256, 4.95 -> 3.49 ms; N = 384, 13.5 ->
 // 9.2 ms; N = 512, 19.9 -> 13.7 ms; N = 2048, 35.0 -> 26.1 ms,
-// bit-identical.  Up to N = 128 the LDS kernel's chains are short enough
-// for 4 waves per SIMD, and it stays (N = 80: 0.83 against 0.86 ms).
+// bit-identical.  With 64 lanes (one chain per wave, which leaves the step
+// loop once its chain has ended) against wide words in LDS: N = 2049,
+// 32.5 -> 20.4 ms; N = 3000, 43.1 -> 23.5 ms; N = 4096, 57.9 -> 45.5 ms
+// (3 10^4 chains; 10^4 chains, 21.3 -> 22.9 ms: 3.5 % of N = 4096
+// chains leave the box and are regrown).  Up to N = 128 the LDS kernel's
+// chains are short enough for 4 waves per SIMD, and it stays (N = 80:
+// 0.83 against 0.86 ms).
 // Unbounded, the compiler takes 186 VGPRs (2 waves per SIMD: 4.20 ms at
 // N = 256); at 4 waves it spills in the step loop.
 constexpr int kGrpSlots = 32; // slots per lane and plane
@@ -556,6 +561,10 @@ __device__ __forceinline__ bool lattice_grp_grow(const GrowArgs &a, const uint32
         for (int i = 1; i < N; i += 2) {
             step(i, po);
             if (i + 1 < N) step(i + 1, pe);
+            // one chain per wave: the wave leaves once its chain has ended
+            if constexpr (G == 64) {
+                if (__ballot(alive) == 0) break;
+            }
         }
         if (alive) grown = N;
         double lw = 0.0;
@@ -714,13 +723,13 @@ int lattice_lds_max_monomers() { return 16384; }
 
 // Shape of a lattice group kernel for N monomers, G lanes per chain and
 // `threads` per block (64 or 256) in one word format: byte words (in the
-// group's registers where 128 < N <= 64 G and G <= 32, format 2, else in
-// LDS, format 0) or wide words (LDS, format 1).  hipErrorInvalidValue when the
+// group's registers where 128 < N <= 64 G, format 2, else in LDS up to
+// N = 2048, format 0) or wide words (LDS, format 1).  hipErrorInvalidValue when the
 // block's LDS exceeds the CU's 160 KiB or, for boxed byte words, holds no
 // chain of the wide regrowth.
 static hipError_t lds_shape_fmt(int N, bool i16, int G, int threads, bool wide, GrowVariant *v)
 {
-    if (!wide && N > kByteExactN && N <= 2 * kGrpSlots * G && G <= 32) {
+    if (!wide && N > kByteExactN && N <= 2 * kGrpSlots * G) {
         // registers: LDS for the move table and the regrowth of up to four
         // chains at a time (fewer where they would pass 40 KiB)
         int room = 4;
@@ -759,26 +768,29 @@ static hipError_t lds_shape_fmt(int N, bool i16, int G, int threads, bool wide, 
     return hipSuccess;
 }
 
-// Shape for a mapping: byte words up to N = 2048 (boxed beyond N = 128)
-// where the block can host the regrowth, else wide words (G >= 8).  Byte
-// words need less LDS than wide ones, and their regrowth room does not grow
-// back as N shrinks, so a mapping legal at some N is legal at every smaller
-// N of the kernel.
+// Shape for a mapping: byte words (boxed beyond N = 128) in the group's
+// registers for 128 < N <= 64 G, else in LDS up to N = 2048 where the block
+// can host the regrowth, else wide words (G >= 8).  Byte words need less
+// LDS than wide ones, and their regrowth room does not grow back as N
+// shrinks, so a mapping legal at some N is legal at every smaller N of the
+// kernel.
 static hipError_t lds_shape(int N, bool i16, int G, int threads, GrowVariant *v)
 {
     if (G != 4 && G != 8 && G != 16 && G != 32 && G != 64) return hipErrorInvalidValue;
     if (threads != 64 && threads != 256) return hipErrorInvalidValue;
-    if (N <= kByteBoxedMaxN && lds_shape_fmt(N, i16, G, threads, false, v) == hipSuccess) return hipSuccess;
+    if ((N <= kByteBoxedMaxN || (N > kByteExactN && N <= 2 * kGrpSlots * G)) &&
+        lds_shape_fmt(N, i16, G, threads, false, v) == hipSuccess)
+        return hipSuccess;
     if (G == 4) return hipErrorInvalidValue;
     return lds_shape_fmt(N, i16, G, threads, true, v);
 }
 
-// Variant for 64 < N <= 16384.  Built-in rule (measured on MI355X, 10^5 to
+// Variant for 64 < N <= 16384.  Built-in rule (measured on MI355X, 10^4 to
 // 10^6 chains): byte words with 4 lanes per chain up to N = 256 (in LDS to
-// N = 128, in the group's registers beyond), 8 up to N = 512, 16 up to 1024
-// and 32 up to 2048 (registers: the fewest lanes whose 32 slots hold a
-// plane); wide words beyond, 32 lanes in
-// 256-thread blocks while eight chains fit in a CU's LDS, else 64 lanes.
+// N = 128, in the group's registers beyond), 8 up to N = 512, 16 up to
+// 1024, 32 up to 2048 and 64 up to 4096 (registers: the fewest lanes whose
+// 32 slots hold a plane); wide words beyond, 32 lanes in 256-thread blocks
+// while eight chains fit in a CU's LDS, else 64 lanes.
 // Four or more waves per block share the move table when the block fits in
 // half a CU's LDS.  A legal mapping of the tuning table replaces the rule.
 hipError_t lattice_lds_variant(const GrowArgs &a, bool i16, GrowVariant *v)
@@ -789,10 +801,10 @@ hipError_t lattice_lds_variant(const GrowArgs &a, bool i16, GrowVariant *v)
         lds_shape(N, i16, tl, tt, v) == hipSuccess)
         return hipSuccess;
     const int G = N <= 256 ? 4 : (N <= 512 ? 8 : (N <= 1024 ? 16 : (N <= 2048 ? 32 : 64)));
-    // wide words just past N = 2048: eight chains of 32 lanes in one
-    // 256-thread block per CU while they fit (N = 2200: 37.8 against 49.2 ms
-    // for one-chain blocks of 64 lanes, 5 * 10^4 chains)
-    if (N > kByteBoxedMaxN && lds_shape(N, i16, 32, 256, v) == hipSuccess) return hipSuccess;
+    // wide words past N = 4096: eight chains of 32 lanes in one 256-thread
+    // block per CU while they fit (N = 2200, before the registers took
+    // N <= 4096: 37.8 against 49.2 ms for one-chain blocks of 64 lanes)
+    if (N > 2 * kGrpSlots * 64 && lds_shape(N, i16, 32, 256, v) == hipSuccess) return hipSuccess;
     GrowVariant half_cu;
     if (lds_shape(N, i16, G, 256, &half_cu) == hipSuccess && half_cu.shmem <= 81920) {
         *v = half_cu;
@@ -854,7 +866,8 @@ static hipError_t dispatch_lds(const GrowArgs &a, const GrowVariant &v, const Gr
         case 4: RSAW_GRP(4);
         case 8: RSAW_GRP(8);
         case 16: RSAW_GRP(16);
-        default: RSAW_GRP(32);
+        case 32: RSAW_GRP(32);
+        default: RSAW_GRP(64);
         }
     }
 #undef RSAW_GRP

@@ -58,10 +58,20 @@ def _check_summary(s, ref, M, exact_ref=None):
     for key in SUM_KEYS:
         a, b = s[key], ref[key]
         assert abs(a - b) <= RTOL_SUM * abs(b), (key, a, b)
-    for key in ("r2_err", "rg2_err", "c_rel_err"):
+    b = ref["c_rel_err"]
+    if math.isfinite(b):
+        assert abs(s["c_rel_err"] - b) <= 1e-6 * abs(b) + 1e-300, ("c_rel_err", s["c_rel_err"], b)
+    # std. error of <A> (Eq. 2): sqrt(|S_w2A2 - 2 <A> S_w2A + <A>^2 S2|) / S0
+    # on both sides.  The three terms agree to RTOL_SUM, but they cancel when
+    # a few chains carry the weight, so the square under the root is
+    # compared on the scale of its terms, not relative to itself.
+    for key, k4, k3, km in (("r2_err", "sum_w2_r2sq", "sum_w2_r2", "r2_mean"),
+                            ("rg2_err", "sum_w2_rg2sq", "sum_w2_rg2", "rg2_mean")):
         a, b = s[key], ref[key]
         if math.isfinite(b):
-            assert abs(a - b) <= 1e-6 * abs(b) + 1e-300, (key, a, b)
+            S0, m = ref["sum_w"], ref[km]
+            scale = ref[k4] + 2.0 * abs(m) * ref[k3] + m * m * ref["sum_w2"]
+            assert abs((a * S0) ** 2 - (b * S0) ** 2) <= 1e-10 * scale + 1e-300, (key, a, b)
     if exact_ref is not None:
         assert s["exact_valid"] == 1
         assert s["sum_w_exact"] == exact_ref["sum_w"]
@@ -105,14 +115,16 @@ def test_lattice_bit_exact(N, M, seed, coord):
 
 @pytest.mark.parametrize("N,M,seed,coord", [
     # group kernels: byte words with 4 lanes per chain (N <= 128 in LDS; to
-    # 256 boxed, in the group's registers), 8 (N <= 512), 16 (N <= 1024) and
-    # 32 (N <= 2048; each lane's last slot at the top of each range), then
-    # wide words in LDS with 32 and 64 lanes per chain, up to the largest N
+    # 256 boxed, in the group's registers), 8 (N <= 512), 16 (N <= 1024), 32
+    # (N <= 2048) and 64 (N <= 4096; each lane's last slot at the top of each
+    # range), then wide words in LDS with 32 and 64 lanes per chain, up to
+    # the largest N
     (65, 3_001, 21, "i16"), (100, 1_500, 22, "i32"), (128, 2_000, 23, "i16"),
     (129, 801, 24, "i32"), (256, 2_000, 41, "i16"), (257, 700, 42, "i32"),
     (300, 333, 25, "i16"), (512, 300, 26, "i32"),
     (513, 200, 27, "i16"), (1_024, 100, 32, "i16"), (1_025, 80, 33, "i32"),
-    (2_048, 60, 28, "i32"), (2_049, 40, 29, "i16"),
+    (2_048, 60, 28, "i32"), (2_049, 40, 29, "i16"), (3_001, 16, 34, "i32"),
+    (4_096, 10, 35, "i16"), (4_097, 8, 36, "i32"),
     (5_000, 12, 30, "i32"), (16_384, 3, 31, "i16")])
 def test_lattice_long_chains_bit_exact(N, M, seed, coord):
     _lattice_case(N, M, seed, coord=coord, bins=256)
