@@ -139,7 +139,7 @@ def path_model(w) -> dict:
     geo, N, M = w["geometry"], w["N"], w["n_chains"]
     if geo == "lattice":
         reg = N <= 64 or w.get("exact_w", False)
-        grp = not reg and 128 < N <= 4096  # history in the group's VGPRs (built-in lane rule)
+        grp = not reg and N <= 4096  # history in the group's VGPRs (built-in lane rule)
         kernel = "grow_lattice_reg" if reg else ("grow_lattice_grp" if grp else "grow_lattice_lds")
         return dict(kernel=kernel, kernel_file="grow_lattice.hip" if reg else "grow_lattice_lds.hip",
                     ops=lattice_alg_ops_per_chain(N) * M, peak=VALU_PEAK_INT32_TOPS, int_path=True,

@@ -465,7 +465,7 @@ rsaw_status rsaw_fp64_check(const double *d_a, const double *d_b, double *d_sqrt
  * Three growth kernels spread one chain over a group of lanes: the
  * six-neighbour lattice for N > 64 (Sec. 3.3.2, Algorithm 1), hard spheres
  * up to N = 1536 (Sec. 3.3.3, Algorithm 2) and the 26-neighbour lattice for
- * N > 64.  Their mapping has two knobs: lanes per chain (4..64, a power of
+ * N > 64.  Their mapping has two knobs: lanes per chain (2..64, a power of
  * two; 64 / lanes chains share a wavefront, and the lanes split the scan of
  * the chain's earlier monomers) and threads per block (64 or 256, which
  * sets how many chains share a block's LDS and its tables).  A built-in
@@ -480,13 +480,13 @@ rsaw_status rsaw_fp64_check(const double *d_a, const double *d_b, double *d_sqrt
  * chain's scan.
  *
  * Legal mappings:
- *   RSAW_LATTICE_SC  lanes 4 (N <= 2048 only), 8, 16, 32, 64; up to
- *                    N = 2048 one 4-byte word per monomer (see
- *                    rsaw_set_byte_box), held in the chain's lanes'
- *                    registers for 128 < N <= 64 lanes (lanes <= 32), else
- *                    in LDS where the block can also hold one chain's
- *                    regrowth (all but 64 lanes in 64-thread blocks
- *                    beyond N = 768), else two words in LDS;
+ *   RSAW_LATTICE_SC  lanes 2 (N <= 128 only), 4 (N <= 2048 only), 8, 16,
+ *                    32, 64; one 4-byte word per monomer (see
+ *                    rsaw_set_byte_box) in the chain's lanes' registers
+ *                    where 128 < N <= 64 lanes, and with 2 lanes, else up
+ *                    to N = 2048 in LDS where the block can also hold one
+ *                    chain's regrowth (all but 64 lanes in 64-thread
+ *                    blocks beyond N = 768), else two words in LDS;
  *   RSAW_REAL_HS     lanes 8, 16, 32, 64 with lanes >= k; lanes 64 only
  *                    with 64 threads; N <= 1536;
  *   RSAW_LATTICE_26  lanes 4 (N <= 256 only), 8, 16, 32, 64; up to

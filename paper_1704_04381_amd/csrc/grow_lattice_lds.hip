@@ -2,7 +2,7 @@
 // (N > 64): the same growth rule as the register kernel (Sec. 3.3.2,
 // Algorithm 1; weight of Eq. 3) with G lanes per chain.  Two kernels share
 // the step: one keeps the chain history in the group's VGPRs (byte words,
-// 128 < N <= 64 G, so N <= 4096), the other in LDS (any N to 16384).
+// N <= 64 G, so N <= 4096), the other in LDS (any N to 16384).
 //
 // On the bipartite cubic lattice the monomers that can neighbour the tip at
 // step i are those of index i - 2, i - 4, ..., i.e. the first floor(i / 2)
@@ -445,7 +445,8 @@ __device__ void regrow_wide(const GrowArgs &a, uint64_t first_chain, bool mine, 
         regrow_passes<32, CT>(a, first_chain, n, slots, planes);
 }
 
-// Register-resident byte words (128 < N <= 64 G), the layout of
+// Register-resident byte words (N <= 64 G; beyond N = 128 only, except with
+// 2 lanes), the layout of
 // the file header.  Against the LDS kernel (same lanes, 10^5 to 10^6
 // chains, MI355X) the step loses its scan loads and their round trips, and
 // the block's LDS shrinks to the move table and the regrowth, so the kernel
@@ -458,7 +459,11 @@ __device__ void regrow_wide(const GrowArgs &a, uint64_t first_chain, bool mine, 
 // (3 10^4 chains; 10^4 chains, 21.3 -> 22.9 ms: 3.5 % of N = 4096
 // chains leave the box and are regrown).  Up to N = 128 the LDS kernel's
 // chains are short enough for 4 waves per SIMD, and it stays (N = 80:
-// 0.83 against 0.86 ms).
+// 0.83 against 0.86 ms).  With 2 lanes per chain, which only registers
+// allow (N <= 128), a wave's 32 chains share each step's pick and
+// bookkeeping, and that beats both: N = 65, 0.84 -> 0.43 ms; N = 80,
+// 0.82 -> 0.52 ms; N = 100, 1.03 -> 0.67 ms; N = 128, 1.36 -> 0.92 ms
+// (10^6 chains, bit-identical).
 // Unbounded, the compiler takes 186 VGPRs (2 waves per SIMD: 4.20 ms at
 // N = 256); at 4 waves it spills in the step loop.
 constexpr int kGrpSlots = 32; // slots per lane and plane
@@ -723,16 +728,16 @@ int lattice_lds_max_monomers() { return 16384; }
 
 // Shape of a lattice group kernel for N monomers, G lanes per chain and
 // `threads` per block (64 or 256) in one word format: byte words (in the
-// group's registers where 128 < N <= 64 G, format 2, else in LDS up to
-// N = 2048, format 0) or wide words (LDS, format 1).  hipErrorInvalidValue when the
+// group's registers where 128 < N <= 64 G, or G = 2 and N <= 128, format
+// 2, else in LDS up to N = 2048, format 0) or wide words (LDS, format 1).  hipErrorInvalidValue when the
 // block's LDS exceeds the CU's 160 KiB or, for boxed byte words, holds no
 // chain of the wide regrowth.
 static hipError_t lds_shape_fmt(int N, bool i16, int G, int threads, bool wide, GrowVariant *v)
 {
-    if (!wide && N > kByteExactN && N <= 2 * kGrpSlots * G) {
+    if (!wide && (N > kByteExactN || G == 2) && N <= 2 * kGrpSlots * G) {
         // registers: LDS for the move table and the regrowth of up to four
         // chains at a time (fewer where they would pass 40 KiB)
-        int room = 4;
+        int room = N > kByteExactN ? 4 : 0;
         while (room > 1 && (kRegrowListWords + room * regrow_stride(N)) * 4 > 40960) --room;
         int words = kRegrowListWords + room * regrow_stride(N);
         if (words < kLutSize) words = kLutSize;
@@ -769,14 +774,16 @@ static hipError_t lds_shape_fmt(int N, bool i16, int G, int threads, bool wide, 
 }
 
 // Shape for a mapping: byte words (boxed beyond N = 128) in the group's
-// registers for 128 < N <= 64 G, else in LDS up to N = 2048 where the block
-// can host the regrowth, else wide words (G >= 8).  Byte words need less
+// registers for 128 < N <= 64 G and with G = 2 (N <= 128 only), else in
+// LDS up to N = 2048 where the block can host the regrowth, else wide
+// words (G >= 8).  Byte words need less
 // LDS than wide ones, and their regrowth room does not grow back as N
 // shrinks, so a mapping legal at some N is legal at every smaller N of the
 // kernel.
 static hipError_t lds_shape(int N, bool i16, int G, int threads, GrowVariant *v)
 {
-    if (G != 4 && G != 8 && G != 16 && G != 32 && G != 64) return hipErrorInvalidValue;
+    if (G != 2 && G != 4 && G != 8 && G != 16 && G != 32 && G != 64) return hipErrorInvalidValue;
+    if (G == 2 && N > 2 * kGrpSlots * 2) return hipErrorInvalidValue;
     if (threads != 64 && threads != 256) return hipErrorInvalidValue;
     if ((N <= kByteBoxedMaxN || (N > kByteExactN && N <= 2 * kGrpSlots * G)) &&
         lds_shape_fmt(N, i16, G, threads, false, v) == hipSuccess)
@@ -786,10 +793,9 @@ static hipError_t lds_shape(int N, bool i16, int G, int threads, GrowVariant *v)
 }
 
 // Variant for 64 < N <= 16384.  Built-in rule (measured on MI355X, 10^4 to
-// 10^6 chains): byte words with 4 lanes per chain up to N = 256 (in LDS to
-// N = 128, in the group's registers beyond), 8 up to N = 512, 16 up to
-// 1024, 32 up to 2048 and 64 up to 4096 (registers: the fewest lanes whose
-// 32 slots hold a plane); wide words beyond, 32 lanes in 256-thread blocks
+// 10^6 chains): byte words in the group's registers with 2 lanes per chain
+// up to N = 128, 4 up to 256, 8 up to 512, 16 up to 1024, 32 up to 2048
+// and 64 up to 4096 (the fewest lanes whose 32 slots hold a plane); wide words beyond, 32 lanes in 256-thread blocks
 // while eight chains fit in a CU's LDS, else 64 lanes.
 // Four or more waves per block share the move table when the block fits in
 // half a CU's LDS.  A legal mapping of the tuning table replaces the rule.
@@ -800,7 +806,7 @@ hipError_t lattice_lds_variant(const GrowArgs &a, bool i16, GrowVariant *v)
     if (tuned_mapping(0 /* simple cubic lattice */, N, a.k_trials, &tl, &tt) &&
         lds_shape(N, i16, tl, tt, v) == hipSuccess)
         return hipSuccess;
-    const int G = N <= 256 ? 4 : (N <= 512 ? 8 : (N <= 1024 ? 16 : (N <= 2048 ? 32 : 64)));
+    const int G = N <= 128 ? 2 : N <= 256 ? 4 : (N <= 512 ? 8 : (N <= 1024 ? 16 : (N <= 2048 ? 32 : 64)));
     // wide words past N = 4096: eight chains of 32 lanes in one 256-thread
     // block per CU while they fit (N = 2200, before the registers took
     // N <= 4096: 37.8 against 49.2 ms for one-chain blocks of 64 lanes)
@@ -863,6 +869,7 @@ static hipError_t dispatch_lds(const GrowArgs &a, const GrowVariant &v, const Gr
                : launch_grp<G, int32_t>(a, v, tab, block0, n, blocks, shmem, s)
     if (v.p1 == 2) {
         switch (v.p0) {
+        case 2: RSAW_GRP(2);
         case 4: RSAW_GRP(4);
         case 8: RSAW_GRP(8);
         case 16: RSAW_GRP(16);

@@ -1236,7 +1236,7 @@ rsaw_status rsaw_autotune(const rsaw_config *base, const int32_t *n_edges, int32
         *ms = (double)t / reps;
         return RSAW_OK;
     };
-    static const int kLanes[] = {4, 8, 16, 32, 64};
+    static const int kLanes[] = {2, 4, 8, 16, 32, 64};
     static const int kThreads[] = {64, 256};
     for (int32_t b = 0; b < n_buckets && st == RSAW_OK; ++b) {
         rsaw_config c = *base;

@@ -18,7 +18,7 @@ import paper_1704_04381_amd as rs
 
 pytestmark = pytest.mark.gpu
 
-LANES = (4, 8, 16, 32, 64)
+LANES = (2, 4, 8, 16, 32, 64)
 THREADS = (64, 256)
 
 
@@ -157,7 +157,7 @@ def test_autotune_argument_errors():
     for edges, reps in (([64, 64], 1), ([0], 1), ([64], 0), ([64], 101)):
         with pytest.raises(rs.RsawError):
             rs.autotune("lattice", 6, edges, 100, reps=reps)
-    assert rs.mapping_query(rs.make_config("lattice", 100, 6, 100, 1))["lanes"] == 4  # nothing installed
+    assert rs.mapping_query(rs.make_config("lattice", 100, 6, 100, 1))["lanes"] == 2  # nothing installed
 
 
 def test_hard_sphere_rule_window_matches_the_oracle():

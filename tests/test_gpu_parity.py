@@ -114,11 +114,11 @@ def test_lattice_bit_exact(N, M, seed, coord):
 
 
 @pytest.mark.parametrize("N,M,seed,coord", [
-    # group kernels: byte words with 4 lanes per chain (N <= 128 in LDS; to
-    # 256 boxed, in the group's registers), 8 (N <= 512), 16 (N <= 1024), 32
-    # (N <= 2048) and 64 (N <= 4096; each lane's last slot at the top of each
-    # range), then wide words in LDS with 32 and 64 lanes per chain, up to
-    # the largest N
+    # group kernels: byte words in the group's registers with 2 lanes per
+    # chain (N <= 128), 4 (N <= 256; boxed beyond 128), 8 (N <= 512), 16
+    # (N <= 1024), 32 (N <= 2048) and 64 (N <= 4096; each lane's last slot at
+    # the top of each range), then wide words in LDS with 32 and 64 lanes
+    # per chain, up to the largest N
     (65, 3_001, 21, "i16"), (100, 1_500, 22, "i32"), (128, 2_000, 23, "i16"),
     (129, 801, 24, "i32"), (256, 2_000, 41, "i16"), (257, 700, 42, "i32"),
     (300, 333, 25, "i16"), (512, 300, 26, "i32"),

@@ -32,7 +32,7 @@ def test_builtin_rule():
     # group widths of the built-in rule
     assert [_q("lattice", n, 6)["lanes"] for n in (65, 128, 129, 256, 257, 512, 513, 1024, 2048, 2049, 3000,
                                                    4096, 4097)] == \
-        [4, 4, 4, 4, 8, 8, 16, 16, 32, 64, 64, 64, 64]
+        [2, 2, 4, 4, 8, 8, 16, 16, 32, 64, 64, 64, 64]
     assert [_q("lattice26", n, 26)["lanes"] for n in (65, 160, 256, 257, 400, 800, 1600)] == [4, 4, 4, 8, 16, 32, 64]
     assert _q("real", 64, 8)["lanes"] == 8 and _q("real", 64, 16)["lanes"] == 16
     assert _q("real", 300, 8)["lanes"] == 32  # 0.075 N = 22.5 -> 32
@@ -80,7 +80,9 @@ def test_hard_sphere_mapping_is_per_k():
 
 @pytest.mark.parametrize("args", [
     ("lattice", 6, 65, 2100, 4, 64),     # 4 lanes: byte words, N <= 2048
-    ("lattice", 6, 65, 100, 2, 64),      # not a group width
+    ("lattice", 6, 65, 129, 2, 64),      # 2 lanes hold N <= 128 only
+    ("real", 8, 65, 100, 2, 256),        # not a hard-sphere group width
+    ("lattice26", 26, 65, 100, 2, 256),  # not a 26-neighbour group width
     ("lattice", 6, 65, 100, 8, 128),     # threads must be 64 or 256
     ("lattice", 6, 10, 64, 8, 64),       # N <= 64: register kernel
     ("real", 16, 10, 100, 8, 256),       # fewer lanes than trials
@@ -102,7 +104,7 @@ def test_set_rejects_illegal_mappings(args):
 
 def test_legal_mapping_at_n_hi_is_legal_below():
     for geo, k in (("lattice", 6), ("real", 8), ("lattice26", 26)):
-        for lanes in (4, 8, 16, 32, 64):
+        for lanes in (2, 4, 8, 16, 32, 64):
             for threads in (64, 256):
                 try:
                     rs.mapping_set(geo, k, 65, 1000, lanes, threads)
