@@ -489,11 +489,11 @@ rsaw_status rsaw_fp64_check(const double *d_a, const double *d_b, double *d_sqrt
  *                    blocks beyond N = 768), else two words in LDS;
  *   RSAW_REAL_HS     lanes 8, 16, 32, 64 with lanes >= k; lanes 64 only
  *                    with 64 threads; N <= 1536;
- *   RSAW_LATTICE_26  lanes 4 (N <= 256 only), 8, 16, 32, 64; up to
- *                    N = 4096 one word per monomer, held in the chain's
- *                    lanes' registers for N <= 64 lanes, else in LDS where
- *                    the block can also hold one chain's regrowth, else
- *                    two words in LDS;
+ *   RSAW_LATTICE_26  lanes 2 (N <= 128 only), 4 (N <= 256 only), 8, 16,
+ *                    32, 64; up to N = 4096 one word per monomer, held in
+ *                    the chain's lanes' registers for N <= 64 lanes, else
+ *                    in LDS where the block can also hold one chain's
+ *                    regrowth, else two words in LDS;
  * threads 64 or 256; and the block's LDS (lds_bytes) at most 160 KiB.
  * Calls outside the group kernels' ranges (lattice N <= 64 or exact
  * weights, hard spheres N > 1536) never consult the table.

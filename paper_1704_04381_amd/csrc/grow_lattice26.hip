@@ -44,7 +44,7 @@ template <int G>
 __device__ __forceinline__ uint32_t z26_group_or(uint32_t v)
 {
     v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
-    v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
+    if constexpr (G >= 4) v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
     if constexpr (G >= 8) v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);
     if constexpr (G >= 16) v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false);
     if constexpr (G >= 32) {
@@ -546,8 +546,10 @@ __device__ __forceinline__ bool z26_grp_grow(const GrowArgs &a, const double *lo
     bool alive = false;
     bool left_box = false;
     int grown = 1;
+    // n_m counters as in the LDS kernel; with G = 2 (N <= 128) a lane's 13
+    // 8-bit fields take a second word for fields 8 and up
     constexpr uint32_t FW = G >= 8 ? 16u : 8u;
-    uint64_t n_mine = 0;
+    uint64_t n_mine = 0, n_mine2 = 0;
     bool rng_fail = false;
     Philox4 blk{0, 0, 0, 0};
     double res_lw = -__builtin_huge_val();
@@ -569,6 +571,7 @@ __device__ __forceinline__ bool z26_grp_grow(const GrowArgs &a, const double *lo
         if (pending) {
             ta = BYTE ? kZ26LaneOrigin : kP32Origin;
             n_mine = 0;
+            n_mine2 = 0;
         }
         pl[0] = (pending && t == 0) ? (BYTE ? kZ26LaneOrigin + kZ26Bias : kP32Origin) : pl[0];
         alive = pending;
@@ -641,7 +644,16 @@ __device__ __forceinline__ bool z26_grp_grow(const GrowArgs &a, const double *lo
             }
             ta = step_ok ? na : ta;
             const uint32_t mm1 = m - 1u;
-            n_mine += (step_ok && (mm1 & (G - 1)) == (uint32_t)t) ? 1ull << (FW * (mm1 / G)) : 0ull;
+            const bool counts = step_ok && (mm1 & (G - 1)) == (uint32_t)t;
+            if constexpr (G == 2) {
+                const uint32_t f = mm1 / G;
+                const bool upper = f >= 8u;
+                const uint64_t inc = 1ull << (FW * (upper ? f - 8u : f));
+                n_mine += (counts && !upper) ? inc : 0ull;
+                n_mine2 += (counts && upper) ? inc : 0ull;
+            } else {
+                n_mine += counts ? 1ull << (FW * (mm1 / G)) : 0ull;
+            }
             const bool mine = step_ok && t == (i & (G - 1));
             const uint32_t nw = BYTE ? na + kZ26Bias : na;
             const int slot = i / G;
@@ -658,9 +670,11 @@ __device__ __forceinline__ bool z26_grp_grow(const GrowArgs &a, const double *lo
         double lw = 0.0;
 #pragma unroll 1
         for (int mm = 1; mm <= 26; ++mm) {
-            const int f = (mm - 1) / G;
+            const int f0 = (mm - 1) / G;
+            const bool upper = G == 2 && f0 >= 8;
+            const int f = upper ? f0 - 8 : f0;
             const int per = 32 / (int)FW;
-            const uint32_t half = (uint32_t)(n_mine >> (32 * (f / per)));
+            const uint32_t half = (uint32_t)((upper ? n_mine2 : n_mine) >> (32 * (f / per)));
             const uint32_t v = (uint32_t)__shfl((int)half, gbase + ((mm - 1) & (G - 1)), 64);
             const uint32_t nm = (v >> (FW * (uint32_t)(f % per))) & ((1u << FW) - 1u);
             lw = lw + (double)nm * logm[mm];
@@ -1101,9 +1115,10 @@ static hipError_t z26_shape_fmt(int N, bool i16, int G, int threads, int fmt, Gr
 // group kernel.
 static hipError_t z26_shape(int N, bool i16, int G, int threads, GrowVariant *v)
 {
-    if (G != 4 && G != 8 && G != 16 && G != 32 && G != 64) return hipErrorInvalidValue;
+    if (G != 2 && G != 4 && G != 8 && G != 16 && G != 32 && G != 64) return hipErrorInvalidValue;
     if (threads != 64 && threads != 256) return hipErrorInvalidValue;
     if (G == 4 && N > 256) return hipErrorInvalidValue;
+    if (G == 2 && N > kZ26Slots * 2) return hipErrorInvalidValue; // registers only
     const int fmt = N <= kZ26ByteMaxN ? kZ26Byte : (N <= kZ26PackedMaxN ? kZ26Packed : kZ26Wide);
     if (fmt != kZ26Wide && N <= kZ26Slots * G) {
         // registers: LDS for the regrowth of up to four chains at a time
@@ -1126,10 +1141,13 @@ static hipError_t z26_shape(int N, bool i16, int G, int threads, GrowVariant *v)
 }
 
 // One lane per chain up to N = 64 (and for exact weights, N <= 14); above,
-// G lanes per chain.  Built-in rule: G grows with N (the widths measured
-// best when the words sat in LDS): 4 up to N = 256 (whose 8-bit n_m fields
-// need N <= 256), 8 up to 384, 16 up to 768, 32 up to 1536, 64 beyond, so
-// every chain up to N = 4096 keeps its words in registers; 256-thread
+// G lanes per chain.  Built-in rule: G grows with N: 2 up to N = 128 (only
+// registers allow it; a wave's 32 chains share each step's pick: N = 65,
+// 1.30 -> 0.85 ms; N = 100, 2.10 -> 1.54 ms; N = 128, 2.83 -> 2.20 ms
+// against 4 lanes, 10^6 chains), then the widths measured best when the
+// words sat in LDS: 4 up to N = 256 (whose 8-bit n_m fields need N <= 256),
+// 8 up to 384, 16 up to 768, 32 up to 1536, 64 beyond, so every chain up
+// to N = 4096 keeps its words in registers; 256-thread
 // blocks when the block's LDS fits in half a CU's, else one wave.  A legal mapping of the tuning table replaces
 // the rule for the group kernel.
 hipError_t lattice26_variant(const GrowArgs &a, bool exact, bool i16, GrowVariant *v)
@@ -1152,7 +1170,7 @@ hipError_t lattice26_variant(const GrowArgs &a, bool exact, bool i16, GrowVarian
     if (tuned_mapping(2 /* 26-neighbour lattice */, N, a.k_trials, &tl, &tt) &&
         z26_shape(N, i16, tl, tt, v) == hipSuccess)
         return hipSuccess;
-    const int G = N <= 256 ? 4 : (N <= 384 ? 8 : (N <= 768 ? 16 : (N <= 1536 ? 32 : 64)));
+    const int G = N <= 128 ? 2 : (N <= 256 ? 4 : (N <= 384 ? 8 : (N <= 768 ? 16 : (N <= 1536 ? 32 : 64))));
     GrowVariant half_cu;
     if (z26_shape(N, i16, G, 256, &half_cu) == hipSuccess && half_cu.shmem <= 81920) {
         *v = half_cu;
@@ -1223,11 +1241,15 @@ template <int G, typename CT>
 static hipError_t launch26_ct(const GrowArgs &a, const GrowVariant &v, const GrowEntry *tab,
                               const uint64_t *block0, int n, uint64_t blocks, size_t shmem, hipStream_t s)
 {
-    if (v.p1 == kZ26Byte + 2) return launch26_grp<G, CT, kZ26Byte>(a, v, tab, block0, n, blocks, shmem, s);
-    if (v.p1 == kZ26Packed + 2) return launch26_grp<G, CT, kZ26Packed>(a, v, tab, block0, n, blocks, shmem, s);
-    if (v.p1 == kZ26Byte) return launch26<G, CT, kZ26Byte>(a, v, tab, block0, n, blocks, shmem, s);
-    if (v.p1 == kZ26Packed) return launch26<G, CT, kZ26Packed>(a, v, tab, block0, n, blocks, shmem, s);
-    return launch26<G, CT, kZ26Wide>(a, v, tab, block0, n, blocks, shmem, s);
+    if constexpr (G == 2) { // byte words in registers only (N <= 128)
+        return launch26_grp<2, CT, kZ26Byte>(a, v, tab, block0, n, blocks, shmem, s);
+    } else {
+        if (v.p1 == kZ26Byte + 2) return launch26_grp<G, CT, kZ26Byte>(a, v, tab, block0, n, blocks, shmem, s);
+        if (v.p1 == kZ26Packed + 2) return launch26_grp<G, CT, kZ26Packed>(a, v, tab, block0, n, blocks, shmem, s);
+        if (v.p1 == kZ26Byte) return launch26<G, CT, kZ26Byte>(a, v, tab, block0, n, blocks, shmem, s);
+        if (v.p1 == kZ26Packed) return launch26<G, CT, kZ26Packed>(a, v, tab, block0, n, blocks, shmem, s);
+        return launch26<G, CT, kZ26Wide>(a, v, tab, block0, n, blocks, shmem, s);
+    }
 }
 
 template <int G>
@@ -1250,6 +1272,7 @@ static hipError_t dispatch26(const GrowArgs &a, const GrowVariant &v, const Grow
                    : launch26_lane<false, int32_t>(a, v, tab, block0, n, blocks, shmem, s);
     }
     switch (v.p0) {
+    case 2: return launch26_g<2>(a, v, tab, block0, n, blocks, shmem, s);
     case 4: return launch26_g<4>(a, v, tab, block0, n, blocks, shmem, s);
     case 8: return launch26_g<8>(a, v, tab, block0, n, blocks, shmem, s);
     case 16: return launch26_g<16>(a, v, tab, block0, n, blocks, shmem, s);

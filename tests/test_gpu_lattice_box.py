@@ -103,6 +103,8 @@ def test_regrown_chains_in_a_batch():
 # knob) is regrown in two-word format by its block.
 @pytest.mark.parametrize("N,M,seed,coord,edge,mapping,offset,restart", [
     (200, 800, 91, "i16", 20, None, 0, False),
+    # 2 lanes per chain (N <= 128, registers only), with restarts
+    (100, 600, 112, "i16", 20, None, 0, True),
     # 4 lanes per chain (8-bit n_m fields), every chain regrown from step 1
     (129, 600, 92, "i32", 1, None, 0, False),
     (300, 300, 93, "i16", 25, None, 0, True),

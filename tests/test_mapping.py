@@ -33,7 +33,8 @@ def test_builtin_rule():
     assert [_q("lattice", n, 6)["lanes"] for n in (65, 128, 129, 256, 257, 512, 513, 1024, 2048, 2049, 3000,
                                                    4096, 4097)] == \
         [2, 2, 4, 4, 8, 8, 16, 16, 32, 64, 64, 64, 64]
-    assert [_q("lattice26", n, 26)["lanes"] for n in (65, 160, 256, 257, 400, 800, 1600)] == [4, 4, 4, 8, 16, 32, 64]
+    assert [_q("lattice26", n, 26)["lanes"] for n in (65, 128, 129, 256, 257, 400, 800, 1600)] == \
+        [2, 2, 4, 4, 8, 16, 32, 64]
     assert _q("real", 64, 8)["lanes"] == 8 and _q("real", 64, 16)["lanes"] == 16
     assert _q("real", 300, 8)["lanes"] == 32  # 0.075 N = 22.5 -> 32
     # k = 8: 16 lanes while a 256-thread block leaves 3 blocks per CU, then
@@ -63,7 +64,7 @@ def test_set_overrides_inside_its_range_only():
     assert (m["lanes"], m["threads"]) == (32, 64)
     assert _q("lattice", 129, 6)["lanes"] == 4       # outside the range
     assert _q("lattice", 64, 6)["lanes"] == 1        # register kernel: never tuned
-    assert _q("lattice26", 100, 26)["lanes"] == 4    # other geometry
+    assert _q("lattice26", 100, 26)["lanes"] == 2    # other geometry
     # a later entry wins where ranges overlap
     rs.mapping_set("lattice", 6, 90, 110, 16, 256)
     assert (_q("lattice", 100, 6)["lanes"], _q("lattice", 100, 6)["threads"]) == (16, 256)
@@ -82,7 +83,7 @@ def test_hard_sphere_mapping_is_per_k():
     ("lattice", 6, 65, 2100, 4, 64),     # 4 lanes: byte words, N <= 2048
     ("lattice", 6, 65, 129, 2, 64),      # 2 lanes hold N <= 128 only
     ("real", 8, 65, 100, 2, 256),        # not a hard-sphere group width
-    ("lattice26", 26, 65, 100, 2, 256),  # not a 26-neighbour group width
+    ("lattice26", 26, 65, 129, 2, 256),  # 2 lanes hold N <= 128 only
     ("lattice", 6, 65, 100, 8, 128),     # threads must be 64 or 256
     ("lattice", 6, 10, 64, 8, 64),       # N <= 64: register kernel
     ("real", 16, 10, 100, 8, 256),       # fewer lanes than trials
