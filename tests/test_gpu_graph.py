@@ -80,11 +80,17 @@ def test_captured_calls_replay_bit_identically():
     del g
 
 
+# one ensemble per growth-kernel family: lattice in registers (one lane,
+# and a group), lattice with its words in LDS (N > 4096), hard spheres with
+# LDS and HBM planes, 26-neighbour lattice in registers and in LDS, and an
+# empty ensemble
 BATCH = [dict(geometry="lattice", N=16, k=6, n_chains=30_000, seed=11, coord="i32", exact_w=True, hist_bins=8),
          dict(geometry="lattice", N=100, k=6, n_chains=20_000, seed=12, coord="i16", hist_bins=64),
+         dict(geometry="lattice", N=5_000, k=6, n_chains=12, seed=17, coord="i32"),
          dict(geometry="real", N=64, k=8, n_chains=10_000, seed=13, hist_bins=16),
          dict(geometry="real", N=1800, k=8, n_chains=40, seed=14),
          dict(geometry="lattice26", N=200, k=26, n_chains=5_000, seed=15, coord="i32"),
+         dict(geometry="lattice26", N=5_000, k=26, n_chains=6, seed=18, coord="i16"),
          dict(geometry="lattice", N=33, k=6, n_chains=0, seed=16, coord="i32", hist_bins=4)]
 
 
