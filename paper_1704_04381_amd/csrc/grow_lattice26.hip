@@ -513,10 +513,11 @@ __device__ __forceinline__ bool z26_grow(const GrowArgs &a, const double *logm, 
 // Register-resident one-word formats (byte or packed words, N <= 64 G):
 // entry j (monomer j) of the chain sits in lane j mod G of its group, slot
 // j / G of a 64-slot array.  A step tests the slots that can hold monomers
-// 0 .. i - 2, four at a time behind one wave-uniform count test (slots past
-// them hold the tip, code 13, masked, or the sentinel), and appends the new
-// word with one indexed register read and write (uniform slot; the lane that
-// holds entry i takes it).  Against the same mapping with the words in LDS
+// 0 .. i - 2, four at a time behind one wave-uniform count test, two in a
+// last group with one or two slots left (4-6 % faster than whole groups;
+// slots past them hold the tip, code 13, masked, or the sentinel), and
+// appends the new word with one indexed register read and write (uniform
+// slot; the lane that holds entry i takes it).  Against the same mapping with the words in LDS
 // (MI355X, kernel time, bit-identical): N = 100, 2.57 -> 2.07 ms; N = 256,
 // 15.2 -> 8.27 ms; N = 640, 35.8 -> 25.8 ms; N = 2048, 49.4 -> 35.9 ms;
 // N = 4000, 81.0 -> 51.0 ms.  The step loses its scan loads and their
@@ -582,26 +583,22 @@ __device__ __forceinline__ bool z26_grp_grow(const GrowArgs &a, const double *lo
             const int ns = (i - 1 + G - 1) / G; // slots that can hold monomers 0 .. i - 2
             uint32_t occ = 0, occ2 = 0;
             const uint32_t tp = BYTE ? ta + 0x7F7F7Fu : ta - kP32One;
-            const auto test4 = [&](uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3) {
+            const auto test2 = [&](uint32_t w0, uint32_t w1) {
                 if constexpr (BYTE) {
                     occ |= z26_bits8(w0, tp);
                     occ2 |= z26_bits8(w1, tp);
-                    occ |= z26_bits8(w2, tp);
-                    occ2 |= z26_bits8(w3, tp);
                 } else {
                     occ |= z26_bits32(w0, tp);
                     occ2 |= z26_bits32(w1, tp);
-                    occ |= z26_bits32(w2, tp);
-                    occ2 |= z26_bits32(w3, tp);
                 }
             };
+            const auto word = [&](int sl) { return sl < SL / 2 ? pl[sl] : ph[sl - SL / 2]; };
 #pragma unroll
             for (int q = 0; q < SL / 4; ++q) {
                 if (4 * q >= ns) break;
-                if (q < SL / 8)
-                    test4(pl[4 * q], pl[4 * q + 1], pl[4 * q + 2], pl[4 * q + 3]);
-                else
-                    test4(ph[4 * q - SL / 2], ph[4 * q + 1 - SL / 2], ph[4 * q + 2 - SL / 2], ph[4 * q + 3 - SL / 2]);
+                test2(word(4 * q), word(4 * q + 1));
+                if (4 * q + 2 >= ns) break; // a tail of one or two slots
+                test2(word(4 * q + 2), word(4 * q + 3));
             }
             occ = z26_group_or<G>(occ | occ2);
             const uint32_t freem = ~occ & kZ26Codes;
