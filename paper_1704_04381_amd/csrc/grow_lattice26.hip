@@ -25,10 +25,10 @@
 // ten operations per pair.  The G partial masks are OR-reduced across the
 // group; every lane then picks the same r-th free code (Lemire on the same
 // 16-bit words as the six-neighbour lattice; the code by a binary search
-// over the free mask, the move computed from the code, so that the step
-// makes no LDS table lookup), and lane (m - 1) mod G counts the steps with
-// m free candidates for log W.  Short chains (N <= 64) use the
-// one-lane-per-chain kernel further down.
+// over the free mask in this LDS kernel, from the byte-rank table in the
+// register kernel further down; the move computed from the code), and
+// lane (m - 1) mod G counts the steps with m free candidates for log W.
+// Short chains (N <= 64) use the one-lane-per-chain kernel further down.
 #include "rsaw_device.hpp"
 
 namespace rsaw {
@@ -517,17 +517,22 @@ __device__ __forceinline__ bool z26_grow(const GrowArgs &a, const double *logm, 
 // last group with one or two slots left (4-6 % faster than whole groups;
 // slots past them hold the tip, code 13, masked, or the sentinel), and
 // appends the new word with one indexed register read and write (uniform
-// slot; the lane that holds entry i takes it).  Against the same mapping with the words in LDS
-// (MI355X, kernel time, bit-identical): N = 100, 2.57 -> 2.07 ms; N = 256,
-// 15.2 -> 8.27 ms; N = 640, 35.8 -> 25.8 ms; N = 2048, 49.4 -> 35.9 ms;
-// N = 4000, 81.0 -> 51.0 ms.  The step loses its scan loads and their
+// slot; the lane that holds entry i takes it).  The r-th free code comes
+// from the one-lane kernel's byte-rank table in LDS (2 KB), about 20
+// operations where the binary search takes about 45 (3-4 % faster at
+// N = 256 and 2048, the same with 2 lanes).  Against the same mapping with
+// the words in LDS (MI355X, kernel time, bit-identical, before the last
+// two changes): N = 100, 2.57 -> 2.07 ms; N = 256, 15.2 -> 8.27 ms;
+// N = 640, 35.8 -> 25.8 ms; N = 2048, 49.4 -> 35.9 ms; N = 4000, 81.0 ->
+// 51.0 ms.  The step loses its scan loads and their
 // round trips, and the kernel runs at 3 waves per SIMD (168 VGPRs; the
 // compiler spills a few values outside the step loop) where the LDS kernel
 // ran at 2; unbounded it takes 192 VGPRs and runs 10-40 % slower.
 constexpr int kZ26Slots = 64;
 
 template <int G, typename CT, int FMT>
-__device__ __forceinline__ bool z26_grp_grow(const GrowArgs &a, const double *logm, uint64_t c, bool valid, int box)
+__device__ __forceinline__ bool z26_grp_grow(const GrowArgs &a, const double *logm, const uint8_t *sel, uint64_t c,
+                                             bool valid, int box)
 {
     constexpr int SL = kZ26Slots;
     constexpr bool BYTE = FMT == kZ26Byte;
@@ -615,7 +620,7 @@ __device__ __forceinline__ bool z26_grp_grow(const GrowArgs &a, const double *lo
                     r = 0;
                 }
             }
-            const uint32_t code = m ? z26_select_bits(freem, r) : 13u;
+            const uint32_t code = m ? z26_select(freem, r, sel) : 13u;
 
             bool step_ok = alive && m != 0;
             grown = (alive && m == 0) ? i : grown;
@@ -852,13 +857,15 @@ __device__ __forceinline__ void grow_lattice26_grp_body(const GrowArgs &a, uint6
 {
     const int cpb = blockDim.x / G;
     __shared__ double logm[27];
+    __shared__ uint8_t sel[2048];
     for (int q = threadIdx.x; q < 27; q += blockDim.x) logm[q] = a.logm[q];
+    z26_fill_select_table(sel);
     __syncthreads();
     const int t = threadIdx.x & (G - 1);
     const int chb = threadIdx.x / G;
     const uint64_t c = bid * cpb + chb;
     const int box = FMT == kZ26Byte ? z26_box(a, kZ26ByteEdge) : z26_box(a, kZ26PackedEdge);
-    const bool left = z26_grp_grow<G, CT, FMT>(a, logm, c, c < a.n_chains, box);
+    const bool left = z26_grp_grow<G, CT, FMT>(a, logm, sel, c, c < a.n_chains, box);
     z26_regrow_wide<CT>(a, logm, bid * cpb, left && t == 0, (uint32_t)chb, words);
 }
 
