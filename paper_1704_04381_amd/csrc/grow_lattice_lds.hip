@@ -447,27 +447,25 @@ __device__ void regrow_wide(const GrowArgs &a, uint64_t first_chain, bool mine, 
         regrow_passes<32, CT>(a, first_chain, n, slots, planes);
 }
 
-// Register-resident byte words (N <= 64 G; beyond N = 128 only, except with
-// 2 lanes), the layout of
-// the file header.  Against the LDS kernel (same lanes, 10^5 to 10^6
-// chains, MI355X) the step loses its scan loads and their round trips, and
-// the block's LDS shrinks to the move table and the regrowth, so the kernel
-// runs at 3 waves per SIMD (168 VGPRs) where the LDS kernel ran at 2 to 3:
-// N = 160, 2.09 -> 1.86 ms; N = 256, 4.95 -> 3.49 ms; N = 384, 13.5 ->
-// 9.2 ms; N = 512, 19.9 -> 13.7 ms; N = 2048, 35.0 -> 26.1 ms,
-// bit-identical.  With 64 lanes (one chain per wave, which leaves the step
-// loop once its chain has ended) against wide words in LDS: N = 2049,
-// 32.5 -> 20.4 ms; N = 3000, 43.1 -> 23.5 ms; N = 4096, 57.9 -> 45.5 ms
-// (3 10^4 chains; 10^4 chains, 21.3 -> 22.9 ms: 3.5 % of N = 4096
-// chains leave the box and are regrown).  Up to N = 128 the LDS kernel's
-// chains are short enough for 4 waves per SIMD, and it stays (N = 80:
-// 0.83 against 0.86 ms).  With 2 lanes per chain, which only registers
-// allow (N <= 128), a wave's 32 chains share each step's pick and
-// bookkeeping, and that beats both: N = 65, 0.84 -> 0.43 ms; N = 80,
-// 0.82 -> 0.52 ms; N = 100, 1.03 -> 0.67 ms; N = 128, 1.36 -> 0.92 ms
-// (10^6 chains, bit-identical).
-// Unbounded, the compiler takes 186 VGPRs (2 waves per SIMD: 4.20 ms at
-// N = 256); at 4 waves it spills in the step loop.
+// Register-resident byte words, the layout of the file header: N <= 64 G,
+// with 2 lanes up to N = 128 and 4 to 64 lanes beyond.  Against the LDS
+// kernel (same lanes, 10^5 to 10^6 chains, MI355X, bit-identical) the step
+// loses its scan loads and their round trips, and the block's LDS shrinks
+// to the move table and the regrowth, so the kernel runs at 3 waves per
+// SIMD (168 VGPRs) where the LDS kernel ran at 2 to 3: N = 160, 2.09 ->
+// 1.86 ms; N = 256, 4.95 -> 3.49 ms; N = 384, 13.5 -> 9.2 ms; N = 512,
+// 19.9 -> 13.7 ms; N = 2048, 35.0 -> 26.1 ms.  With 64 lanes (one chain per
+// wave, which leaves the step loop once its chain has ended) against wide
+// words in LDS: N = 2049, 32.5 -> 20.4 ms; N = 3000, 43.1 -> 23.5 ms;
+// N = 4096, 57.9 -> 45.5 ms (3 10^4 chains; 10^4 chains, 21.3 -> 22.9 ms:
+// 3.5 % of N = 4096 chains leave the box and are regrown).  Up to N = 128
+// the LDS kernel's chains are short enough for 4 waves per SIMD, and 4
+// lanes in registers only tie (N = 80: 0.86 against 0.83 ms); but 2 lanes
+// per chain, which only registers allow, let a wave's 32 chains share each
+// step's pick and bookkeeping: N = 65, 0.84 -> 0.43 ms; N = 80, 0.82 ->
+// 0.52 ms; N = 100, 1.03 -> 0.67 ms; N = 128, 1.36 -> 0.92 ms.  Unbounded,
+// the compiler takes 186 VGPRs (2 waves per SIMD: 4.20 ms at N = 256); at
+// 4 waves it spills in the step loop.
 constexpr int kGrpSlots = 32; // slots per lane and plane
 
 template <int G, typename CT>
