@@ -1145,14 +1145,15 @@ static hipError_t z26_shape(int N, bool i16, int G, int threads, GrowVariant *v)
 }
 
 // One lane per chain up to N = 64 (and for exact weights, N <= 14); above,
-// G lanes per chain.  Built-in rule: G grows with N: 2 up to N = 128 (only
-// registers allow it; a wave's 32 chains share each step's pick: N = 65,
-// 1.30 -> 0.85 ms; N = 100, 2.10 -> 1.54 ms; N = 128, 2.83 -> 2.20 ms
-// against 4 lanes, 10^6 chains), then the widths measured best when the
-// words sat in LDS: 4 up to N = 256 (whose 8-bit n_m fields need N <= 256),
-// 8 up to 384, 16 up to 768, 32 up to 1536, 64 beyond, so every chain up
-// to N = 4096 keeps its words in registers; 256-thread
-// blocks when the block's LDS fits in half a CU's, else one wave.  A legal mapping of the tuning table replaces
+// G lanes per chain, the fewest whose 64 register slots hold the chain:
+// 2 up to N = 128, 4 up to 256, 8 up to 512, 16 up to 1024, 32 up to 2048
+// and 64 beyond (wide words in LDS past N = 4096).  Against the widths
+// measured best when the words sat in LDS (10^5 to 10^6 chains): N = 500,
+// 18.5 -> 13.9 ms (8 lanes, not 16); N = 1000, 15.4 -> 11.9 ms (16, not
+// 32); N = 2000, 31.2 -> 24.1 ms (32, not 64); with 2 lanes a wave's 32
+// chains share each step's pick (N = 65, 1.30 -> 0.85 ms; N = 100, 2.10 ->
+// 1.54 ms against 4 lanes).  256-thread blocks when the block's LDS fits in
+// half a CU's, else one wave.  A legal mapping of the tuning table replaces
 // the rule for the group kernel.
 hipError_t lattice26_variant(const GrowArgs &a, bool exact, bool i16, GrowVariant *v)
 {
@@ -1174,7 +1175,7 @@ hipError_t lattice26_variant(const GrowArgs &a, bool exact, bool i16, GrowVarian
     if (tuned_mapping(2 /* 26-neighbour lattice */, N, a.k_trials, &tl, &tt) &&
         z26_shape(N, i16, tl, tt, v) == hipSuccess)
         return hipSuccess;
-    const int G = N <= 128 ? 2 : (N <= 256 ? 4 : (N <= 384 ? 8 : (N <= 768 ? 16 : (N <= 1536 ? 32 : 64))));
+    const int G = N <= 128 ? 2 : (N <= 256 ? 4 : (N <= 512 ? 8 : (N <= 1024 ? 16 : (N <= 2048 ? 32 : 64))));
     GrowVariant half_cu;
     if (z26_shape(N, i16, G, 256, &half_cu) == hipSuccess && half_cu.shmem <= 81920) {
         *v = half_cu;

@@ -33,8 +33,9 @@ def test_builtin_rule():
     assert [_q("lattice", n, 6)["lanes"] for n in (65, 128, 129, 256, 257, 512, 513, 1024, 2048, 2049, 3000,
                                                    4096, 4097)] == \
         [2, 2, 4, 4, 8, 8, 16, 16, 32, 64, 64, 64, 64]
-    assert [_q("lattice26", n, 26)["lanes"] for n in (65, 128, 129, 256, 257, 400, 800, 1600)] == \
-        [2, 2, 4, 4, 8, 16, 32, 64]
+    assert [_q("lattice26", n, 26)["lanes"] for n in (65, 128, 129, 256, 257, 512, 513, 1024, 1025, 2048, 2049,
+                                                     4096, 4097)] == \
+        [2, 2, 4, 4, 8, 8, 16, 16, 32, 32, 64, 64, 64]
     assert _q("real", 64, 8)["lanes"] == 8 and _q("real", 64, 16)["lanes"] == 16
     assert _q("real", 300, 8)["lanes"] == 32  # 0.075 N = 22.5 -> 32
     # k = 8: 16 lanes while a 256-thread block leaves 3 blocks per CU, then
